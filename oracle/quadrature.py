@@ -1,0 +1,211 @@
+"""Quadrature rules for the RLBM (oracle; test infrastructure only).
+
+A rule is the set of discrete momenta p_i = (p_i^0, p_i^1..p_i^d), weights w_i
+and displacements delta_i (lattice sites travelled in one time step), see
+Sec. 5.3, Eqs. (discrete-momentum-vectors), (ur-discrete-momentum-vectors),
+and Sec. 6.1, Eq. (v0dt=dx).  The weights satisfy the orthonormality
+conditions of Eq. (mj-orthogonal-conditions) for polynomials up to the
+expansion order N, i.e. the rule integrates every polynomial of degree <= 2N
+exactly against the weight omega(p^0) ~ exp(-p^0) with measure d^dp/p^0
+(normalised so that sum_i w_i = 1, Eq. numerical-normalization-cond).
+
+Population order (shared interface with the library, stated in its header):
+shell-major, i = j * n_dirs + k, with the direction list below in which
+antipodal directions are adjacent (k, k+1 for even k).  Zero-weight
+populations of the printed ultra-relativistic rule are dropped.
+
+Rules:
+* ``ur_onlattice_2d``: the printed (2+1)-d massless rule of order 2
+  (Sec. 5.3, worked example, and App. H.2 "Order 2"), stencil
+  (+-3,+-4)_FS U (+-5,0)_FS, three energy shells.  Displacements are the
+  integer stencil vectors: speed c = 1 means |n_i| = 5 sites per step
+  (v0 = 1/5).  Reading of the printed weight list: the main-text values
+  w_{1j} = (0, 0, 1.7536e-3) belong to the (+-5,0) group and
+  w_{2j} = (8.889e-2, 3.481e-2, 4.219e-4) to the (+-3,+-4) group, the only
+  assignment with sum_i w_i = 1.
+* ``product_2d`` / ``product_3d``: off-lattice product rules.  The paper names
+  off-lattice schemes but does not build them (Sec. 5.3, last paragraphs;
+  Sec. 7.3 closing remark); this is the reading used here.  In d = 2,
+  d^2p/p^0 = dp^0 dphi, so with x = p^0 - m the radial weight is e^{-x}:
+  Gauss-Laguerre nodes x_j (N+1 of them, exact to degree 2N+1) times eight
+  equally weighted directions (exact for angular degree <= 7).  In d = 3,
+  d^3p/p^0 = |p| dp^0 dOmega, radial weight sqrt(x^2 + 2 m x) e^{-x} (Gauss
+  rule from its moments) times 26 directions (+-1,0,0)_FS, (+-1,+-1,0)_FS,
+  (+-1,+-1,+-1)_FS with group weights fixed by exactness at degrees 0, 4, 6.
+  Displacements: delta_i = v_i n_i / |n_i| with v_i = |p_i| / p_i^0 and
+  c dt = dx (one lattice site per step at the speed of light).
+"""
+from __future__ import annotations
+
+import itertools
+import math
+from dataclasses import dataclass
+
+import mpmath
+import numpy as np
+
+from . import mj
+
+# Printed (2+1)-d ultra-relativistic order-2 rule (Sec. 5.3 worked example and App. H.2).
+UR2D_SHELLS = (0.4157745567834790, 2.2942803602790417, 6.2899450829374791)
+UR2D_W_34 = (0.0888866262411466, 0.0348147166961551, 0.0004218743543938)   # (+-3,+-4)_FS group
+UR2D_W_50 = (0.0, 0.0, 0.0017535654166088)                                  # (+-5, 0)_FS group
+
+DIRS_UR2D = [(3, 4), (-3, -4), (-3, 4), (3, -4), (4, 3), (-4, -3), (-4, 3), (4, -3),
+             (5, 0), (-5, 0), (0, 5), (0, -5)]
+DIRS_2D = [(1, 0), (-1, 0), (0, 1), (0, -1), (1, 1), (-1, -1), (-1, 1), (1, -1)]
+DIRS_3D = [(1, 0, 0), (-1, 0, 0), (0, 1, 0), (0, -1, 0), (0, 0, 1), (0, 0, -1),
+           (1, 1, 0), (-1, -1, 0), (1, -1, 0), (-1, 1, 0),
+           (1, 0, 1), (-1, 0, -1), (1, 0, -1), (-1, 0, 1),
+           (0, 1, 1), (0, -1, -1), (0, 1, -1), (0, -1, 1),
+           (1, 1, 1), (-1, -1, -1), (1, 1, -1), (-1, -1, 1),
+           (1, -1, 1), (-1, 1, -1), (-1, 1, 1), (1, -1, -1)]
+
+
+@dataclass
+class Quadrature:
+    d: int
+    m: float            # reduced mass m~ (T0 = 1)
+    order: int          # expansion order N the rule supports
+    p: np.ndarray       # (Q, d+1) momenta, energy first
+    w: np.ndarray       # (Q,) weights
+    disp: np.ndarray    # (Q, d) displacement per step, in lattice sites
+    on_lattice: bool
+
+    @property
+    def Q(self) -> int:
+        return self.w.shape[0]
+
+
+def ur_onlattice_2d() -> Quadrature:
+    """Printed massless (2+1)-d rule of order 2 (Sec. 5.3 and App. H.2), 28 non-zero populations."""
+    p, w, disp = [], [], []
+    for j, p0 in enumerate(UR2D_SHELLS):
+        for (nx, ny) in DIRS_UR2D:
+            wj = UR2D_W_50[j] if nx * ny == 0 else UR2D_W_34[j]
+            if wj == 0.0:
+                continue
+            norm = math.hypot(nx, ny)          # = 5 for every vector of the stencil
+            p.append((p0, p0 * nx / norm, p0 * ny / norm))
+            w.append(wj)
+            disp.append((float(nx), float(ny)))
+    return Quadrature(2, 0.0, 2, np.array(p), np.array(w), np.array(disp), True)
+
+
+def product_2d(m: float, order: int) -> Quadrature:
+    """Off-lattice (2+1)-d product rule: Gauss-Laguerre in x = p^0 - m times 8 directions."""
+    x, W = np.polynomial.laguerre.laggauss(order + 1)
+    p, w, disp = [], [], []
+    for j in range(order + 1):
+        p0 = m + x[j]
+        pm = math.sqrt(x[j] * x[j] + 2.0 * m * x[j])
+        v = pm / p0
+        for (nx, ny) in DIRS_2D:
+            norm = math.hypot(nx, ny)
+            ux, uy = nx / norm, ny / norm
+            p.append((p0, pm * ux, pm * uy))
+            w.append(W[j] / len(DIRS_2D))
+            disp.append((v * ux, v * uy))
+    return Quadrature(2, float(m), order, np.array(p), np.array(w), np.array(disp), False)
+
+
+def sphere_average(a: int, b: int, c: int) -> float:
+    """Mean of x^a y^b z^c over the unit sphere: (a-1)!!(b-1)!!(c-1)!!/(a+b+c+1)!! for even a, b, c."""
+    if a % 2 or b % 2 or c % 2:
+        return 0.0
+
+    def dfact(k):
+        return 1 if k <= 0 else k * dfact(k - 2)
+    return dfact(a - 1) * dfact(b - 1) * dfact(c - 1) / dfact(a + b + c + 1)
+
+
+def octahedral_group_weights() -> np.ndarray:
+    """Per-direction weights of the axis / edge / corner groups of DIRS_3D.
+
+    Chosen so that the 26-point rule reproduces the sphere average of every
+    monomial of degree <= 7 (odd ones vanish by symmetry); solved as a
+    consistent least-squares system over all even monomials up to degree 6.
+    """
+    groups = [DIRS_3D[0:6], DIRS_3D[6:18], DIRS_3D[18:26]]
+    rows, rhs = [], []
+    for deg in (0, 2, 4, 6):
+        for (a, b, c) in itertools.product(range(deg + 1), repeat=3):
+            if a + b + c != deg:
+                continue
+            row = []
+            for grp in groups:
+                s = 0.0
+                for n in grp:
+                    u = np.array(n, dtype=float) / np.linalg.norm(n)
+                    s += u[0] ** a * u[1] ** b * u[2] ** c
+                row.append(s)
+            rows.append(row)
+            rhs.append(sphere_average(a, b, c))
+    sol, *_ = np.linalg.lstsq(np.array(rows), np.array(rhs), rcond=None)
+    return sol
+
+
+def radial_gauss_3d(m: float, npts: int, dps: int = 50):
+    """Gauss rule for int_0^inf g(x) sqrt(x^2 + 2 m x) e^{-x} dx with ``npts`` nodes.
+
+    Plain construction at ``dps`` decimal digits: moments by mpmath.quad, the
+    monic orthogonal polynomial from the Hankel system, its roots as nodes and
+    the weights from the moment (Vandermonde) equations.
+    """
+    with mpmath.workdps(dps):
+        mm = mpmath.mpf(m)
+        wfun = lambda x: mpmath.sqrt(x * x + 2 * mm * x) * mpmath.exp(-x)
+        mu = [mpmath.quad(lambda x, k=k: x ** k * wfun(x), [0, 1, 10, mpmath.inf])
+              for k in range(2 * npts)]
+        H = mpmath.matrix(npts, npts)
+        rhs = mpmath.matrix(npts, 1)
+        for i in range(npts):
+            for j in range(npts):
+                H[i, j] = mu[i + j]
+            rhs[i] = -mu[i + npts]
+        c = mpmath.lu_solve(H, rhs)                  # pi(x) = x^n + sum_j c_j x^j
+        coeffs = [mpmath.mpf(1)] + [c[j] for j in reversed(range(npts))]
+        nodes = sorted([mpmath.re(r) for r in mpmath.polyroots(coeffs, maxsteps=200, extraprec=200)])
+        V = mpmath.matrix(npts, npts)
+        b = mpmath.matrix(npts, 1)
+        for k in range(npts):
+            for j in range(npts):
+                V[k, j] = nodes[j] ** k
+            b[k] = mu[k]
+        W = mpmath.lu_solve(V, b)
+        return np.array([float(v) for v in nodes]), np.array([float(W[j]) for j in range(npts)])
+
+
+def product_3d(m: float, order: int) -> Quadrature:
+    """Off-lattice (3+1)-d product rule: radial Gauss rule times the 26-direction rule."""
+    x, W = radial_gauss_3d(m, order + 1)
+    W = W / W.sum()
+    gw = octahedral_group_weights()
+    dir_w = [gw[0]] * 6 + [gw[1]] * 12 + [gw[2]] * 8
+    p, w, disp = [], [], []
+    for j in range(order + 1):
+        p0 = m + x[j]
+        pm = math.sqrt(x[j] * x[j] + 2.0 * m * x[j])
+        v = pm / p0
+        for k, n in enumerate(DIRS_3D):
+            u = np.array(n, dtype=float) / np.linalg.norm(n)
+            p.append((p0, *(pm * u)))
+            w.append(W[j] * dir_w[k])
+            disp.append(tuple(v * u))
+    return Quadrature(3, float(m), order, np.array(p), np.array(w), np.array(disp), False)
+
+
+def rest_frame_moment(idx, m: float, d: int) -> float:
+    """int omega(p^0) p^{idx} d^dp/p^0 for the weight omega = C exp(-p^0) normalised to 1.
+
+    omega is the rest-frame Maxwell-Juettner at T = T0 = 1 (Sec. 5.2); its
+    moments follow from ``mj.mj_tensor_moment`` with U = (1, 0, ..) and the
+    density n = A_1/A_0 that makes the zeroth moment equal to one.
+    """
+    import torch
+    U = torch.zeros(d + 1, dtype=torch.float64)
+    U[0] = 1.0
+    T = torch.tensor(1.0, dtype=torch.float64)
+    z = torch.tensor(float(m), dtype=torch.float64)
+    n = 1.0 / mj.a_ratio(0, z, d) if d == 2 else 1.0 / float(mj.a_ratio(0, float(m), d))
+    return float(mj.mj_tensor_moment(tuple(idx), n, T, U, float(m), d))

@@ -1,0 +1,229 @@
+"""Pins of the oracle's time step (Sec. 6.2) against what the method fixes.
+
+* Landau frame: a stress-energy tensor built from known (eps, P, U) plus a
+  shear part orthogonal to U gives back eps and U (Sec. 4).
+* Collision invariants: the Anderson-Witting update conserves N^0 and T^{0a}
+  at every site (Sec. 3 conservation laws; discrete form of Sec. 6.2 step 8).
+* A uniform equilibrium is a fixed point of the whole step.
+* Streaming: integer displacements are exact shifts (Sec. 6.3); interpolated
+  streaming conserves sum_x f_i per population on a periodic grid.
+* Global conservation over many steps (periodic grids).
+* Taylor-Green decay (Sec. 7.1, Eq. tg-relativistic-approx) against the
+  Chapman-Enskog viscosity of App. C, with the lattice viscosity read as
+  eta = f_CE(zeta) P (tau - 1/2) (dt = 1).
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import workloads as W
+from oracle import lattice as L
+from oracle import mj
+from oracle import quadrature as qd
+
+RULES = {
+    "ur": lambda: qd.ur_onlattice_2d(),
+    "p2m0": lambda: qd.product_2d(0.0, 3),
+    "p2m1": lambda: qd.product_2d(1.0, 3),
+    "p2m5": lambda: qd.product_2d(5.0, 3),
+    "p3m1": lambda: qd.product_3d(1.0, 3),
+}
+
+
+def random_state(lat, shape, seed, amp=0.05, umax=0.3):
+    g = np.random.default_rng(seed)
+    d = lat.d
+    n = torch.tensor(g.uniform(0.7, 1.4, shape))
+    T = torch.tensor(g.uniform(0.8, 1.3, shape))
+    u = torch.tensor(g.uniform(-umax, umax, (d,) + shape)) / math.sqrt(d)
+    xi = torch.tensor(g.uniform(-1, 1, (lat.quad.Q,) + shape))
+    return lat.init(n, T, u, xi, amp), (n, T, u)
+
+
+@pytest.mark.parametrize("d", [2, 3])
+def test_landau_recovers_known_state(d):
+    g = np.random.default_rng(3)
+    lat = L.Lattice(qd.product_2d(1.0, 2) if d == 2 else qd.product_3d(1.0, 2), 1.0, (4,) * d)
+    eta = L.eta_matrix(d).numpy()
+    S = 6
+    Ts, eps_ref, U_ref = [], [], []
+    for _ in range(S):
+        u = g.uniform(-0.5, 0.5, d) / math.sqrt(d)
+        U = np.concatenate([[1.0], u]) / math.sqrt(1 - u @ u)
+        eps, P = g.uniform(1, 3), g.uniform(0.2, 0.9)
+        Delta = eta - np.outer(U, U)                       # Delta^{ab} = eta^{ab} - U^a U^b
+        A = g.normal(size=(d + 1, d + 1)) * 0.1
+        A = A + A.T
+        pi = Delta @ eta @ A @ eta @ Delta                 # Delta^a_c A^{cd} Delta_d^b, orthogonal to U
+        T = (eps + P) * np.outer(U, U) - P * eta + pi
+        Ts.append(T)
+        eps_ref.append(eps)
+        U_ref.append(U)
+    Tt = torch.tensor(np.stack(Ts, axis=-1))[..., None]    # (d+1, d+1, S, 1)
+    eps_got, U_got = lat.landau(Tt)
+    assert np.allclose(eps_got[:, 0].numpy(), eps_ref, rtol=1e-13)
+    assert np.allclose(U_got[:, :, 0].numpy().T, np.array(U_ref), atol=1e-13)
+
+
+@pytest.mark.parametrize("rule", list(RULES))
+def test_collision_invariants(rule):
+    q = RULES[rule]()
+    shape = (5, 4) if q.d == 2 else (3, 3, 2)
+    lat = L.Lattice(q, 0.77, tuple(reversed(shape)))
+    f, _ = random_state(lat, shape, seed=11)
+    df = lat.collide(f) - f
+    p0 = lat.p[:, 0].reshape((-1,) + (1,) * q.d)
+    N0 = (p0 * f).sum(0).abs().max()
+    dN0 = (p0 * df).sum(0).abs().max()
+    assert dN0 / N0 < 2e-14
+    for a in range(q.d + 1):
+        pa = lat.p[:, a].reshape(p0.shape)
+        T0a = (p0 * p0 * f).sum(0).abs().max()
+        assert (p0 * pa * df).sum(0).abs().max() / T0a < 2e-14
+    # the collision does change non-conserved moments (the check is not vacuous)
+    assert (lat.p[:, 1].reshape(p0.shape) ** 2 * df).sum(0).abs().max() > 1e-6
+
+
+@pytest.mark.parametrize("rule", ["ur", "p2m1", "p3m1"])
+@pytest.mark.parametrize("bc", ["periodic", "open"])
+def test_uniform_equilibrium_is_fixed_point(rule, bc):
+    q = RULES[rule]()
+    shape = (6, 7) if q.d == 2 else (3, 4, 5)
+    lat = L.Lattice(q, 0.9, tuple(reversed(shape)), bc=(bc,) + ("periodic",) * (q.d - 1))
+    n = torch.full(shape, 1.2, dtype=torch.float64)
+    T = torch.full(shape, 1.1, dtype=torch.float64)
+    u = torch.zeros((q.d,) + shape, dtype=torch.float64)
+    u[0] = 0.2
+    f = lat.init(n, T, u)
+    f2 = lat.run(f, 3)
+    assert (f2 - f).abs().max() / f.abs().max() < 1e-13
+
+
+def test_integer_streaming_is_a_shift():
+    q = qd.ur_onlattice_2d()
+    lat = L.Lattice(q, 0.9, (16, 12))
+    g = torch.tensor(np.random.default_rng(0).uniform(size=(q.Q, 12, 16)))
+    out = lat.stream(g)
+    for i in range(q.Q):
+        dx, dy = int(q.disp[i, 0]), int(q.disp[i, 1])
+        assert torch.equal(out[i], torch.roll(g[i], shifts=(dy, dx), dims=(0, 1)))
+
+
+@pytest.mark.parametrize("rule", ["p2m1", "p3m1"])
+def test_interpolated_streaming_conserves_each_population(rule):
+    q = RULES[rule]()
+    shape = (9, 11) if q.d == 2 else (4, 5, 6)
+    lat = L.Lattice(q, 0.9, tuple(reversed(shape)))
+    g = torch.tensor(np.random.default_rng(1).uniform(size=(q.Q,) + shape))
+    out = lat.stream(g)
+    dims = tuple(range(1, q.d + 1))
+    assert torch.allclose(out.sum(dims), g.sum(dims), rtol=1e-14)
+    # a linear field along x is shifted by exactly -delta_x (interpolation is exact on linear data)
+    if q.d == 2:
+        lat2 = L.Lattice(q, 0.9, (40, 5), bc=("open", "periodic"))
+        x = torch.arange(40, dtype=torch.float64)
+        lin = (x[None, None, :] * torch.ones((q.Q, 5, 1), dtype=torch.float64))
+        o = lat2.stream(lin)
+        for i in range(q.Q):
+            assert torch.allclose(o[i, :, 2:-2], lin[i, :, 2:-2] - q.disp[i, 0], atol=1e-12)
+
+
+@pytest.mark.parametrize("rule,nsteps", [("ur", 20), ("p2m1", 20), ("p2m5", 10), ("p3m1", 4)])
+def test_global_conservation(rule, nsteps):
+    q = RULES[rule]()
+    shape = (16, 20) if q.d == 2 else (5, 6, 7)
+    lat = L.Lattice(q, 0.7, tuple(reversed(shape)))
+    f, _ = random_state(lat, shape, seed=5, amp=0.02, umax=0.2)
+    p0 = lat.p[:, 0].reshape((-1,) + (1,) * q.d)
+
+    def invariants(f):
+        out = [(p0 * f).sum()]
+        for a in range(q.d + 1):
+            out.append((p0 * lat.p[:, a].reshape(p0.shape) * f).sum())
+        return torch.stack(out)
+
+    I0 = invariants(f)
+    f = lat.run(f, nsteps)
+    I1 = invariants(f)
+    scale = I0.abs().max()
+    assert ((I1 - I0).abs() / scale).max() < 1e-13
+
+
+def _tg_rate(q, L_side, tau, u0, nsteps, t0, amp=0.0, seed=1):
+    lat = L.Lattice(q, tau, (L_side, L_side))
+    n, T, u = W.taylor_green_2d(L_side, L_side, u0)
+    xi = W.population_noise(q.Q, (L_side, L_side), seed) if amp else None
+    f = lat.init(torch.tensor(n), torch.tensor(T), torch.tensor(u),
+                 torch.tensor(xi) if xi is not None else None, amp)
+    ts, logs = [], []
+    for t in range(nsteps + 1):
+        if t >= t0:
+            mac = lat.macro(f)
+            U = mac["U"]
+            ubar = torch.sqrt(((U[1] / U[0]) ** 2 + (U[2] / U[0]) ** 2).mean())
+            ts.append(t)
+            logs.append(math.log(ubar.item()))
+        if t < nsteps:
+            f = lat.step(f)
+    slope = np.polyfit(ts, logs, 1)[0]
+    return -slope
+
+
+def discrete_shear_factor(q):
+    """Ratio of the Chapman-Enskog stress moment for the Taylor-Green strain, rule vs continuum.
+
+    The Chapman-Enskog shear stress (App. C.1) of the Anderson-Witting model in the rest frame
+    involves the fourth-rank moment int f^eq p^i p^j p^k p^l / p^0.  For the massless rule this
+    is sum_i w_i p0_i^3 n^i n^j n^k n^l, which the printed order-2 rule does not integrate exactly
+    (it is not a polynomial of degree <= 4).  The Taylor-Green strain is purely
+    d_x u_x - d_y u_y, whose viscosity is (A - B)/2 with A = <p0^3 n_x^4>, B = <p0^3 n_x^2 n_y^2>.
+    Continuum: <p0^3> = 3! = 6, <n_x^4> = 3/8, <n_x^2 n_y^2> = 1/8.
+    """
+    p0 = q.p[:, 0]
+    nx, ny = q.p[:, 1] / p0, q.p[:, 2] / p0
+    A = np.sum(q.w * p0 ** 3 * nx ** 4)
+    B = np.sum(q.w * p0 ** 3 * nx ** 2 * ny ** 2)
+    return (A - B) / (6 * 3 / 8 - 6 * 1 / 8)
+
+
+def test_taylor_green_decay_ultra_relativistic_onlattice():
+    """64 x 64, zeta = 0, N = 2 printed rule, u0 = 0.01, 1e-6 population noise (seed 1).
+
+    Prediction: u ~ exp(-gamma t), gamma = 2 k^2 eta/(eps + P) (Sec. 7.1, Eq. tg-relativistic-approx)
+    with eta = f_CE(0) s P (tau - 1/2), f_CE(0) = 3/4, (eps + P)/P = G_2(0) = 3, k = 2 pi/(64 v0),
+    v0 = 1/5, and s the rule's discrete factor above (s = 0.6931 for this rule).
+    """
+    q = qd.ur_onlattice_2d()
+    s = discrete_shear_factor(q)
+    assert abs(s - 0.6931) < 5e-4
+    k = 2 * math.pi / (64 * 0.2)
+    rates = {}
+    for tau in (0.6, 0.9):
+        rates[tau] = _tg_rate(q, 64, tau, 0.01, 100, 10, amp=1e-6)
+        pred = 2 * k * k * mj.ce_shear_ratio(0.0, 2) * s * (tau - 0.5) / 3.0
+        assert abs(rates[tau] - pred) / pred < 0.025, (tau, rates[tau], pred)
+    # the rate is linear in tau with its zero at tau0 ~ 1/2 (the dt/2 lattice shift)
+    tau0 = 0.6 - rates[0.6] * (0.9 - 0.6) / (rates[0.9] - rates[0.6])
+    assert abs(tau0 - 0.5) < 0.02
+
+
+def test_product_rule_has_no_discrete_shear_factor():
+    # equally spaced directions on every shell: the fourth-rank moment is isotropic and exact
+    assert abs(discrete_shear_factor(qd.product_2d(0.0, 3)) - 1.0) < 1e-13
+
+
+def test_taylor_green_viscosity_slope_off_lattice():
+    """Off-lattice product rule, zeta = 1: d gamma / d tau = 2 k^2 f_CE(1) / G_2(1).
+
+    Interpolation adds a tau-independent numerical viscosity, so only the slope is pinned.
+    """
+    q = qd.product_2d(1.0, 3)
+    Ls = 48
+    k = 2 * math.pi / Ls
+    r1 = _tg_rate(q, Ls, 0.8, 0.01, 120, 20)
+    r2 = _tg_rate(q, Ls, 1.4, 0.01, 120, 20)
+    slope = (r2 - r1) / 0.6
+    pred = 2 * k * k * mj.ce_shear_ratio(1.0, 2) / float(mj.G_d(1.0, 2))
+    assert abs(slope - pred) / pred < 0.04, (slope, pred)
