@@ -1,0 +1,142 @@
+"""Benchmark of the RLBM collide-and-stream update on one MI355X.
+
+Workload (the 2D configuration the headline metric is quoted on): d = 2,
+zeta = 1, order N = 3, off-lattice product quadrature (Q = 32), 1024 x 1024
+periodic grid, relativistic Taylor-Green vortex u0 = 0.1, T = 1, density
+1 + 1e-3 N(0,1) (seed 2), tau = 0.8, double storage.  A step is one fused
+stream + collide over the whole lattice.
+
+Prints one JSON line: MLUPS (10^6 site updates per second), the HBM roofline
+of the step kernel (algorithmic bytes 2 Q s per site), variants (float
+deviation storage), and the FP64 CPU oracle timed on this host.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "MLUPS and % HBM roofline (fwd, adjoint, batched) at stated error vs FP64 oracle"
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--size", type=int, default=1024)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-variants", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    return ap.parse_args()
+
+
+def time_steps(lat, fa, fb, warmup, steps):
+    """Average duration of one step, from HIP events on the launch stream around `steps` steps."""
+    import torch
+    lat.step(fa, fb, warmup)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    lat.step(fa, fb, steps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    lat.sync()
+    return e0.elapsed_time(e1) / steps * 1e-3       # seconds per step
+
+
+def make_lattice(L, storage):
+    import torch
+    import workloads as W
+    from paper_1909_04502_amd import rlbm as R
+    n, T, u = W.taylor_green_2d(L, L, 0.1, density_sigma=1e-3, seed=2)
+    lat = R.Lattice(d=2, zeta=1.0, order=3, kind="product", extent=(L, L), storage=storage, tau=0.8)
+    fa = lat.init(torch.tensor(n), torch.tensor(T), torch.tensor(u))
+    fb = lat.new_state()
+    return lat, fa, fb
+
+
+def cpu_baseline(seconds):
+    """The FP64 oracle (as it stands) on a 128 x 128 lattice of the same workload, on this host's cores."""
+    import torch
+    import workloads as W
+    from oracle import lattice as OL
+    from oracle import quadrature as qd
+    L = 128
+    n, T, u = W.taylor_green_2d(L, L, 0.1, density_sigma=1e-3, seed=2)
+    ol = OL.Lattice(qd.product_2d(1.0, 3), 0.8, (L, L))
+    f = ol.collide(ol.init(torch.tensor(n), torch.tensor(T), torch.tensor(u)))
+    steps = 0
+    t0 = time.perf_counter()
+    while time.perf_counter() - t0 < seconds or steps < 2:
+        f = ol.collide(ol.stream(f))
+        steps += 1
+    dt = time.perf_counter() - t0
+    return {"value": L * L * steps / dt / 1e6, "unit": "MLUPS", "cores": torch.get_num_threads(),
+            "kind": "oracle",
+            "sample": f"{steps} steps of a {L}x{L} lattice of the same workload ({dt:.1f} s, torch float64 on CPU)"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py: this build measures one GPU only (asked for --gpus {args.gpus}); "
+              "the path is a single-GPU lattice update", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    torch.cuda.set_device(0)
+    L = args.size
+    Q = 32
+    sites = L * L
+    lat, fa, fb = make_lattice(L, "f64")
+    t = time_steps(lat, fa, fb, args.warmup, args.steps)
+    mlups = sites / t / 1e6
+    bytes_step = 2 * Q * 8 * sites
+    achieved = bytes_step / t / 1e9
+    out = {
+        "metric": METRIC,
+        "value": round(mlups, 2),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(t * 1e3, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"2D RLBM zeta=1 N=3 Q=32 off-lattice, {L}x{L} periodic, Taylor-Green u0=0.1, "
+                               f"tau=0.8, density noise 1e-3 (seed 2)",
+                   "sites": sites, "Q": Q, "storage": "f64"},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "kernel": "k_step<Stencil<PROD2D,4>,3,double>", "algorithmic_bytes_per_site": 2 * Q * 8},
+    }
+    del lat, fa, fb
+    torch.cuda.empty_cache()
+    if not args.no_variants:
+        lat, fa, fb = make_lattice(L, "f32dev")
+        t32 = time_steps(lat, fa, fb, args.warmup, args.steps)
+        b32 = 2 * Q * 4 * sites
+        out["variants"] = {"f32dev": {"MLUPS": round(sites / t32 / 1e6, 2), "ms_per_step": round(t32 * 1e3, 5),
+                                      "achieved_GBs": round(b32 / t32 / 1e9, 1),
+                                      "frac": round(b32 / t32 / 1e9 / HBM_PEAK_GBS, 4)}}
+        del lat, fa, fb
+        torch.cuda.empty_cache()
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

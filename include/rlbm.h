@@ -1,0 +1,182 @@
+/*
+ * rlbm.h -- C ABI of an MI355X (gfx950) library for the relativistic lattice
+ * Boltzmann method (RLBM) of Gabbana, Simeoni, Succi, Tripiccione,
+ * "Relativistic Lattice Boltzmann Methods: Theory and Applications",
+ * arXiv:1909.04502.
+ *
+ * The library implements the per-site collide-and-stream update of Sec. 6.2:
+ * moments N^a and T^ab (step 1), the Landau-frame eigenproblem
+ * T^ab U_b = eps U^a (step 2), n = U_a N^a (step 3), the temperature from the
+ * equation of state eps/n = T (G_d(m/T) - 1) (step 4, Sec. 3 Eqs. defG and
+ * eos-ddim), the equilibrium projected on orthonormal polynomials up to order
+ * N (step 5, Sec. 5.2 Eqs. mj-feq-expansion and mj-discrete-feq), and
+ * Anderson-Witting relaxation Omega_i = p_i.U/(p_i^0 tau) followed by
+ * streaming (step 8, Sec. 5.1 Eq. discrete-rbe).  Off-lattice velocities are
+ * streamed by linear interpolation (bilinear in 2D, trilinear in 3D).
+ *
+ * Units: lattice units with c = k_B = 1 and reference temperature T0 = 1
+ * (Sec. 6.1).  zeta = m c^2 / (k_B T0) is the reduced mass of Sec. 5.2.
+ *
+ * Memory and ownership
+ *   All population, field and gradient buffers are allocated and owned by the
+ *   caller, in device memory of the current HIP device, and are passed as
+ *   plain pointers.  Every call enqueues its work on the given hipStream_t
+ *   (0 = the null stream) and returns without synchronising.  A handle owns
+ *   only small constant tables, an error flag and cached launch graphs; it is
+ *   freed by the matching destroy call.  One handle must not be used from two
+ *   streams at once.
+ *
+ * Population layout ("SoA")
+ *   f[i * sites + s] with s = x + nx * (y + ny * z) (x fastest), i the
+ *   population index.  Population order: shell-major, i = j * n_dirs + k,
+ *   with directions (2D product rule)
+ *     (1,0) (-1,0) (0,1) (0,-1) (1,1) (-1,-1) (-1,1) (1,-1)          [unit vectors]
+ *   and (3D product rule) the 6 axis, 12 edge, 8 corner directions
+ *     (+-1,0,0) (0,+-1,0) (0,0,+-1), (1,1,0) (-1,-1,0) (1,-1,0) (-1,1,0),
+ *     (1,0,1) (-1,0,-1) (1,0,-1) (-1,0,1), (0,1,1) (0,-1,-1) (0,1,-1) (0,-1,1),
+ *     (1,1,1) (-1,-1,-1) (1,1,-1) (-1,-1,1) (1,-1,1) (-1,1,-1) (-1,1,1) (1,-1,-1);
+ *   for the printed on-lattice massless rule (Sec. 5.3 / App. H.2, order 2)
+ *     (3,4) (-3,-4) (-3,4) (3,-4) (4,3) (-4,-3) (-4,3) (4,-3) (5,0) (-5,0) (0,5) (0,-5)
+ *   on three shells, zero-weight populations dropped (28 populations).
+ *   Antipodal populations are always adjacent (i, i+1 for even i).
+ *
+ * State convention
+ *   A state buffer holds the post-collision populations f*(x, t) (the values
+ *   about to stream).  rlbm_init builds f*(x, 0) from the initial fields;
+ *   rlbm_step advances t by streaming then colliding; the pre-collision
+ *   populations of time t are f(x, t) = f*(x - delta_i, t - 1) (interpolated).
+ *
+ * Storage (rlbm_storage)
+ *   RLBM_F64      populations stored as double.
+ *   RLBM_F32_DEV  populations stored as float deviations g_i = f_i - f^ref_i
+ *                 from the rest-frame equilibrium f^ref(n_ref, T = 1, U = 0);
+ *                 moments accumulate the deviations in float, the
+ *                 eigenproblem, equation of state and equilibrium
+ *                 coefficients are computed in double.
+ *
+ * Errors
+ *   Functions return rlbm_status.  Invalid arguments are reported
+ *   synchronously.  A non-physical state met by a kernel (n <= 0, eps <= 0,
+ *   T <= 0, NaN, a space-like Landau eigenvector) sets a device flag that
+ *   rlbm_sync reports as RLBM_ERR_NONPHYSICAL.
+ */
+#ifndef RLBM_H
+#define RLBM_H
+
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  RLBM_OK = 0,
+  RLBM_ERR_INVALID_ARG = 1,   /* bad pointer, size, or parameter */
+  RLBM_ERR_UNSUPPORTED = 2,   /* valid request outside what this build implements */
+  RLBM_ERR_QUADRATURE = 3,    /* quadrature construction or verification failed */
+  RLBM_ERR_DEVICE = 4,        /* a HIP runtime call failed */
+  RLBM_ERR_NONPHYSICAL = 5    /* a kernel met a non-physical state (see above) */
+} rlbm_status;
+
+typedef enum { RLBM_F64 = 0, RLBM_F32_DEV = 1 } rlbm_storage;
+typedef enum { RLBM_PERIODIC = 0, RLBM_OPEN = 1 } rlbm_bc;
+typedef enum {
+  RLBM_QUAD_UR_ONLATTICE = 0, /* printed massless (2+1)-d order-2 rule, integer streaming (zeta = 0) */
+  RLBM_QUAD_PRODUCT = 1       /* off-lattice product rule: shells x directions, interpolated streaming */
+} rlbm_quad_kind;
+
+/* The paper's statement of the problem (Sec. 5.2-5.3): dimension d, reduced
+ * mass zeta = m/T0, expansion order N and the quadrature. */
+typedef struct {
+  int32_t d;        /* spatial dimensions: 2 or 3 */
+  int32_t order;    /* expansion order N: 2 or 3 (RLBM_QUAD_UR_ONLATTICE: 2) */
+  int32_t kind;     /* rlbm_quad_kind */
+  int32_t pad_;
+  double zeta;      /* reduced mass m c^2/(k_B T0), >= 0 */
+} rlbm_model;
+
+typedef struct {
+  rlbm_model model;
+  int64_t extent[3];   /* nx, ny, nz (nz = 1 for d = 2); each >= 1 */
+  int32_t bc[3];       /* rlbm_bc per axis; RLBM_OPEN = zero-gradient (reads clamp to the edge) */
+  int32_t storage;     /* rlbm_storage */
+  double tau;          /* relaxation time, used where tau_field is NULL; > 0.5 recommended */
+  const void *tau_field; /* device [sites] per-site tau, double (F64) or float (F32_DEV), or NULL */
+  double n_ref;        /* reference density of the F32_DEV deviations (T_ref = 1, U = 0) */
+} rlbm_config;
+
+typedef struct {
+  int32_t Q;           /* populations per site */
+  int32_t n_basis;     /* dimension of the polynomial space (N+1)^2 (2D), (N+1)(N+2)(2N+3)/6 (3D) */
+  int64_t sites;       /* nx * ny * nz */
+  int64_t state_bytes; /* bytes of one population buffer */
+  int32_t elem_bytes;  /* 8 (F64) or 4 (F32_DEV) */
+  int32_t on_lattice;  /* 1 if displacements are integers */
+} rlbm_info;
+
+typedef struct rlbm_lattice rlbm_lattice;   /* opaque */
+
+/* Macroscopic output fields (device, [sites] each; U is [d+1][sites]).
+ * Any pointer may be NULL to skip that field. */
+typedef struct {
+  double *n;     /* particle density n = U_a N^a (Sec. 6.2 step 3) */
+  double *eps;   /* energy density, largest eigenvalue of T^a_b (step 2) */
+  double *T;     /* temperature from the equation of state (step 4) */
+  double *U;     /* four-velocity, U^a U_a = 1, U^0 > 0 (step 2) */
+} rlbm_fields;
+
+/* ---------------------------------------------------------------- host only */
+
+/* Build the quadrature of a model on the host (Sec. 5.3; App. H.2 for the
+ * printed rule).  Call with p = w = disp = NULL to query *Q.  Otherwise p is
+ * [Q][d+1] (energy first), w is [Q], disp is [Q][d] (sites per step), all host
+ * memory of the caller.  No GPU is touched. */
+rlbm_status rlbm_quadrature_build(const rlbm_model *model, int32_t *Q,
+                                  double *p, double *w, double *disp);
+
+const char *rlbm_status_string(rlbm_status s);
+
+/* Message of the last failing call on this host thread (static storage, valid
+ * until the next failing call on the same thread). */
+const char *rlbm_last_error(void);
+
+/* ---------------------------------------------------------------- lattices */
+
+/* Create a lattice handle: builds and verifies the quadrature and the
+ * projection matrix on the host, uploads them, and picks a launch shape.
+ * Synchronous.  *out receives the handle. */
+rlbm_status rlbm_create(const rlbm_config *cfg, rlbm_lattice **out);
+rlbm_status rlbm_destroy(rlbm_lattice *h);
+rlbm_status rlbm_get_info(const rlbm_lattice *h, rlbm_info *info);
+
+/* Initial condition (Sec. 6.2: f(x, t0) = f^eq).  Inputs are device arrays of
+ * [sites] doubles: density n0, temperature T0 and the d components of the
+ * three-velocity u0 ([d][sites], |u0| < 1; U = gamma (1, u0)).  noise is NULL
+ * or a device [Q][sites] double array xi; the pre-collision populations are
+ * f^eq_i (1 + noise_amp xi_i).  Writes the post-collision state f*(x, 0) to
+ * f_out (state layout above).  fields0 (may be NULL) receives the macroscopic
+ * fields of the pre-collision state at t = 0. */
+rlbm_status rlbm_init(rlbm_lattice *h, const double *n0, const double *T0, const double *u0,
+                      const double *noise, double noise_amp, void *f_out,
+                      const rlbm_fields *fields0, hipStream_t stream);
+
+/* Advance nsteps >= 0 time steps, ping-ponging between f_a (input) and f_b.
+ * The result is in f_b when nsteps is odd and in f_a when it is even.  f_a and
+ * f_b must not overlap.  last (may be NULL) receives the macroscopic fields of
+ * the pre-collision state of the final step's time level. */
+rlbm_status rlbm_step(rlbm_lattice *h, void *f_a, void *f_b, int32_t nsteps,
+                      const rlbm_fields *last, hipStream_t stream);
+
+/* Macroscopic fields of the populations obtained by streaming the state f
+ * (i.e. the pre-collision state of the next time level). */
+rlbm_status rlbm_moments(rlbm_lattice *h, const void *f, const rlbm_fields *out,
+                         hipStream_t stream);
+
+/* Drain the stream and report a deferred device error (clears the flag). */
+rlbm_status rlbm_sync(rlbm_lattice *h, hipStream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* RLBM_H */

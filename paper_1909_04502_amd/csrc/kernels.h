@@ -1,0 +1,34 @@
+// kernels.h -- launch interface between the C ABI runtime and the HIP kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "rlbm_defs.h"
+
+namespace rlbm {
+
+enum Op : int { OP_STEP = 0, OP_MOMENTS = 1, OP_INIT = 2 };
+
+// Device pointers of the macroscopic output fields (NULL = skip).
+struct FieldPtrs {
+  double *n, *eps, *T, *U;
+  int any;
+};
+
+struct LaunchArgs {
+  int op = 0;
+  int stencil = 0, order = 0, storage = 0;
+  int nx = 0, ny = 0, nz = 1;
+  const Tables *tb = nullptr;      // device pointer
+  const void *fin = nullptr;
+  void *fout = nullptr;
+  const void *tau_field = nullptr;
+  FieldPtrs fields = {nullptr, nullptr, nullptr, nullptr, 0};
+  const double *n0 = nullptr, *T0 = nullptr, *u0 = nullptr, *noise = nullptr;
+  double amp = 0.0;
+  int *err = nullptr;               // device error flag
+  hipStream_t stream = 0;
+};
+
+hipError_t launch(const LaunchArgs &a);
+
+}  // namespace rlbm

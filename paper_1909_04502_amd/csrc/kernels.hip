@@ -1,0 +1,414 @@
+// kernels.hip -- HIP kernels of the RLBM update for gfx950 (MI355X).
+//
+// Design (memory-bound: 2 Q words of HBM traffic per site update):
+//  * populations in SoA planes f[i][z][y][x]; one thread per site, 64-wide
+//    wavefronts along x so every population plane is read and written with
+//    fully coalesced 512 B (f64) / 256 B (f32) wavefront accesses;
+//  * fused pull-stream + collide: the pre-collision value of population i at
+//    x is read from the post-collision planes at the upstream taps (a pure
+//    shift on-lattice; bilinear / trilinear interpolation off-lattice, taps
+//    and their count fixed at compile time from the direction signs, weights
+//    from the per-lattice table); neighbouring taps of a wavefront hit the
+//    same cache lines, so the extra taps are served from L1/L2, not HBM;
+//  * all constant tables are read through uniform (scalar) loads;
+//  * antipodal populations are processed in pairs: sums and differences feed
+//    the even / odd halves of the moments and of the projected equilibrium,
+//    halving both the moment and the equilibrium arithmetic;
+//  * the Landau eigenproblem, equation of state and equilibrium moments are
+//    evaluated in double for every storage mode.
+#include <hip/hip_runtime.h>
+
+#include <utility>
+
+#include "device_math.h"
+#include "kernels.h"
+
+namespace rlbm {
+
+__device__ __forceinline__ int wrap_or_clamp(int v, int n, int open) {
+  if (open) return v < 0 ? 0 : (v >= n ? n - 1 : v);
+  v = v < 0 ? v + n : v;
+  return v >= n ? v - n : v;
+}
+
+// Coordinates of the upstream neighbours -1, 0, +1 along each axis.
+struct Nbr {
+  int x[3], y[3], z[3];
+};
+
+template <class ST>
+__device__ __forceinline__ Nbr make_nbr(const Tables *__restrict__ tb, int x, int y, int z) {
+  Nbr nb;
+#pragma unroll
+  for (int o = -1; o <= 1; ++o) {
+    nb.x[o + 1] = wrap_or_clamp(x + o, tb->nx, tb->open[0]);
+    nb.y[o + 1] = wrap_or_clamp(y + o, tb->ny, tb->open[1]);
+    nb.z[o + 1] = ST::D == 3 ? wrap_or_clamp(z + o, tb->nz, tb->open[2]) : 0;
+  }
+  return nb;
+}
+
+template <typename S>
+struct Acc;
+template <>
+struct Acc<double> {
+  typedef double T;
+};
+template <>
+struct Acc<float> {
+  typedef float T;
+};
+
+// Pre-collision value of population I at the site (pull from post-collision planes).
+template <class ST, int I, typename S>
+__device__ __forceinline__ S pull(const Tables *__restrict__ tb, const S *__restrict__ f, int64_t sites,
+                                  const Nbr &nb, int x, int y, int z) {
+  const S *plane = f + (int64_t)I * sites;
+  const int nx = tb->nx, ny = tb->ny;
+  if constexpr (ST::ONLAT) {
+    const int sx = wrap_or_clamp(x - ST::dir(I, 0), nx, tb->open[0]);
+    const int sy = wrap_or_clamp(y - ST::dir(I, 1), ny, tb->open[1]);
+    return plane[(int64_t)sy * nx + sx];
+  } else {
+    constexpr int dx = ST::dir(I, 0), dy = ST::dir(I, 1);
+    constexpr int dz = ST::D == 3 ? ST::dir(I, ST::D - 1) : 0;
+    constexpr int nzc = (dx != 0) + (dy != 0) + (dz != 0);
+    S acc = 0;
+#pragma unroll
+    for (int tap = 0; tap < (1 << nzc); ++tap) {
+      int bit = 0, ox = 0, oy = 0, oz = 0;
+      if (dx != 0) {
+        const int c = (tap >> bit++) & 1;
+        ox = dx > 0 ? (c ? 0 : -1) : (c ? 1 : 0);
+      }
+      if (dy != 0) {
+        const int c = (tap >> bit++) & 1;
+        oy = dy > 0 ? (c ? 0 : -1) : (c ? 1 : 0);
+      }
+      if (dz != 0) {
+        const int c = (tap >> bit++) & 1;
+        oz = dz > 0 ? (c ? 0 : -1) : (c ? 1 : 0);
+      }
+      const int64_t idx = ((int64_t)nb.z[oz + 1] * ny + nb.y[oy + 1]) * nx + nb.x[ox + 1];
+      S wgt;
+      if constexpr (sizeof(S) == 8)
+        wgt = tb->tapw[I][tap];
+      else
+        wgt = tb->tapwf[I][tap];
+      acc += wgt * plane[idx];
+    }
+    return acc;
+  }
+}
+
+template <class ST, typename S, int... I>
+__device__ __forceinline__ void pull_all_impl(const Tables *__restrict__ tb, const S *__restrict__ f, int64_t sites,
+                                              const Nbr &nb, int x, int y, int z, S (&v)[ST::Q],
+                                              std::integer_sequence<int, I...>) {
+  ((v[I] = pull<ST, I, S>(tb, f, sites, nb, x, y, z)), ...);
+}
+
+template <class ST, typename S>
+__device__ __forceinline__ void pull_all(const Tables *__restrict__ tb, const S *__restrict__ f, int64_t sites,
+                                         const Nbr &nb, int x, int y, int z, S (&v)[ST::Q]) {
+  pull_all_impl<ST, S>(tb, f, sites, nb, x, y, z, v, std::make_integer_sequence<int, ST::Q>{});
+}
+
+// Macroscopic state of a site (double).
+template <int D>
+struct Macro {
+  double n, eps, T;
+  double U[D + 1];
+  bool ok;
+};
+
+// ---------------------------------------------------------------------------
+// Collision of one site: f (pre-collision, storage precision; deviations in
+// the F32_DEV mode) is replaced by f* in place.  Returns the macro state of
+// the pre-collision populations.
+// ---------------------------------------------------------------------------
+template <class ST, int N, typename S, bool DEV, bool RELAX>
+__device__ __forceinline__ Macro<ST::D> collide(const Tables *__restrict__ tb, S (&f)[ST::Q], double tau) {
+  constexpr int D = ST::D, Q = ST::Q, NP = Q / 2;
+  using B = BasisDef<D, N>;
+  constexpr int NE = B::NE, NO = B::NO;
+  typedef typename Acc<S>::T A;
+  // ---- step 1: moments (pairs: s = f_i + f_i', d = f_i - f_i') ----
+  A me[2 + D * (D + 1) / 2];   // N^0, T^00, T^ab (a <= b spatial)
+  A mo[2 * D];                 // N^a, T^0a
+#pragma unroll
+  for (int k = 0; k < 2 + D * (D + 1) / 2; ++k) me[k] = 0;
+#pragma unroll
+  for (int k = 0; k < 2 * D; ++k) mo[k] = 0;
+#pragma unroll
+  for (int pr = 0; pr < NP; ++pr) {
+    const A s = (A)f[2 * pr] + (A)f[2 * pr + 1];
+    const A d = (A)f[2 * pr] - (A)f[2 * pr + 1];
+#pragma unroll
+    for (int k = 0; k < 2 + D * (D + 1) / 2; ++k) {
+      if constexpr (sizeof(A) == 8) me[k] += (A)tb->mom_e[pr][k] * s;
+      else me[k] += tb->mom_ef[pr][k] * s;
+    }
+#pragma unroll
+    for (int k = 0; k < 2 * D; ++k) {
+      if constexpr (sizeof(A) == 8) mo[k] += (A)tb->mom_o[pr][k] * d;
+      else mo[k] += tb->mom_of[pr][k] * d;
+    }
+  }
+  double Nv[D + 1], T[D + 1][D + 1];
+  Nv[0] = (double)me[0];
+  T[0][0] = (double)me[1];
+  {
+    int e = 2;
+#pragma unroll
+    for (int a = 1; a <= D; ++a)
+#pragma unroll
+      for (int b = a; b <= D; ++b) {
+        T[a][b] = T[b][a] = (double)me[e];
+        ++e;
+      }
+  }
+#pragma unroll
+  for (int a = 1; a <= D; ++a) {
+    Nv[a] = (double)mo[a - 1];
+    T[0][a] = T[a][0] = (double)mo[D + a - 1];
+  }
+  if constexpr (DEV) {
+    int s = 0;
+#pragma unroll
+    for (int a = 0; a <= D; ++a) {
+      Nv[a] += tb->Nref[a];
+#pragma unroll
+      for (int b = a; b <= D; ++b) {
+        T[a][b] += tb->Tref[s];
+        if (a != b) T[b][a] = T[a][b];
+        ++s;
+      }
+    }
+  }
+  // ---- steps 2-4 ----
+  Macro<D> mac;
+  mac.ok = landau_frame<D, 3>(T, mac.eps, mac.U);
+  mac.n = lorentz_dot<D>(mac.U, Nv);
+  const double m = tb->m;
+  Ratios rr;
+  if constexpr (D == 2) {
+    mac.ok = temperature_2d(mac.eps / mac.n, m, mac.T) && mac.ok;
+    rr = ratios_2d(m / mac.T);
+  } else {
+    double r;
+    mac.ok = temperature_3d(tb, mac.eps / mac.n, m, mac.T, r) && mac.ok;
+    rr = ratios_3d(m / mac.T, r);
+  }
+  mac.ok = mac.ok && mac.n > 0.0 && mac.eps > 0.0;
+  if constexpr (!RELAX) return mac;
+  // ---- step 5: equilibrium moments (deviation from the reference in F32_DEV) ----
+  double Md[B::NM];
+  basis_moments<D, N>(mac.n, mac.T, mac.U, rr, Md);
+  A M[B::NM];
+#pragma unroll
+  for (int k = 0; k < B::NM; ++k) M[k] = DEV ? (A)(Md[k] - tb->Mref[k]) : (A)Md[k];
+  // ---- step 8: Omega_i = (U^0 - c_i . U)/tau; f* = f + Omega (f^eq - f) ----
+  const double itau = 1.0 / tau;
+  const A a0 = (A)(mac.U[0] * itau);
+  A ub[D];
+#pragma unroll
+  for (int a = 0; a < D; ++a) ub[a] = (A)(mac.U[a + 1] * itau);
+#pragma unroll
+  for (int pr = 0; pr < NP; ++pr) {
+    A E = 0, O = 0, cb = 0;
+#pragma unroll
+    for (int k = 0; k < NE; ++k) {
+      if constexpr (sizeof(A) == 8) E += (A)tb->Re[pr][k] * M[k];
+      else E += tb->Ref[pr][k] * M[k];
+    }
+#pragma unroll
+    for (int k = 0; k < NO; ++k) {
+      if constexpr (sizeof(A) == 8) O += (A)tb->Ro[pr][k] * M[NE + k];
+      else O += tb->Rof[pr][k] * M[NE + k];
+    }
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+      if constexpr (sizeof(A) == 8) cb += (A)tb->c[pr][a] * ub[a];
+      else cb += tb->cf[pr][a] * ub[a];
+    }
+    const A om0 = a0 - cb, om1 = a0 + cb;
+    const A f0 = (A)f[2 * pr], f1 = (A)f[2 * pr + 1];
+    f[2 * pr] = (S)(f0 + om0 * ((E + O) - f0));
+    f[2 * pr + 1] = (S)(f1 + om1 * ((E - O) - f1));
+  }
+  return mac;
+}
+
+template <int D>
+__device__ __forceinline__ void write_fields(const FieldPtrs &fp, int64_t site, int64_t sites, const Macro<D> &mac) {
+  if (fp.n) fp.n[site] = mac.n;
+  if (fp.eps) fp.eps[site] = mac.eps;
+  if (fp.T) fp.T[site] = mac.T;
+  if (fp.U) {
+#pragma unroll
+    for (int a = 0; a <= D; ++a) fp.U[a * sites + site] = mac.U[a];
+  }
+}
+
+__device__ __forceinline__ void flag_error(int *err) {
+  // all writers store the same value: a benign race
+  *(volatile int *)err = 1;
+}
+
+template <typename S>
+__device__ __forceinline__ double site_tau(const Tables *__restrict__ tb, const void *tau_field, int64_t site) {
+  if (tau_field == nullptr) return tb->tau;
+  return (double)((const S *)tau_field)[site];
+}
+
+// ---------------------------------------------------------------------------
+// Kernels
+// ---------------------------------------------------------------------------
+template <class ST, int N, typename S, bool DEV>
+__global__ void __launch_bounds__(256) k_step(const Tables *__restrict__ tb, const S *__restrict__ fin,
+                                              S *__restrict__ fout, const void *__restrict__ tau_field,
+                                              FieldPtrs last, int *err) {
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  const int y = blockIdx.y * blockDim.y + threadIdx.y;
+  const int z = blockIdx.z;
+  if (x >= tb->nx || y >= tb->ny) return;
+  const int64_t sites = tb->sites;
+  const int64_t site = ((int64_t)z * tb->ny + y) * tb->nx + x;
+  const Nbr nb = make_nbr<ST>(tb, x, y, z);
+  S f[ST::Q];
+  pull_all<ST, S>(tb, fin, sites, nb, x, y, z, f);
+  const double tau = site_tau<S>(tb, tau_field, site);
+  const Macro<ST::D> mac = collide<ST, N, S, DEV, true>(tb, f, tau);
+  if (!mac.ok) flag_error(err);
+#pragma unroll
+  for (int i = 0; i < ST::Q; ++i) fout[(int64_t)i * sites + site] = f[i];
+  if (last.any) write_fields<ST::D>(last, site, sites, mac);
+}
+
+template <class ST, int N, typename S, bool DEV>
+__global__ void __launch_bounds__(256) k_moments(const Tables *__restrict__ tb, const S *__restrict__ fin,
+                                                 FieldPtrs out, int *err) {
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  const int y = blockIdx.y * blockDim.y + threadIdx.y;
+  const int z = blockIdx.z;
+  if (x >= tb->nx || y >= tb->ny) return;
+  const int64_t sites = tb->sites;
+  const int64_t site = ((int64_t)z * tb->ny + y) * tb->nx + x;
+  const Nbr nb = make_nbr<ST>(tb, x, y, z);
+  S f[ST::Q];
+  pull_all<ST, S>(tb, fin, sites, nb, x, y, z, f);
+  const Macro<ST::D> mac = collide<ST, N, S, DEV, false>(tb, f, 1.0);
+  if (!mac.ok) flag_error(err);
+  write_fields<ST::D>(out, site, sites, mac);
+}
+
+// f(x, 0) = f^eq(n0, T0, U(u0)) (1 + amp xi), then collide; store f*(x, 0).
+template <class ST, int N, typename S, bool DEV>
+__global__ void __launch_bounds__(256) k_init(const Tables *__restrict__ tb, const double *__restrict__ n0,
+                                              const double *__restrict__ T0, const double *__restrict__ u0,
+                                              const double *__restrict__ noise, double amp, S *__restrict__ fout,
+                                              const void *__restrict__ tau_field, FieldPtrs fields0, int *err) {
+  constexpr int D = ST::D, Q = ST::Q, NP = Q / 2;
+  using B = BasisDef<D, N>;
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  const int y = blockIdx.y * blockDim.y + threadIdx.y;
+  const int z = blockIdx.z;
+  if (x >= tb->nx || y >= tb->ny) return;
+  const int64_t sites = tb->sites;
+  const int64_t site = ((int64_t)z * tb->ny + y) * tb->nx + x;
+  double U[D + 1], uu = 0.0;
+#pragma unroll
+  for (int a = 0; a < D; ++a) {
+    U[a + 1] = u0[a * sites + site];
+    uu += U[a + 1] * U[a + 1];
+  }
+  const double g = 1.0 / sqrt(1.0 - uu);
+  U[0] = g;
+#pragma unroll
+  for (int a = 1; a <= D; ++a) U[a] *= g;
+  const double n = n0[site], T = T0[site];
+  Ratios rr;
+  if constexpr (D == 2) {
+    rr = ratios_2d(tb->m / T);
+  } else {
+    bool inr;
+    const double r = tb->m == 0.0 ? 0.0 : cheb_r(tb, tb->m / T, inr);
+    rr = ratios_3d(tb->m / T, r);
+  }
+  if (!(uu < 1.0) || !(n > 0.0) || !(T > 0.0)) flag_error(err);
+  double M[B::NM];
+  basis_moments<D, N>(n, T, U, rr, M);
+  double fd[Q];
+#pragma unroll
+  for (int pr = 0; pr < NP; ++pr) {
+    double E = 0.0, O = 0.0;
+#pragma unroll
+    for (int k = 0; k < B::NE; ++k) E += tb->Re[pr][k] * M[k];
+#pragma unroll
+    for (int k = 0; k < B::NO; ++k) O += tb->Ro[pr][k] * M[B::NE + k];
+    fd[2 * pr] = E + O;
+    fd[2 * pr + 1] = E - O;
+  }
+  if (noise != nullptr) {
+#pragma unroll
+    for (int i = 0; i < Q; ++i) fd[i] *= 1.0 + amp * noise[(int64_t)i * sites + site];
+  }
+  S f[Q];
+#pragma unroll
+  for (int i = 0; i < Q; ++i) f[i] = DEV ? (S)(fd[i] - tb->fref[i]) : (S)fd[i];
+  const double tau = site_tau<S>(tb, tau_field, site);
+  const Macro<D> mac = collide<ST, N, S, DEV, true>(tb, f, tau);
+  if (!mac.ok) flag_error(err);
+#pragma unroll
+  for (int i = 0; i < Q; ++i) fout[(int64_t)i * sites + site] = f[i];
+  if (fields0.any) write_fields<D>(fields0, site, sites, mac);
+}
+
+// ---------------------------------------------------------------------------
+// Dispatch
+// ---------------------------------------------------------------------------
+template <class ST, int N, typename S, bool DEV>
+static hipError_t launch_t(const LaunchArgs &a) {
+  const int bx = 64, by = 4;
+  dim3 block(bx, by, 1);
+  dim3 grid((a.nx + bx - 1) / bx, (a.ny + by - 1) / by, a.nz);
+  switch (a.op) {
+    case OP_STEP:
+      hipLaunchKernelGGL((k_step<ST, N, S, DEV>), grid, block, 0, a.stream, a.tb, (const S *)a.fin, (S *)a.fout,
+                         a.tau_field, a.fields, a.err);
+      break;
+    case OP_MOMENTS:
+      hipLaunchKernelGGL((k_moments<ST, N, S, DEV>), grid, block, 0, a.stream, a.tb, (const S *)a.fin, a.fields,
+                         a.err);
+      break;
+    case OP_INIT:
+      hipLaunchKernelGGL((k_init<ST, N, S, DEV>), grid, block, 0, a.stream, a.tb, a.n0, a.T0, a.u0, a.noise,
+                         a.amp, (S *)a.fout, a.tau_field, a.fields, a.err);
+      break;
+    default:
+      return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+template <class ST, int N>
+static hipError_t launch_storage(const LaunchArgs &a) {
+  if (a.storage == 0) return launch_t<ST, N, double, false>(a);
+  return launch_t<ST, N, float, true>(a);
+}
+
+hipError_t launch(const LaunchArgs &a) {
+  if (a.stencil == ST_UR2D) return launch_storage<Stencil<ST_UR2D, 3>, 2>(a);
+  if (a.stencil == ST_PROD2D) {
+    if (a.order == 2) return launch_storage<Stencil<ST_PROD2D, 3>, 2>(a);
+    return launch_storage<Stencil<ST_PROD2D, 4>, 3>(a);
+  }
+  if (a.stencil == ST_PROD3D) {
+    if (a.order == 2) return launch_storage<Stencil<ST_PROD3D, 3>, 2>(a);
+    return launch_storage<Stencil<ST_PROD3D, 4>, 3>(a);
+  }
+  return hipErrorInvalidValue;
+}
+
+}  // namespace rlbm

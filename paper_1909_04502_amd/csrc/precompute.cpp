@@ -1,0 +1,522 @@
+// precompute.cpp -- host construction of quadratures, basis and tables.
+//
+// Quadratures (Sec. 5.3; App. H.2 for the printed massless rule):
+//  * RLBM_QUAD_UR_ONLATTICE: the printed (2+1)-d order-2 rule.  Shells and
+//    weights are the paper's numbers; its stencil vectors have length 5, so a
+//    massless particle crosses 5 sites per step (v0 = 1/5, Sec. 6.1).
+//  * RLBM_QUAD_PRODUCT: off-lattice product rule.  In d = 2 the measure
+//    d^2p/p^0 = dp^0 dphi makes the radial weight e^{-(p^0 - m)}: Gauss-Laguerre
+//    shells times 8 equally weighted directions.  In d = 3, d^3p/p^0 =
+//    |p| dp^0 dOmega: a Gauss rule for sqrt(x^2 + 2 m x) e^{-x} times 26
+//    directions with octahedral group weights 1/21, 4/105, 9/280 (exact for
+//    spherical harmonics of degree <= 7).  Displacement per step
+//    delta_i = p_i / p_i^0 in sites (c dt = dx).
+// Gauss rules are computed with the Golub-Welsch method: the eigenvalues of
+// the Jacobi matrix of the weight's orthogonal polynomials are the nodes.
+#include "precompute.h"
+
+#include <cmath>
+#include <cstring>
+
+#include "../../include/rlbm.h"
+
+namespace rlbm {
+
+typedef long double ld;
+
+// ---------------------------------------------------------------------------
+// small dense linear algebra (extended precision)
+// ---------------------------------------------------------------------------
+
+// Cyclic Jacobi eigenvalue method for a symmetric n x n matrix A (row major,
+// destroyed).  Eigenvalues in ev, eigenvectors in the columns of V.
+static void jacobi_eig(int n, std::vector<ld> &A, std::vector<ld> &ev, std::vector<ld> &V) {
+  V.assign(n * n, 0.0L);
+  for (int i = 0; i < n; ++i) V[i * n + i] = 1.0L;
+  for (int sweep = 0; sweep < 100; ++sweep) {
+    ld off = 0.0L;
+    for (int i = 0; i < n; ++i)
+      for (int j = i + 1; j < n; ++j) off += A[i * n + j] * A[i * n + j];
+    if (off < 1e-60L) break;
+    for (int p = 0; p < n; ++p)
+      for (int q = p + 1; q < n; ++q) {
+        ld apq = A[p * n + q];
+        if (fabsl(apq) < 1e-300L) continue;
+        ld theta = (A[q * n + q] - A[p * n + p]) / (2.0L * apq);
+        ld t = (theta >= 0 ? 1.0L : -1.0L) / (fabsl(theta) + sqrtl(theta * theta + 1.0L));
+        ld c = 1.0L / sqrtl(t * t + 1.0L), s = t * c;
+        for (int k = 0; k < n; ++k) {   // A <- A J
+          ld akp = A[k * n + p], akq = A[k * n + q];
+          A[k * n + p] = c * akp - s * akq;
+          A[k * n + q] = s * akp + c * akq;
+        }
+        for (int k = 0; k < n; ++k) {   // A <- J^T A
+          ld apk = A[p * n + k], aqk = A[q * n + k];
+          A[p * n + k] = c * apk - s * aqk;
+          A[q * n + k] = s * apk + c * aqk;
+        }
+        for (int k = 0; k < n; ++k) {
+          ld vkp = V[k * n + p], vkq = V[k * n + q];
+          V[k * n + p] = c * vkp - s * vkq;
+          V[k * n + q] = s * vkp + c * vkq;
+        }
+      }
+  }
+  ev.resize(n);
+  for (int i = 0; i < n; ++i) ev[i] = A[i * n + i];
+}
+
+// Gauss rule from the recurrence coefficients (monic: x pi_k = pi_{k+1} + a_k pi_k + b_k pi_{k-1})
+static void golub_welsch(int n, const std::vector<ld> &a, const std::vector<ld> &b, ld mu0,
+                         std::vector<ld> &x, std::vector<ld> &w) {
+  std::vector<ld> J(n * n, 0.0L), ev, V;
+  for (int i = 0; i < n; ++i) {
+    J[i * n + i] = a[i];
+    if (i + 1 < n) J[i * n + i + 1] = J[(i + 1) * n + i] = sqrtl(b[i + 1]);
+  }
+  jacobi_eig(n, J, ev, V);
+  std::vector<int> order(n);
+  for (int i = 0; i < n; ++i) order[i] = i;
+  for (int i = 0; i < n; ++i)
+    for (int j = i + 1; j < n; ++j)
+      if (ev[order[j]] < ev[order[i]]) std::swap(order[i], order[j]);
+  x.resize(n);
+  w.resize(n);
+  for (int i = 0; i < n; ++i) {
+    x[i] = ev[order[i]];
+    w[i] = mu0 * V[0 * n + order[i]] * V[0 * n + order[i]];
+  }
+}
+
+// Gauss-Laguerre: weight x^alpha e^{-x}; a_k = 2k + alpha + 1, b_k = k (k + alpha).
+static void gauss_laguerre(int n, ld alpha, std::vector<ld> &x, std::vector<ld> &w) {
+  std::vector<ld> a(n), b(n + 1, 0.0L);
+  for (int k = 0; k < n; ++k) a[k] = 2.0L * k + alpha + 1.0L;
+  for (int k = 1; k <= n; ++k) b[k] = k * (k + alpha);
+  golub_welsch(n, a, b, tgammal(alpha + 1.0L), x, w);
+}
+
+// Gauss rule for sqrt(x^2 + 2 m x) e^{-x} on [0, inf): Stieltjes procedure on
+// a discretised measure.  With x = t^2 the integrand becomes the even,
+// analytic function 2 t^2 sqrt(t^2 + 2m) e^{-t^2} g(t^2), for which the
+// trapezoidal rule on the half line converges geometrically.
+static void gauss_radial_3d(int n, ld m, std::vector<ld> &x, std::vector<ld> &w) {
+  if (m == 0.0L) {       // weight x e^{-x}
+    gauss_laguerre(n, 1.0L, x, w);
+    return;
+  }
+  ld h = fminl(0.04L, sqrtl(2.0L * m) / 8.0L);
+  int M = (int)(14.0L / h) + 1;
+  std::vector<ld> xs(M), lam(M);
+  for (int k = 1; k <= M; ++k) {
+    ld t = k * h;
+    xs[k - 1] = t * t;
+    lam[k - 1] = h * 2.0L * t * t * sqrtl(t * t + 2.0L * m) * expl(-t * t);
+  }
+  std::vector<ld> a(n), b(n + 1, 0.0L), pim1(M, 0.0L), pi0(M, 1.0L), pi1(M);
+  ld norm_prev = 1.0L, mu0 = 0.0L;
+  for (int k = 0; k < n; ++k) {
+    ld nrm = 0.0L, xn = 0.0L;
+    for (int j = 0; j < M; ++j) {
+      nrm += lam[j] * pi0[j] * pi0[j];
+      xn += lam[j] * xs[j] * pi0[j] * pi0[j];
+    }
+    if (k == 0) mu0 = nrm;
+    a[k] = xn / nrm;
+    b[k] = (k == 0) ? nrm : nrm / norm_prev;
+    for (int j = 0; j < M; ++j) pi1[j] = (xs[j] - a[k]) * pi0[j] - (k ? b[k] : 0.0L) * pim1[j];
+    pim1.swap(pi0);
+    pi0.swap(pi1);
+    norm_prev = nrm;
+  }
+  golub_welsch(n, a, b, mu0, x, w);
+}
+
+// Printed massless order-2 rule (Sec. 5.3 example and App. H.2 table):
+// shells p^0_j and weights of the (+-3,+-4) and (+-5,0) groups.
+static const double kURShells[3] = {0.4157745567834790, 2.2942803602790417, 6.2899450829374791};
+static const double kURW34[3] = {0.0888866262411466, 0.0348147166961551, 0.0004218743543938};
+static const double kURW50[3] = {0.0, 0.0, 0.0017535654166088};
+
+int build_quadrature(int d, double m, int order, int kind, QuadHost &q, std::string &err) {
+  q = QuadHost();
+  q.d = d;
+  q.m = m;
+  q.order = order;
+  q.kind = kind;
+  if (kind == RLBM_QUAD_UR_ONLATTICE) {
+    if (d != 2 || order != 2 || m != 0.0) {
+      err = "the printed on-lattice rule is massless (zeta = 0), d = 2, order N = 2";
+      return RLBM_ERR_UNSUPPORTED;
+    }
+    q.nshell = 3;
+    q.ndir = 12;
+    for (int i = 0; i < kUR2DQ; ++i) {
+      int j = kURShell[i], k = kURDir[i];
+      double nx = kDirUR[k][0], ny = kDirUR[k][1];
+      double len = std::sqrt(nx * nx + ny * ny);   // 5
+      double wj = (nx * ny == 0.0) ? kURW50[j] : kURW34[j];
+      double p0 = kURShells[j];
+      q.p.insert(q.p.end(), {p0, p0 * nx / len, p0 * ny / len});
+      q.w.push_back(wj);
+      q.disp.insert(q.disp.end(), {nx, ny});
+    }
+    q.Q = kUR2DQ;
+    return 0;
+  }
+  if (kind != RLBM_QUAD_PRODUCT) {
+    err = "unknown quadrature kind";
+    return RLBM_ERR_INVALID_ARG;
+  }
+  if (!(m >= 0.0) || !std::isfinite(m)) {
+    err = "zeta must be finite and >= 0";
+    return RLBM_ERR_INVALID_ARG;
+  }
+  if (order < 2 || order > 3) {
+    err = "product rules are provided for orders N = 2 and 3";
+    return RLBM_ERR_UNSUPPORTED;
+  }
+  int nr = order + 1;
+  std::vector<ld> x, W;
+  if (d == 2) {
+    gauss_laguerre(nr, 0.0L, x, W);
+  } else if (d == 3) {
+    gauss_radial_3d(nr, (ld)m, x, W);
+  } else {
+    err = "d must be 2 or 3";
+    return RLBM_ERR_UNSUPPORTED;
+  }
+  ld Wsum = 0.0L;
+  for (int j = 0; j < nr; ++j) Wsum += W[j];
+  q.nshell = nr;
+  q.ndir = d == 2 ? 8 : 26;
+  for (int j = 0; j < nr; ++j) {
+    ld p0 = (ld)m + x[j];
+    ld pm = sqrtl(x[j] * x[j] + 2.0L * (ld)m * x[j]);
+    ld v = pm / p0;
+    for (int k = 0; k < q.ndir; ++k) {
+      ld n[3] = {0, 0, 0}, len = 0.0L, dw;
+      for (int a = 0; a < d; ++a) {
+        n[a] = d == 2 ? kDir2D[k][a] : kDir3D[k][a];
+        len += n[a] * n[a];
+      }
+      len = sqrtl(len);
+      if (d == 2) {
+        dw = 1.0L / 8.0L;
+      } else {
+        int nnz = (n[0] != 0) + (n[1] != 0) + (n[2] != 0);
+        dw = nnz == 1 ? 1.0L / 21.0L : (nnz == 2 ? 4.0L / 105.0L : 9.0L / 280.0L);
+      }
+      q.p.push_back((double)p0);
+      for (int a = 0; a < d; ++a) q.p.push_back((double)(pm * n[a] / len));
+      q.w.push_back((double)(W[j] / Wsum * dw));
+      for (int a = 0; a < d; ++a) q.disp.push_back((double)(v * n[a] / len));
+    }
+  }
+  q.Q = nr * q.ndir;
+  return 0;
+}
+
+// ---------------------------------------------------------------------------
+// A_n ratios (App. B): r_n = A_n / A_1 at zeta.  d = 2 through the reverse
+// Bessel polynomials theta_n; d = 3 through K_nu computed from
+// K_nu(z) = int_0^inf exp(-z cosh t) cosh(nu t) dt (trapezoidal rule).
+// ---------------------------------------------------------------------------
+static ld bessel_k(ld nu, ld z) {
+  ld tmax = acoshl(fmaxl(2.0L, 11000.0L / z + 1.0L));
+  const ld h = 0.01L;
+  ld s = 0.5L * expl(-z);
+  for (int k = 1; k * h <= tmax; ++k) {
+    ld t = k * h;
+    s += expl(-z * coshl(t)) * coshl(nu * t);
+  }
+  return s * h;
+}
+
+static void a_ratios(int d, ld zeta, ld &r0, ld &r2, ld &r3) {
+  if (d == 2) {
+    ld t1 = zeta + 1.0L;
+    r0 = 1.0L / t1;
+    r2 = (zeta * zeta + 3.0L * zeta + 3.0L) / t1;
+    r3 = (zeta * zeta * zeta + 6.0L * zeta * zeta + 15.0L * zeta + 15.0L) / t1;
+    return;
+  }
+  // d = 3: A_n/A_1 = zeta^{n-1} K_{n+1}/K_2.  With r = K_1/K_2:
+  // r0 = r/zeta, r2 = zeta r + 4 (K_3 = K_1 + 4 K_2/zeta), r3 = zeta^2 + 6 r2.
+  if (zeta == 0.0L) {
+    r0 = 0.5L;
+    r2 = 4.0L;
+    r3 = 24.0L;
+    return;
+  }
+  ld r = bessel_k(1.0L, zeta) / bessel_k(2.0L, zeta);
+  r0 = r / zeta;
+  r2 = zeta * r + 4.0L;
+  r3 = zeta * zeta + 6.0L * r2;
+}
+
+static inline ld eta(int a, int b) { return a != b ? 0.0L : (a == 0 ? 1.0L : -1.0L); }
+
+// Maxwell-Juettner moment of the monomial with tensor index tuple idx (App. B):
+// deg 0: n r0 / T; deg 1: n U^a; deg 2: n T (r2 U^a U^b - eta^ab);
+// deg 3: n T^2 (r3 U^a U^b U^c - r2 (eta^ab U^c + eta^ac U^b + eta^bc U^a)).
+static ld mj_moment(const signed char *idx, ld n, ld T, const ld *U, ld r0, ld r2, ld r3) {
+  int deg = (idx[0] >= 0) + (idx[1] >= 0) + (idx[2] >= 0);
+  if (deg == 0) return n * r0 / T;
+  if (deg == 1) return n * U[idx[0]];
+  int a = idx[0], b = idx[1];
+  if (deg == 2) return n * T * (r2 * U[a] * U[b] - eta(a, b));
+  int c = idx[2];
+  return n * T * T * (r3 * U[a] * U[b] * U[c] - r2 * (eta(a, b) * U[c] + eta(a, c) * U[b] + eta(b, c) * U[a]));
+}
+
+template <int D, int N>
+static void basis_moments_t(ld m, ld n, ld T, const ld *U, ld *M) {
+  ld r0, r2, r3;
+  a_ratios(D, m / T, r0, r2, r3);
+  for (int k = 0; k < BasisDef<D, N>::NM; ++k) M[k] = mj_moment(BasisDef<D, N>::idx[k], n, T, U, r0, r2, r3);
+}
+
+static void basis_moments_ld(int d, int order, ld m, ld n, ld T, const ld *U, ld *M) {
+  if (d == 2 && order == 2) basis_moments_t<2, 2>(m, n, T, U, M);
+  else if (d == 2 && order == 3) basis_moments_t<2, 3>(m, n, T, U, M);
+  else if (d == 3 && order == 2) basis_moments_t<3, 2>(m, n, T, U, M);
+  else basis_moments_t<3, 3>(m, n, T, U, M);
+}
+
+void basis_moments_host(int d, int order, double m, double n, double T, const double *U, double *M) {
+  ld Ul[4] = {0, 0, 0, 0}, Ml[kMaxNM];
+  for (int a = 0; a <= d; ++a) Ul[a] = U[a];
+  basis_moments_ld(d, order, m, n, T, Ul, Ml);
+  for (int k = 0; k < basis_size(d, order); ++k) M[k] = (double)Ml[k];
+}
+
+static const signed char *basis_idx(int d, int order, int k) {
+  if (d == 2 && order == 2) return BasisDef<2, 2>::idx[k];
+  if (d == 2 && order == 3) return BasisDef<2, 3>::idx[k];
+  if (d == 3 && order == 2) return BasisDef<3, 2>::idx[k];
+  return BasisDef<3, 3>::idx[k];
+}
+static int basis_ne(int d, int order) {
+  if (d == 2) return order == 2 ? BasisDef<2, 2>::NE : BasisDef<2, 3>::NE;
+  return order == 2 ? BasisDef<3, 2>::NE : BasisDef<3, 3>::NE;
+}
+
+int build_eos_fit(double m, Tables &t, std::string &err) {
+  t.cheb_n = 0;
+  if (m == 0.0) return 0;
+  const int n = 44;
+  const ld lo = logl((ld)m / 4.0L), hi = logl((ld)m * 4.0L);
+  const ld pi = 3.141592653589793238462643383279502884L;
+  ld fk[n];
+  for (int k = 0; k < n; ++k) {
+    ld s = cosl(pi * (k + 0.5L) / n);
+    ld z = expl(0.5L * (hi + lo) + 0.5L * (hi - lo) * s);
+    fk[k] = bessel_k(1.0L, z) / bessel_k(2.0L, z);
+  }
+  for (int j = 0; j < n; ++j) {
+    ld c = 0.0L;
+    for (int k = 0; k < n; ++k) c += fk[k] * cosl(pi * j * (k + 0.5L) / n);
+    c *= 2.0L / n;
+    if (j == 0) c *= 0.5L;
+    t.cheb[j] = (double)c;
+  }
+  t.cheb_n = n;
+  t.cheb_lo = (double)lo;
+  t.cheb_hi = (double)hi;
+  // verify the fit between the nodes
+  for (int k = 0; k <= 64; ++k) {
+    ld s = -1.0L + 2.0L * k / 64.0L;
+    ld z = expl(0.5L * (hi + lo) + 0.5L * (hi - lo) * s);
+    ld ref = bessel_k(1.0L, z) / bessel_k(2.0L, z);
+    ld b1 = 0.0L, b2 = 0.0L;
+    for (int j = n - 1; j >= 1; --j) {
+      ld b0 = 2.0L * s * b1 - b2 + (ld)t.cheb[j];
+      b2 = b1;
+      b1 = b0;
+    }
+    ld got = s * b1 - b2 + (ld)t.cheb[0];
+    if (fabsl(got - ref) > 4e-16L * fabsl(ref)) {
+      err = "equation-of-state fit failed";
+      return RLBM_ERR_QUADRATURE;
+    }
+  }
+  return 0;
+}
+
+// ---------------------------------------------------------------------------
+// Tables
+// ---------------------------------------------------------------------------
+int build_tables(const QuadHost &q, double tau, double n_ref, int storage, const int64_t extent[3],
+                 const int bc[3], Tables &t, std::string &err) {
+  std::memset(&t, 0, sizeof(Tables));
+  const int d = q.d, Q = q.Q, D1 = d + 1;
+  const int NM = basis_size(d, q.order), NE = basis_ne(d, q.order), NO = NM - NE;
+  if (Q > kMaxQ || (Q & 1)) {
+    err = "internal: population count";
+    return RLBM_ERR_UNSUPPORTED;
+  }
+  t.nx = (int32_t)extent[0];
+  t.ny = (int32_t)extent[1];
+  t.nz = (int32_t)(d == 3 ? extent[2] : 1);
+  for (int a = 0; a < 3; ++a) t.open[a] = (a < d) ? (bc[a] == RLBM_OPEN) : 0;
+  t.storage = storage;
+  t.sites = (int64_t)t.nx * t.ny * t.nz;
+  t.m = q.m;
+  t.tau = tau;
+  t.inv_tau = 1.0 / tau;
+  t.n_ref = n_ref;
+
+  // Gram matrix of the basis under the discrete inner product, G = sum_i w_i phi phi^T
+  std::vector<ld> Phi(Q * NM);
+  for (int i = 0; i < Q; ++i)
+    for (int k = 0; k < NM; ++k) {
+      const signed char *idx = basis_idx(d, q.order, k);
+      ld v = 1.0L;
+      for (int s = 0; s < 3; ++s)
+        if (idx[s] >= 0) v *= (ld)q.p[i * D1 + idx[s]];
+      Phi[i * NM + k] = v;
+    }
+  std::vector<ld> G(NM * NM, 0.0L);
+  for (int i = 0; i < Q; ++i)
+    for (int a = 0; a < NM; ++a)
+      for (int b = 0; b < NM; ++b) G[a * NM + b] += (ld)q.w[i] * Phi[i * NM + a] * Phi[i * NM + b];
+  // Cholesky G = L L^T
+  std::vector<ld> L(NM * NM, 0.0L);
+  for (int j = 0; j < NM; ++j) {
+    ld s = G[j * NM + j];
+    for (int k = 0; k < j; ++k) s -= L[j * NM + k] * L[j * NM + k];
+    if (!(s > 0.0L)) {
+      err = "Gram matrix of the basis is not positive definite: the quadrature cannot carry order N";
+      return RLBM_ERR_QUADRATURE;
+    }
+    L[j * NM + j] = sqrtl(s);
+    for (int i = j + 1; i < NM; ++i) {
+      ld r = G[i * NM + j];
+      for (int k = 0; k < j; ++k) r -= L[i * NM + k] * L[j * NM + k];
+      L[i * NM + j] = r / L[j * NM + j];
+    }
+  }
+  // R[i][k] = w_i (G^{-1} phi(p_i))_k : f^eq_i = sum_k R[i][k] M_k reproduces every basis moment.
+  std::vector<ld> R(Q * NM);
+  for (int i = 0; i < Q; ++i) {
+    std::vector<ld> y(NM);
+    for (int a = 0; a < NM; ++a) {
+      ld s = Phi[i * NM + a];
+      for (int k = 0; k < a; ++k) s -= L[a * NM + k] * y[k];
+      y[a] = s / L[a * NM + a];
+    }
+    for (int a = NM - 1; a >= 0; --a) {
+      ld s = y[a];
+      for (int k = a + 1; k < NM; ++k) s -= L[k * NM + a] * R[i * NM + k];
+      R[i * NM + a] = s / L[a * NM + a];
+    }
+    for (int a = 0; a < NM; ++a) R[i * NM + a] *= (ld)q.w[i];
+  }
+  // reproduction check: sum_i R[i][k] phi_l(p_i) = delta_kl
+  ld worst = 0.0L;
+  for (int k = 0; k < NM; ++k)
+    for (int l = 0; l < NM; ++l) {
+      ld s = 0.0L;
+      for (int i = 0; i < Q; ++i) s += R[i * NM + k] * Phi[i * NM + l];
+      worst = fmaxl(worst, fabsl(s - (k == l ? 1.0L : 0.0L)));
+    }
+  if (worst > 1e-9L) {
+    err = "projection does not reproduce the basis moments";
+    return RLBM_ERR_QUADRATURE;
+  }
+  // antipodal structure: R[2pr+1] = +-R[2pr] (even / odd basis part)
+  for (int pr = 0; pr < Q / 2; ++pr) {
+    int i = 2 * pr, j = i + 1;
+    for (int a = 1; a < D1; ++a)
+      if (std::fabs(q.p[i * D1 + a] + q.p[j * D1 + a]) > 1e-12 * (1.0 + std::fabs(q.p[i * D1 + a]))) {
+        err = "internal: populations are not in antipodal pairs";
+        return RLBM_ERR_QUADRATURE;
+      }
+    for (int k = 0; k < NM; ++k) {
+      ld s = k < NE ? 1.0L : -1.0L;
+      if (fabsl(R[j * NM + k] - s * R[i * NM + k]) > 1e-12L * (1.0L + fabsl(R[i * NM + k]))) {
+        err = "internal: projection rows break antipodal symmetry";
+        return RLBM_ERR_QUADRATURE;
+      }
+    }
+    const double *p = &q.p[i * D1];
+    for (int a = 0; a < d; ++a) {
+      t.c[pr][a] = p[1 + a] / p[0];
+      t.cf[pr][a] = (float)t.c[pr][a];
+    }
+    // even moments: N^0 <- p0, T^00 <- p0^2, T^ab <- p^a p^b (a <= b); odd: N^a <- p^a, T^0a <- p0 p^a
+    int e = 0;
+    t.mom_e[pr][e++] = p[0];
+    t.mom_e[pr][e++] = p[0] * p[0];
+    for (int a = 1; a <= d; ++a)
+      for (int b = a; b <= d; ++b) t.mom_e[pr][e++] = p[a] * p[b];
+    int o = 0;
+    for (int a = 1; a <= d; ++a) t.mom_o[pr][o++] = p[a];
+    for (int a = 1; a <= d; ++a) t.mom_o[pr][o++] = p[0] * p[a];
+    for (int k = 0; k < e; ++k) t.mom_ef[pr][k] = (float)t.mom_e[pr][k];
+    for (int k = 0; k < o; ++k) t.mom_of[pr][k] = (float)t.mom_o[pr][k];
+    for (int k = 0; k < NE; ++k) {
+      t.Re[pr][k] = (double)R[i * NM + k];
+      t.Ref[pr][k] = (float)t.Re[pr][k];
+    }
+    for (int k = 0; k < NO; ++k) {
+      t.Ro[pr][k] = (double)R[i * NM + NE + k];
+      t.Rof[pr][k] = (float)t.Ro[pr][k];
+    }
+  }
+  // interpolation weights: for each non-zero direction component (x, y, z
+  // order) a tap bit; sign + : offsets {-1, 0} weights {|d|, 1-|d|};
+  // sign - : offsets {0, +1} weights {1-|d|, |d|}.
+  if (q.kind == RLBM_QUAD_PRODUCT) {
+    for (int i = 0; i < Q; ++i) {
+      int k = i % q.ndir;
+      int sgn[3], nz = 0, axes[3];
+      double mag[3];
+      for (int a = 0; a < d; ++a) {
+        sgn[a] = d == 2 ? kDir2D[k][a] : kDir3D[k][a];
+        mag[a] = std::fabs(q.disp[i * d + a]);
+        if (sgn[a] != 0) axes[nz++] = a;
+        if (mag[a] > 1.0 + 1e-15) {
+          err = "internal: displacement beyond one site";
+          return RLBM_ERR_QUADRATURE;
+        }
+      }
+      for (int tap = 0; tap < (1 << nz); ++tap) {
+        double wgt = 1.0;
+        for (int bI = 0; bI < nz; ++bI) {
+          int a = axes[bI], c = (tap >> bI) & 1;
+          double mg = std::fmin(mag[a], 1.0);
+          if (sgn[a] > 0) wgt *= c ? 1.0 - mg : mg;
+          else wgt *= c ? mg : 1.0 - mg;
+        }
+        t.tapw[i][tap] = wgt;
+        t.tapwf[i][tap] = (float)wgt;
+      }
+    }
+  }
+  // reference state f^ref = equilibrium at (n_ref, T = 1, U = 0) and its moments
+  {
+    ld U[4] = {1.0L, 0.0L, 0.0L, 0.0L}, M[kMaxNM];
+    basis_moments_ld(d, q.order, (ld)q.m, (ld)n_ref, 1.0L, U, M);
+    for (int k = 0; k < NM; ++k) t.Mref[k] = (double)M[k];
+    ld Nr[4] = {0, 0, 0, 0}, Tr[4][4] = {{0}};
+    for (int i = 0; i < Q; ++i) {
+      ld f = 0.0L;
+      for (int k = 0; k < NM; ++k) f += R[i * NM + k] * M[k];
+      t.fref[i] = (double)f;
+      for (int a = 0; a < D1; ++a) {
+        Nr[a] += f * (ld)q.p[i * D1 + a];
+        for (int b = 0; b < D1; ++b) Tr[a][b] += f * (ld)q.p[i * D1 + a] * (ld)q.p[i * D1 + b];
+      }
+    }
+    int s = 0;
+    for (int a = 0; a < D1; ++a) {
+      t.Nref[a] = (double)Nr[a];
+      for (int b = a; b < D1; ++b) t.Tref[s++] = (double)Tr[a][b];
+    }
+  }
+  return 0;
+}
+
+}  // namespace rlbm

@@ -1,0 +1,173 @@
+// rlbm_defs.h -- compile-time descriptions shared by the host precompute and
+// the HIP kernels of the RLBM library: stencils (direction sets and
+// population order), the polynomial basis used for the projected equilibrium,
+// and the layout of the per-lattice constant tables in device memory.
+#pragma once
+#include <cstdint>
+
+#ifndef RLBM_HD
+#if defined(__HIPCC__)
+#define RLBM_HD __host__ __device__
+#else
+#define RLBM_HD
+#endif
+#endif
+
+namespace rlbm {
+
+enum StencilId : int { ST_UR2D = 0, ST_PROD2D = 1, ST_PROD3D = 2 };
+
+// ---------------------------------------------------------------------------
+// Direction sets.  Antipodal directions are adjacent (k, k+1 for even k).
+// ---------------------------------------------------------------------------
+
+// 2D product rule: unit vectors along these integer directions.
+constexpr int kDir2D[8][2] = {{1, 0}, {-1, 0}, {0, 1}, {0, -1}, {1, 1}, {-1, -1}, {-1, 1}, {1, -1}};
+
+// 3D product rule: 6 axis, 12 edge and 8 corner directions (octahedral symmetry).
+constexpr int kDir3D[26][3] = {
+    {1, 0, 0},  {-1, 0, 0},  {0, 1, 0},  {0, -1, 0}, {0, 0, 1},   {0, 0, -1},
+    {1, 1, 0},  {-1, -1, 0}, {1, -1, 0}, {-1, 1, 0}, {1, 0, 1},   {-1, 0, -1},
+    {1, 0, -1}, {-1, 0, 1},  {0, 1, 1},  {0, -1, -1}, {0, 1, -1}, {0, -1, 1},
+    {1, 1, 1},  {-1, -1, -1}, {1, 1, -1}, {-1, -1, 1}, {1, -1, 1}, {-1, 1, -1},
+    {-1, 1, 1}, {1, -1, -1}};
+
+// Printed massless (2+1)-d order-2 rule (Sec. 5.3 worked example, App. H.2):
+// stencil (+-3,+-4)_FS U (+-5,0)_FS; populations in shell-major order with the
+// zero-weight (+-5,0) members of shells 1 and 2 dropped.
+constexpr int kDirUR[12][2] = {{3, 4},  {-3, -4}, {-3, 4}, {3, -4}, {4, 3},  {-4, -3},
+                               {-4, 3}, {4, -3},  {5, 0},  {-5, 0}, {0, 5},  {0, -5}};
+constexpr int kUR2DQ = 28;
+// population -> (shell, direction) for the printed rule
+constexpr int kURShell[kUR2DQ] = {0, 0, 0, 0, 0, 0, 0, 0, 1, 1, 1, 1, 1, 1, 1, 1,
+                                  2, 2, 2, 2, 2, 2, 2, 2, 2, 2, 2, 2};
+constexpr int kURDir[kUR2DQ] = {0, 1, 2, 3, 4, 5, 6, 7, 0, 1, 2, 3, 4, 5, 6, 7,
+                                0, 1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 11};
+
+template <int SID, int KR>
+struct Stencil;
+
+template <int KR>
+struct Stencil<ST_PROD2D, KR> {
+  static constexpr int D = 2, NDIR = 8, Q = KR * 8, NSHELL = KR;
+  static constexpr bool ONLAT = false;
+  RLBM_HD static constexpr int dir(int i, int a) { return kDir2D[i % 8][a]; }
+};
+
+template <int KR>
+struct Stencil<ST_PROD3D, KR> {
+  static constexpr int D = 3, NDIR = 26, Q = KR * 26, NSHELL = KR;
+  static constexpr bool ONLAT = false;
+  RLBM_HD static constexpr int dir(int i, int a) { return kDir3D[i % 26][a]; }
+};
+
+template <>
+struct Stencil<ST_UR2D, 3> {
+  static constexpr int D = 2, NDIR = 12, Q = kUR2DQ, NSHELL = 3;
+  static constexpr bool ONLAT = true;
+  // integer displacement of population i (sites per step)
+  RLBM_HD static constexpr int dir(int i, int a) { return kDirUR[kURDir[i]][a]; }
+};
+
+// Number of interpolation taps of population i: 2^(number of non-zero direction components).
+template <class ST>
+RLBM_HD constexpr int n_taps(int i) {
+  if (ST::ONLAT) return 1;
+  int nz = 0;
+  for (int a = 0; a < ST::D; ++a) nz += ST::dir(i, a) != 0;
+  return 1 << nz;
+}
+
+// ---------------------------------------------------------------------------
+// Polynomial basis on the mass shell: monomials p0^a p1^e1 p2^e2 p3^e3 with
+// a in {0, 1} and total degree <= N (p0^2 = m^2 + |p|^2 removes the rest).
+// Each entry is the tensor index tuple of the monomial (0 = time), unused
+// slots -1.  Even spatial parity first (NE entries), then odd (NO entries):
+// an antipodal pair p -> (p0, -p) keeps even monomials and flips odd ones.
+// ---------------------------------------------------------------------------
+template <int D, int N>
+struct BasisDef;
+
+template <>
+struct BasisDef<2, 2> {
+  static constexpr int NE = 5, NO = 4, NM = 9;
+  static constexpr signed char idx[NM][3] = {
+      {-1, -1, -1}, {0, -1, -1}, {1, 1, -1}, {1, 2, -1}, {2, 2, -1},   // even
+      {1, -1, -1},  {2, -1, -1}, {0, 1, -1}, {0, 2, -1}};              // odd
+};
+template <>
+struct BasisDef<2, 3> {
+  static constexpr int NE = 8, NO = 8, NM = 16;
+  static constexpr signed char idx[NM][3] = {
+      {-1, -1, -1}, {0, -1, -1}, {1, 1, -1}, {1, 2, -1}, {2, 2, -1}, {0, 1, 1}, {0, 1, 2}, {0, 2, 2},
+      {1, -1, -1},  {2, -1, -1}, {0, 1, -1}, {0, 2, -1}, {1, 1, 1},  {1, 1, 2}, {1, 2, 2}, {2, 2, 2}};
+};
+template <>
+struct BasisDef<3, 2> {
+  static constexpr int NE = 8, NO = 6, NM = 14;
+  static constexpr signed char idx[NM][3] = {
+      {-1, -1, -1}, {0, -1, -1}, {1, 1, -1}, {1, 2, -1}, {1, 3, -1}, {2, 2, -1}, {2, 3, -1}, {3, 3, -1},
+      {1, -1, -1},  {2, -1, -1}, {3, -1, -1}, {0, 1, -1}, {0, 2, -1}, {0, 3, -1}};
+};
+template <>
+struct BasisDef<3, 3> {
+  static constexpr int NE = 14, NO = 16, NM = 30;
+  static constexpr signed char idx[NM][3] = {
+      // even: 1, p0, p_a p_b (6), p0 p_a p_b (6)
+      {-1, -1, -1}, {0, -1, -1}, {1, 1, -1}, {1, 2, -1}, {1, 3, -1}, {2, 2, -1}, {2, 3, -1}, {3, 3, -1},
+      {0, 1, 1}, {0, 1, 2}, {0, 1, 3}, {0, 2, 2}, {0, 2, 3}, {0, 3, 3},
+      // odd: p_a (3), p0 p_a (3), p_a p_b p_c (10)
+      {1, -1, -1}, {2, -1, -1}, {3, -1, -1}, {0, 1, -1}, {0, 2, -1}, {0, 3, -1},
+      {1, 1, 1}, {1, 1, 2}, {1, 1, 3}, {1, 2, 2}, {1, 2, 3}, {1, 3, 3}, {2, 2, 2}, {2, 2, 3}, {2, 3, 3},
+      {3, 3, 3}};
+};
+
+RLBM_HD constexpr int basis_size(int D, int N) {
+  return D == 2 ? (N + 1) * (N + 1) : (N + 1) * (N + 2) * (2 * N + 3) / 6;
+}
+
+// ---------------------------------------------------------------------------
+// Per-lattice constant tables (device memory).  Sized for the largest
+// stencil; kernels index only what their stencil uses.
+// ---------------------------------------------------------------------------
+constexpr int kMaxQ = 104;
+constexpr int kMaxPairs = kMaxQ / 2;
+constexpr int kMaxNE = 14, kMaxNO = 16, kMaxNM = 30;
+constexpr int kMaxShell = 4;
+constexpr int kNMom3 = 14;   // 4 (N^a) + 10 (T^ab) in 3D; 2D uses 3 + 6
+
+struct Tables {
+  // geometry and physics
+  int32_t nx, ny, nz, pad0;
+  int32_t open[3], storage;     // open[a]: zero-gradient boundary on axis a
+  int64_t sites;                // nx * ny * nz
+  double m;                     // reduced mass zeta = m/T0
+  double tau;                   // relaxation time (when no field)
+  double inv_tau;
+  double n_ref;
+  // EOS helper for d = 3: Chebyshev fit of r(z) = K1(z)/K2(z) on [z_lo, z_hi]
+  double cheb_lo, cheb_hi;
+  double cheb[48];
+  int32_t cheb_n, pad1;
+  // per pair of antipodal populations (even member 2pr):
+  double c[kMaxPairs][3];       // velocity p^a / p^0
+  double mom_e[kMaxPairs][8];   // even moment weights: p0, p0^2, p^a p^b (upper triangle)
+  double mom_o[kMaxPairs][6];   // odd moment weights: p^a, p0 p^a
+  double Re[kMaxPairs][kMaxNE]; // projection rows, even basis part
+  double Ro[kMaxPairs][kMaxNO]; // projection rows, odd basis part
+  float Ref[kMaxPairs][kMaxNE]; // float copies for the F32_DEV path
+  float Rof[kMaxPairs][kMaxNO];
+  float cf[kMaxPairs][3];
+  float mom_ef[kMaxPairs][8];
+  float mom_of[kMaxPairs][6];
+  // per population
+  double tapw[kMaxQ][8];        // interpolation weights in the stencil's tap order
+  float tapwf[kMaxQ][8];
+  double fref[kMaxQ];           // reference populations f^ref (F32_DEV)
+  // reference moments (F32_DEV): N^a, T^ab upper triangle, basis moments
+  double Nref[4];
+  double Tref[10];
+  double Mref[kMaxNM];
+};
+
+}  // namespace rlbm

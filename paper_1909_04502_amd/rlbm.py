@@ -1,0 +1,233 @@
+"""ctypes binding of the RLBM C ABI (``include/rlbm.h``).
+
+Argument marshalling only: every step of the update runs in the HIP kernels of
+``librlbm.so``.  PyTorch provides device memory and the current stream; the
+library is loaded after torch so that both use the same HIP runtime.  A
+missing library is an error (there is no fallback path).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from ctypes import POINTER, Structure, c_char_p, c_double, c_int32, c_int64, c_void_p
+
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "librlbm.so")
+
+OK, ERR_INVALID_ARG, ERR_UNSUPPORTED, ERR_QUADRATURE, ERR_DEVICE, ERR_NONPHYSICAL = range(6)
+KIND = {"ur_onlattice": 0, "product": 1}
+STORAGE = {"f64": 0, "f32dev": 1}
+BC = {"periodic": 0, "open": 1}
+
+
+class Model(Structure):
+    _fields_ = [("d", c_int32), ("order", c_int32), ("kind", c_int32), ("pad_", c_int32), ("zeta", c_double)]
+
+
+class Config(Structure):
+    _fields_ = [("model", Model), ("extent", c_int64 * 3), ("bc", c_int32 * 3), ("storage", c_int32),
+                ("tau", c_double), ("tau_field", c_void_p), ("n_ref", c_double)]
+
+
+class Info(Structure):
+    _fields_ = [("Q", c_int32), ("n_basis", c_int32), ("sites", c_int64), ("state_bytes", c_int64),
+                ("elem_bytes", c_int32), ("on_lattice", c_int32)]
+
+
+class Fields(Structure):
+    _fields_ = [("n", c_void_p), ("eps", c_void_p), ("T", c_void_p), ("U", c_void_p)]
+
+
+class RLBMError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"rlbm status {status}: {msg}")
+        self.status = status
+
+
+_lib = None
+
+
+def _check_single_hip_runtime():
+    """Refuse to run with two HIP runtimes mapped (ours and torch's must be the same object)."""
+    paths = set()
+    try:
+        with open("/proc/self/maps") as fh:
+            for line in fh:
+                if "libamdhip64" in line:
+                    paths.add(os.path.realpath(line.split()[-1]))
+    except OSError:
+        return
+    if len(paths) > 1:
+        raise RuntimeError("two HIP runtimes are loaded: " + ", ".join(sorted(paths)))
+
+
+def lib():
+    """Load librlbm.so (built in place by paper_1909_04502_amd.build)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is not built; run paper_1909_04502_amd.build.build()")
+    L = ctypes.CDLL(LIB_PATH)
+    st = c_int32
+    L.rlbm_status_string.restype = c_char_p
+    L.rlbm_status_string.argtypes = [st]
+    L.rlbm_last_error.restype = c_char_p
+    L.rlbm_last_error.argtypes = []
+    L.rlbm_quadrature_build.restype = st
+    L.rlbm_quadrature_build.argtypes = [POINTER(Model), POINTER(c_int32), c_void_p, c_void_p, c_void_p]
+    L.rlbm_create.restype = st
+    L.rlbm_create.argtypes = [POINTER(Config), POINTER(c_void_p)]
+    L.rlbm_destroy.restype = st
+    L.rlbm_destroy.argtypes = [c_void_p]
+    L.rlbm_get_info.restype = st
+    L.rlbm_get_info.argtypes = [c_void_p, POINTER(Info)]
+    L.rlbm_init.restype = st
+    L.rlbm_init.argtypes = [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_double, c_void_p,
+                            POINTER(Fields), c_void_p]
+    L.rlbm_step.restype = st
+    L.rlbm_step.argtypes = [c_void_p, c_void_p, c_void_p, c_int32, POINTER(Fields), c_void_p]
+    L.rlbm_moments.restype = st
+    L.rlbm_moments.argtypes = [c_void_p, c_void_p, POINTER(Fields), c_void_p]
+    L.rlbm_sync.restype = st
+    L.rlbm_sync.argtypes = [c_void_p, c_void_p]
+    _lib = L
+    _check_single_hip_runtime()
+    return L
+
+
+def _check(status):
+    if status != OK:
+        L = lib()
+        raise RLBMError(status, L.rlbm_last_error().decode() or L.rlbm_status_string(status).decode())
+
+
+def _model(d, zeta, order, kind):
+    return Model(d=d, order=order, kind=KIND[kind] if isinstance(kind, str) else int(kind), pad_=0, zeta=float(zeta))
+
+
+def quadrature_build(d: int, zeta: float, order: int, kind="product"):
+    """Host-side quadrature of the library: (p [Q, d+1], w [Q], disp [Q, d]) as float64 CPU tensors."""
+    L = lib()
+    m = _model(d, zeta, order, kind)
+    Q = c_int32(0)
+    _check(L.rlbm_quadrature_build(ctypes.byref(m), ctypes.byref(Q), None, None, None))
+    p = torch.empty((Q.value, d + 1), dtype=torch.float64)
+    w = torch.empty((Q.value,), dtype=torch.float64)
+    disp = torch.empty((Q.value, d), dtype=torch.float64)
+    _check(L.rlbm_quadrature_build(ctypes.byref(m), ctypes.byref(Q), p.data_ptr(), w.data_ptr(), disp.data_ptr()))
+    return p, w, disp
+
+
+def _stream():
+    return c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t):
+    return None if t is None else c_void_p(t.data_ptr())
+
+
+class Lattice:
+    """One lattice: handle of the C ABI plus the torch-side shapes."""
+
+    def __init__(self, d=2, zeta=1.0, order=3, kind="product", extent=(64, 64), bc=None, storage="f64",
+                 tau=0.8, tau_field=None, n_ref=1.0):
+        L = lib()
+        self.d = d
+        self.extent = tuple(int(e) for e in extent)
+        if bc is None:
+            bc = ("periodic",) * d
+        self.storage = storage
+        self.dtype = torch.float64 if storage == "f64" else torch.float32
+        self.grid_shape = tuple(reversed(self.extent))
+        if tau_field is not None:
+            tau_field = tau_field.to(device="cuda", dtype=self.dtype).contiguous()
+            assert tuple(tau_field.shape) == self.grid_shape
+        self.tau_field = tau_field          # kept alive: the handle stores its pointer
+        cfg = Config()
+        cfg.model = _model(d, zeta, order, kind)
+        ext = list(self.extent) + [1] * (3 - d)
+        for a in range(3):
+            cfg.extent[a] = ext[a]
+            cfg.bc[a] = BC[bc[a]] if a < d else 0
+        cfg.storage = STORAGE[storage]
+        cfg.tau = float(tau)
+        cfg.tau_field = tau_field.data_ptr() if tau_field is not None else None
+        cfg.n_ref = float(n_ref)
+        self.cfg = cfg
+        h = c_void_p()
+        _check(L.rlbm_create(ctypes.byref(cfg), ctypes.byref(h)))
+        self.h = h
+        info = Info()
+        _check(L.rlbm_get_info(h, ctypes.byref(info)))
+        self.Q = info.Q
+        self.n_basis = info.n_basis
+        self.sites = info.sites
+        self.on_lattice = bool(info.on_lattice)
+
+    def __del__(self):
+        h = getattr(self, "h", None)
+        if h is not None and h.value is not None and _lib is not None:
+            _lib.rlbm_destroy(h)
+            self.h = None
+
+    # ------------------------------------------------------------------
+    def new_state(self):
+        return torch.empty((self.Q,) + self.grid_shape, dtype=self.dtype, device="cuda")
+
+    def new_fields(self):
+        g = self.grid_shape
+        dev = "cuda"
+        return {"n": torch.empty(g, dtype=torch.float64, device=dev),
+                "eps": torch.empty(g, dtype=torch.float64, device=dev),
+                "T": torch.empty(g, dtype=torch.float64, device=dev),
+                "U": torch.empty((self.d + 1,) + g, dtype=torch.float64, device=dev)}
+
+    @staticmethod
+    def _fields_struct(fd):
+        if fd is None:
+            return None
+        return Fields(n=fd["n"].data_ptr(), eps=fd["eps"].data_ptr(), T=fd["T"].data_ptr(), U=fd["U"].data_ptr())
+
+    def _dev64(self, t, shape):
+        t = torch.as_tensor(t, dtype=torch.float64).to("cuda").contiguous()
+        assert tuple(t.shape) == tuple(shape), (t.shape, shape)
+        return t
+
+    def init(self, n0, T0, u0, noise=None, amp=0.0, out=None, want_fields=False):
+        """Post-collision state f*(x, 0) from the initial fields (see rlbm_init)."""
+        g = self.grid_shape
+        n0 = self._dev64(n0, g)
+        T0 = self._dev64(T0, g)
+        u0 = self._dev64(u0, (self.d,) + g)
+        if noise is not None:
+            noise = self._dev64(noise, (self.Q,) + g)
+        out = self.new_state() if out is None else out
+        fd = self.new_fields() if want_fields else None
+        fs = self._fields_struct(fd)
+        _check(lib().rlbm_init(self.h, _ptr(n0), _ptr(T0), _ptr(u0), _ptr(noise), float(amp), _ptr(out),
+                               ctypes.byref(fs) if fs is not None else None, _stream()))
+        self._keep = (n0, T0, u0, noise)
+        return (out, fd) if want_fields else out
+
+    def step(self, f_a, f_b, nsteps, want_last=False):
+        """Advance nsteps; returns the buffer holding the result (and the last fields)."""
+        assert f_a.dtype == self.dtype and f_b.dtype == self.dtype
+        fd = self.new_fields() if want_last else None
+        fs = self._fields_struct(fd)
+        _check(lib().rlbm_step(self.h, _ptr(f_a), _ptr(f_b), int(nsteps),
+                               ctypes.byref(fs) if fs is not None else None, _stream()))
+        res = f_b if nsteps % 2 == 1 else f_a
+        return (res, fd) if want_last else res
+
+    def moments(self, f):
+        """Macroscopic fields of the streamed populations of state f."""
+        fd = self.new_fields()
+        fs = self._fields_struct(fd)
+        _check(lib().rlbm_moments(self.h, _ptr(f), ctypes.byref(fs), _stream()))
+        return fd
+
+    def sync(self):
+        _check(lib().rlbm_sync(self.h, _stream()))

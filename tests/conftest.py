@@ -27,3 +27,13 @@ def pytest_collection_modifyitems(config, items):
     for item in items:
         if "gpu" in item.keywords:
             item.add_marker(skip)
+
+
+@pytest.fixture(scope="session")
+def rlbm_lib():
+    """The built HIP library (built in place if it is missing)."""
+    from paper_1909_04502_amd import build as b
+    if not os.path.exists(b.LIB):
+        b.build()
+    from paper_1909_04502_amd import rlbm
+    return rlbm.lib()

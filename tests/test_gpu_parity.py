@@ -1,0 +1,220 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 CPU oracle.
+
+Bar (max-normalised error, e = max|gpu - oracle| / max|oracle|): 1e-12 for
+double storage; 1e-5 on n, eps, U for the float-deviation storage.
+
+State convention (see include/rlbm.h): a buffer holds post-collision
+populations f*.  The oracle produces the same sequence as
+f*_0 = C(f_0), f*_k = C(S(f*_{k-1})), and rlbm_moments(f*) = macro(S(f*)).
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import workloads as W
+from oracle import lattice as OL
+from oracle import quadrature as qd
+
+pytestmark = pytest.mark.gpu
+
+FP64_TOL = 1e-12
+F32_TOL = 1e-5
+
+
+def oracle_quad(d, zeta, order, kind):
+    if kind == "ur_onlattice":
+        return qd.ur_onlattice_2d()
+    return qd.product_2d(zeta, order) if d == 2 else qd.product_3d(zeta, order)
+
+
+def rel(a, b):
+    a = a.detach().cpu().to(torch.float64)
+    b = b.detach().cpu().to(torch.float64)
+    return ((a - b).abs().max() / b.abs().max()).item()
+
+
+# name: (d, zeta, order, kind, extent, bc, tau, u0, density sigma, population-noise amp)
+CASES = {
+    "c1_ur_64": (2, 0.0, 2, "ur_onlattice", (64, 64), ("periodic", "periodic"), 0.9, 0.01, 0.0, 1e-6),
+    "c2_ragged": (2, 1.0, 3, "product", (96, 70), ("periodic", "periodic"), 0.8, 0.1, 1e-3, 0.0),
+    "n2_open": (2, 2.5, 2, "product", (33, 17), ("open", "periodic"), 1.3, 0.08, 1e-3, 1e-3),
+    "m5": (2, 5.0, 3, "product", (40, 24), ("periodic", "open"), 0.7, 0.05, 0.0, 1e-3),
+    "m0_product": (2, 0.0, 3, "product", (66, 9), ("periodic", "periodic"), 1.0, 0.1, 0.0, 0.0),
+}
+
+
+def setup_case(name, storage="f64"):
+    from paper_1909_04502_amd import rlbm as R
+    d, zeta, order, kind, ext, bc, tau, u0, sig, amp = CASES[name]
+    nx, ny = ext
+    n, T, u = W.taylor_green_2d(nx, ny, u0, density_sigma=sig, seed=2)
+    gl = R.Lattice(d=d, zeta=zeta, order=order, kind=kind, extent=ext, bc=bc, storage=storage, tau=tau)
+    xi = W.population_noise(gl.Q, (ny, nx), seed=1) if amp else None
+    ol = OL.Lattice(oracle_quad(d, zeta, order, kind), tau, ext, bc=bc)
+    tens = [torch.tensor(a) for a in (n, T, u)] + [torch.tensor(xi) if xi is not None else None, amp]
+    return gl, ol, tens
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_init_parity(name):
+    print(f"[case] init {name}", flush=True)
+    gl, ol, (n, T, u, xi, amp) = setup_case(name)
+    f0, fields0 = gl.init(n, T, u, xi, amp, want_fields=True)
+    gl.sync()
+    f0_ref = ol.init(n, T, u, xi, amp)
+    fs_ref = ol.collide(f0_ref)
+    assert rel(f0, fs_ref) < FP64_TOL
+    mac = ol.macro(f0_ref)
+    for k in ("n", "eps", "T"):
+        assert rel(fields0[k], mac[k]) < FP64_TOL, k
+    for a in range(3):
+        assert rel(fields0["U"][a], mac["U"][a]) < FP64_TOL
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_step_parity(name):
+    print(f"[case] steps {name}", flush=True)
+    gl, ol, (n, T, u, xi, amp) = setup_case(name)
+    nsteps = 7
+    fa = gl.init(n, T, u, xi, amp)
+    fb = gl.new_state()
+    res, last = gl.step(fa, fb, nsteps, want_last=True)
+    mom = gl.moments(res)
+    gl.sync()
+    fs = ol.collide(ol.init(n, T, u, xi, amp))
+    for _ in range(nsteps - 1):
+        fs = ol.collide(ol.stream(fs))
+    pre = ol.stream(fs)                       # pre-collision state of the final step
+    last_ref = ol.macro(pre)
+    fs = ol.collide(pre)
+    assert rel(res, fs) < FP64_TOL
+    next_ref = ol.macro(ol.stream(fs))
+    for k in ("n", "eps", "T"):
+        assert rel(last[k], last_ref[k]) < FP64_TOL, k
+        assert rel(mom[k], next_ref[k]) < FP64_TOL, k
+    for a in range(3):
+        if last_ref["U"][a].abs().max() > 0:
+            assert rel(last["U"][a], last_ref["U"][a]) < FP64_TOL
+            assert rel(mom["U"][a], next_ref["U"][a]) < FP64_TOL
+
+
+@pytest.mark.parametrize("name", ["c2_ragged", "n2_open"])
+def test_f32_deviation_storage(name):
+    """Float deviations from f^ref with double eigenproblem / EOS: macro fields within 1e-5 after 40 steps."""
+    print(f"[case] f32dev {name}", flush=True)
+    gl, ol, (n, T, u, xi, amp) = setup_case(name, storage="f32dev")
+    nsteps = 40
+    fa = gl.init(n, T, u, xi, amp)
+    fb = gl.new_state()
+    res = gl.step(fa, fb, nsteps)
+    mom = gl.moments(res)
+    gl.sync()
+    fs = ol.collide(ol.init(n, T, u, xi, amp))
+    for _ in range(nsteps):
+        fs = ol.collide(ol.stream(fs))
+    ref = ol.macro(ol.stream(fs))
+    errs = {k: rel(mom[k], ref[k]) for k in ("n", "eps", "T")}
+    errs.update({f"U{a}": rel(mom["U"][a], ref["U"][a]) for a in range(3)})
+    print("f32dev errors", errs, flush=True)
+    assert max(errs.values()) < F32_TOL
+
+
+def test_tiny_and_degenerate_grids():
+    from paper_1909_04502_amd import rlbm as R
+    for ext, bc in [((1, 1), ("periodic", "periodic")), ((2, 3), ("open", "open")), ((5, 1), ("periodic", "open"))]:
+        print(f"[case] tiny {ext} {bc}", flush=True)
+        nx, ny = ext
+        n, T, u = W.taylor_green_2d(nx, ny, 0.1, density_sigma=1e-3, seed=3)
+        gl = R.Lattice(d=2, zeta=1.0, order=3, extent=ext, bc=bc, tau=0.8)
+        ol = OL.Lattice(qd.product_2d(1.0, 3), 0.8, ext, bc=bc)
+        fa = gl.init(torch.tensor(n), torch.tensor(T), torch.tensor(u))
+        res = gl.step(fa, gl.new_state(), 3)
+        gl.sync()
+        fs = ol.collide(ol.init(torch.tensor(n), torch.tensor(T), torch.tensor(u)))
+        for _ in range(3):
+            fs = ol.collide(ol.stream(fs))
+        assert rel(res, fs) < FP64_TOL
+
+
+def test_zero_steps_and_odd_even_buffers():
+    from paper_1909_04502_amd import rlbm as R
+    gl = R.Lattice(d=2, zeta=1.0, order=3, extent=(16, 8), tau=0.8)
+    n, T, u = W.taylor_green_2d(16, 8, 0.1)
+    fa = gl.init(torch.tensor(n), torch.tensor(T), torch.tensor(u))
+    keep = fa.clone()
+    fb = gl.new_state()
+    assert gl.step(fa, fb, 0) is fa
+    assert torch.equal(fa, keep)
+    r2 = gl.step(fa, fb, 2)
+    assert r2 is fa
+    fc = keep.clone()
+    r1 = gl.step(fc, gl.new_state(), 1)
+    r1b = gl.step(r1, fc, 1)
+    gl.sync()
+    assert torch.equal(r1b, r2)
+
+
+def test_nonphysical_state_sets_error_flag():
+    from paper_1909_04502_amd import rlbm as R
+    gl = R.Lattice(d=2, zeta=1.0, order=3, extent=(8, 8), tau=0.8)
+    n, T, u = W.taylor_green_2d(8, 8, 0.1)
+    n[3, 4] = -1.0
+    gl.init(torch.tensor(n), torch.tensor(T), torch.tensor(u))
+    with pytest.raises(R.RLBMError) as e:
+        gl.sync()
+    assert e.value.status == R.ERR_NONPHYSICAL
+    gl.sync()      # the flag is cleared by the report
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32dev"])
+def test_full_size_sampled_parity_and_conservation(storage):
+    """1024 x 1024, zeta = 1, N = 3 (the benchmark workload): one step checked site by site
+    on a sample of 4096 sites, and the global invariants sum N^0, sum T^0a over 20 steps."""
+    from paper_1909_04502_amd import rlbm as R
+    print(f"[case] full-size {storage}", flush=True)
+    L = 1024
+    n, T, u = W.taylor_green_2d(L, L, 0.1, density_sigma=1e-3, seed=2)
+    gl = R.Lattice(d=2, zeta=1.0, order=3, extent=(L, L), storage=storage, tau=0.8)
+    fa = gl.init(torch.tensor(n), torch.tensor(T), torch.tensor(u))
+    fb = gl.new_state()
+    q = qd.product_2d(1.0, 3)
+    p = torch.tensor(q.p, device="cuda")
+    fref = None
+    if storage == "f32dev":
+        # population offsets f^ref: equilibrium at rest, n = 1, T = 1 (from the oracle)
+        ol0 = OL.Lattice(q, 0.8, (1, 1))
+        fref = ol0.equilibrium(torch.ones(1, 1, dtype=torch.float64), torch.ones(1, 1, dtype=torch.float64),
+                               torch.tensor([1.0, 0.0, 0.0], dtype=torch.float64)[:, None, None])[:, 0, 0]
+
+    def invariants(f):
+        f = f.to(torch.float64)
+        if fref is not None:
+            f = f + fref.to("cuda")[:, None, None]
+        s = f.sum(dim=(1, 2))
+        out = [(p[:, 0] * s).sum()]
+        for a in range(3):
+            out.append((p[:, 0] * p[:, a] * s).sum())
+        return torch.stack(out).cpu()
+
+    I0 = invariants(fa)
+    res = gl.step(fa, fb, 20)
+    I1 = invariants(res)
+    drift = ((I1 - I0).abs() / I0.abs().max()).max().item()
+    print("invariant drift", drift, flush=True)
+    assert drift < (1e-12 if storage == "f64" else 1e-6)
+    if storage == "f32dev":
+        return
+    nxt = gl.step(res, fb if res is fa else fa, 1)
+    gl.sync()
+    # oracle: stream the GPU state, then collide a sample of sites one by one
+    ol = OL.Lattice(q, 0.8, (L, L))
+    pre = ol.stream(res.cpu())
+    g = np.random.default_rng(0)
+    ys = torch.tensor(g.integers(0, L, 4096))
+    xs = torch.tensor(g.integers(0, L, 4096))
+    sample = pre[:, ys, xs]
+    post = ol.collide(sample)
+    got = nxt.cpu()[:, ys, xs]
+    assert rel(got, post) < FP64_TOL
