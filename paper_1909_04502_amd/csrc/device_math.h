@@ -126,6 +126,14 @@ __device__ __forceinline__ bool landau_frame(const double (&T)[D + 1][D + 1], do
 // d = 3: G_3 = z r + 4 with r = K1/K2 from a Chebyshev fit in log z; Newton
 // iterations on e(T) = T (G_3(m/T) - 1), r' = r^2 + 3 r/z - 1.
 // ---------------------------------------------------------------------------
+// Macroscopic state of a site (double).
+template <int D>
+struct Macro {
+  double n, eps, T;
+  double U[D + 1];
+  bool ok;
+};
+
 struct Ratios {
   double r0, r2, r3;   // A_0/A_1, A_2/A_1 (= G_d), A_3/A_1
 };

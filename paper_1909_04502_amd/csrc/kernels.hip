@@ -22,6 +22,7 @@
 
 #include "device_math.h"
 #include "kernels.h"
+#include "prod_math.h"
 
 namespace rlbm {
 
@@ -113,14 +114,6 @@ __device__ __forceinline__ void pull_all(const Tables *__restrict__ tb, const S 
                                          const Nbr &nb, int x, int y, int z, S (&v)[ST::Q]) {
   pull_all_impl<ST, S>(tb, f, sites, nb, x, y, z, v, std::make_integer_sequence<int, ST::Q>{});
 }
-
-// Macroscopic state of a site (double).
-template <int D>
-struct Macro {
-  double n, eps, T;
-  double U[D + 1];
-  bool ok;
-};
 
 // ---------------------------------------------------------------------------
 // Collision of one site: f (pre-collision, storage precision; deviations in
@@ -265,6 +258,48 @@ __device__ __forceinline__ double site_tau(const Tables *__restrict__ tb, const 
 // ---------------------------------------------------------------------------
 // Kernels
 // ---------------------------------------------------------------------------
+template <class ST, typename S>
+__device__ __forceinline__ Offs make_offs(const Tables *__restrict__ tb, int x, int y, int z) {
+  Offs o;
+  const uint32_t nx = tb->nx, nxy = (uint32_t)tb->nx * tb->ny;
+#pragma unroll
+  for (int d = -1; d <= 1; ++d) {
+    o.x[d + 1] = (uint32_t)wrap_or_clamp(x + d, tb->nx, tb->open[0]) * (uint32_t)sizeof(S);
+    o.y[d + 1] = (uint32_t)wrap_or_clamp(y + d, tb->ny, tb->open[1]) * nx * (uint32_t)sizeof(S);
+    o.z[d + 1] = ST::D == 3 ? (uint32_t)wrap_or_clamp(z + d, tb->nz, tb->open[2]) * nxy * (uint32_t)sizeof(S) : 0u;
+  }
+  return o;
+}
+
+// pre-collision populations at the site
+template <class ST, typename S>
+__device__ __forceinline__ void gather(const Tables *__restrict__ tb, const S *__restrict__ fin, int64_t sites, int x,
+                                       int y, int z, S (&f)[ST::Q]) {
+  if constexpr (ST::ONLAT) {
+    const Nbr nb = make_nbr<ST>(tb, x, y, z);
+    pull_all<ST, S>(tb, fin, sites, nb, x, y, z, f);
+  } else {
+    const Offs o = make_offs<ST, S>(tb, x, y, z);
+    pull_prod<ST, S>(tb, fin, sites, o, f);
+  }
+}
+
+template <class ST, int N, typename S, bool DEV, bool RELAX>
+__device__ __forceinline__ Macro<ST::D> collide_site(const Tables *__restrict__ tb, S (&f)[ST::Q], double tau) {
+  if constexpr (ST::ONLAT)
+    return collide<ST, N, S, DEV, RELAX>(tb, f, tau);
+  else
+    return collide_prod<ST, N, S, DEV, RELAX>(tb, f, tau);
+}
+
+// post-collision store: plane base (uniform) + 32-bit byte offset of the site
+template <class ST, typename S>
+__device__ __forceinline__ void store_site(S *__restrict__ fout, int64_t sites, uint32_t site_off,
+                                           const S (&f)[ST::Q]) {
+#pragma unroll
+  for (int i = 0; i < ST::Q; ++i) *(S *)((char *)(fout + (int64_t)i * sites) + site_off) = f[i];
+}
+
 template <class ST, int N, typename S, bool DEV>
 __global__ void __launch_bounds__(256) k_step(const Tables *__restrict__ tb, const S *__restrict__ fin,
                                               S *__restrict__ fout, const void *__restrict__ tau_field,
@@ -275,14 +310,12 @@ __global__ void __launch_bounds__(256) k_step(const Tables *__restrict__ tb, con
   if (x >= tb->nx || y >= tb->ny) return;
   const int64_t sites = tb->sites;
   const int64_t site = ((int64_t)z * tb->ny + y) * tb->nx + x;
-  const Nbr nb = make_nbr<ST>(tb, x, y, z);
   S f[ST::Q];
-  pull_all<ST, S>(tb, fin, sites, nb, x, y, z, f);
+  gather<ST, S>(tb, fin, sites, x, y, z, f);
   const double tau = site_tau<S>(tb, tau_field, site);
-  const Macro<ST::D> mac = collide<ST, N, S, DEV, true>(tb, f, tau);
+  const Macro<ST::D> mac = collide_site<ST, N, S, DEV, true>(tb, f, tau);
   if (!mac.ok) flag_error(err);
-#pragma unroll
-  for (int i = 0; i < ST::Q; ++i) fout[(int64_t)i * sites + site] = f[i];
+  store_site<ST, S>(fout, sites, (uint32_t)site * (uint32_t)sizeof(S), f);
   if (last.any) write_fields<ST::D>(last, site, sites, mac);
 }
 
@@ -295,10 +328,9 @@ __global__ void __launch_bounds__(256) k_moments(const Tables *__restrict__ tb, 
   if (x >= tb->nx || y >= tb->ny) return;
   const int64_t sites = tb->sites;
   const int64_t site = ((int64_t)z * tb->ny + y) * tb->nx + x;
-  const Nbr nb = make_nbr<ST>(tb, x, y, z);
   S f[ST::Q];
-  pull_all<ST, S>(tb, fin, sites, nb, x, y, z, f);
-  const Macro<ST::D> mac = collide<ST, N, S, DEV, false>(tb, f, 1.0);
+  gather<ST, S>(tb, fin, sites, x, y, z, f);
+  const Macro<ST::D> mac = collide_site<ST, N, S, DEV, false>(tb, f, 1.0);
   if (!mac.ok) flag_error(err);
   write_fields<ST::D>(out, site, sites, mac);
 }
@@ -332,8 +364,9 @@ __global__ void __launch_bounds__(256) k_init(const Tables *__restrict__ tb, con
   if constexpr (D == 2) {
     rr = ratios_2d(tb->m / T);
   } else {
-    bool inr;
+    bool inr = true;
     const double r = tb->m == 0.0 ? 0.0 : cheb_r(tb, tb->m / T, inr);
+    if (!inr) flag_error(err);
     rr = ratios_3d(tb->m / T, r);
   }
   if (!(uu < 1.0) || !(n > 0.0) || !(T > 0.0)) flag_error(err);
@@ -358,10 +391,9 @@ __global__ void __launch_bounds__(256) k_init(const Tables *__restrict__ tb, con
 #pragma unroll
   for (int i = 0; i < Q; ++i) f[i] = DEV ? (S)(fd[i] - tb->fref[i]) : (S)fd[i];
   const double tau = site_tau<S>(tb, tau_field, site);
-  const Macro<D> mac = collide<ST, N, S, DEV, true>(tb, f, tau);
+  const Macro<D> mac = collide_site<ST, N, S, DEV, true>(tb, f, tau);
   if (!mac.ok) flag_error(err);
-#pragma unroll
-  for (int i = 0; i < Q; ++i) fout[(int64_t)i * sites + site] = f[i];
+  store_site<ST, S>(fout, sites, (uint32_t)site * (uint32_t)sizeof(S), f);
   if (fields0.any) write_fields<D>(fields0, site, sites, mac);
 }
 

@@ -495,6 +495,78 @@ int build_tables(const QuadHost &q, double tau, double n_ref, int storage, const
       }
     }
   }
+  // Product rules evaluate the equilibrium as f^eq_i = w_i psi(p_i)^T G'^{-1} M'
+  // over the shifted monomials psi = (p^0 - m)^a p^e (M' the matching
+  // moments).  With the kinetic energy p^0 - m instead of p^0 the Gram matrix
+  // stays well conditioned for large m (1 and p^0 are nearly collinear over
+  // the shells when m >> 1).
+  if (q.kind == RLBM_QUAD_PRODUCT) {
+    std::vector<ld> Ps(Q * NM);
+    for (int i = 0; i < Q; ++i)
+      for (int k = 0; k < NM; ++k) {
+        const signed char *idx = basis_idx(d, q.order, k);
+        ld v = 1.0L;
+        for (int s2 = 0; s2 < 3; ++s2)
+          if (idx[s2] == 0) v *= (ld)q.p[i * D1] - (ld)q.m;
+          else if (idx[s2] > 0) v *= (ld)q.p[i * D1 + idx[s2]];
+        Ps[i * NM + k] = v;
+      }
+    std::vector<ld> Gs(NM * NM, 0.0L), Ls(NM * NM, 0.0L);
+    for (int i = 0; i < Q; ++i)
+      for (int a = 0; a < NM; ++a)
+        for (int b = 0; b < NM; ++b) Gs[a * NM + b] += (ld)q.w[i] * Ps[i * NM + a] * Ps[i * NM + b];
+    for (int j = 0; j < NM; ++j) {
+      ld sd = Gs[j * NM + j];
+      for (int k = 0; k < j; ++k) sd -= Ls[j * NM + k] * Ls[j * NM + k];
+      if (!(sd > 0.0L)) {
+        err = "shifted Gram matrix is not positive definite";
+        return RLBM_ERR_QUADRATURE;
+      }
+      Ls[j * NM + j] = sqrtl(sd);
+      for (int i = j + 1; i < NM; ++i) {
+        ld r = Gs[i * NM + j];
+        for (int k = 0; k < j; ++k) r -= Ls[i * NM + k] * Ls[j * NM + k];
+        Ls[i * NM + j] = r / Ls[j * NM + j];
+      }
+    }
+    // Linv = L^{-1} (lower triangular): the orthonormal polynomials of
+    // Sec. 5.2 are J = Linv psi, their projection coefficients a = Linv M'
+    for (int c = 0; c < NM; ++c) {
+      std::vector<ld> y(NM, 0.0L);
+      for (int a = c; a < NM; ++a) {
+        ld sd = (a == c) ? 1.0L : 0.0L;
+        for (int k = c; k < a; ++k) sd -= Ls[a * NM + k] * y[k];
+        y[a] = sd / Ls[a * NM + a];
+      }
+      for (int a = 0; a < NM; ++a) t.Linv[a][c] = (double)y[a];
+    }
+  }
+  if (q.kind == RLBM_QUAD_PRODUCT) {
+    // shell factors: the radial weight W_j is w_i / (direction weight)
+    for (int j = 0; j < q.nshell; ++j) {
+      const int i = j * q.ndir;                    // direction 0 of shell j is an axis direction
+      const double p0 = q.p[i * D1];
+      double pm2 = 0.0;
+      for (int a = 1; a <= d; ++a) pm2 += q.p[i * D1 + a] * q.p[i * D1 + a];
+      const double pm = std::sqrt(pm2);
+      const double dirw = d == 2 ? 1.0 / 8.0 : 1.0 / 21.0;
+      const double Wj = q.w[i] / dirw;
+      t.sv[j] = pm / p0;
+      const double sm[5] = {p0, pm, p0 * p0, p0 * pm, pm * pm};
+      for (int k = 0; k < 5; ++k) t.smom[j][k] = sm[k];
+      for (int a = 0; a < 2; ++a) {
+        double f = (d == 2 ? Wj / 8.0 : Wj) * (a ? p0 - q.m : 1.0);
+        for (int l = 0; l < 4; ++l) {
+          t.sfeq[j][a][l] = f;
+          f *= pm;
+        }
+      }
+      t.svf[j] = (float)t.sv[j];
+      for (int k = 0; k < 5; ++k) t.smomf[j][k] = (float)t.smom[j][k];
+      for (int a = 0; a < 2; ++a)
+        for (int l = 0; l < 4; ++l) t.sfeqf[j][a][l] = (float)t.sfeq[j][a][l];
+    }
+  }
   // reference state f^ref = equilibrium at (n_ref, T = 1, U = 0) and its moments
   {
     ld U[4] = {1.0L, 0.0L, 0.0L, 0.0L}, M[kMaxNM];

@@ -1,0 +1,314 @@
+// prod_math.h -- collide for the off-lattice product rules (HIP device code).
+//
+// The populations of a product rule are p_jk = (p0_j, |p|_j n_k): shells j
+// times unit directions n_k.  The update is evaluated through that structure:
+//  * moments: per shell, direction sums S0 = sum_k f, S^a = sum_k n^a f,
+//    S^ab = sum_k n^a n^b f (antipodal pairs give sums / differences), then
+//    N^0 = sum_j p0 S0, N^a = sum_j |p| S^a, T^00 = sum_j p0^2 S0,
+//    T^0a = sum_j p0 |p| S^a, T^ab = sum_j |p|^2 S^ab;
+//  * equilibrium: f^eq_i = w_i psi(p_i)^T G^{-1} M (M the Maxwell-Juettner
+//    moments of the monomials psi = (p^0 - m)^a p^e, G their Gram matrix
+//    under the quadrature; this is the projection of Eq. mj-discrete-feq).
+//    G^{-1} = Linv^T Linv with Linv the inverse Cholesky factor, both block
+//    diagonal over the parity classes of the monomials; a = Linv M are the
+//    coefficients on the orthonormal polynomials J = Linv psi and with
+//    a' = Linv^T a, per shell c_e = sum_a a'_(a,e) W_j (p0 - m)^a |p|^|e| and
+//    f^eq_jk = omega_k sum_e c_e n_k^e, the direction powers n_k^e being
+//    compile-time constants;
+//  * relaxation Omega_jk = (U^0 - v_j n_k . U)/tau with per-site n_k . U.
+// Only per-shell scalars and the used Linv entries are read from the tables.
+#pragma once
+#include "device_math.h"
+
+namespace rlbm {
+
+constexpr double kInvNorm[4] = {0.0, 1.0, 0.70710678118654752440, 0.57735026918962576451};
+
+template <class ST>
+RLBM_HD constexpr int nnz_dir(int k) {
+  int c = 0;
+  for (int a = 0; a < ST::D; ++a) c += ST::dir(k, a) != 0;
+  return c;
+}
+
+// unit direction component n_k^a
+template <class ST>
+RLBM_HD constexpr double nhat(int k, int a) {
+  return ST::dir(k, a) * kInvNorm[nnz_dir<ST>(k)];
+}
+
+// n_k^e = prod_a (n_k^a)^{e_a}
+template <class ST>
+RLBM_HD constexpr double nhat_pow(int k, int ex, int ey, int ez) {
+  double r = 1.0;
+  for (int i = 0; i < ex; ++i) r *= nhat<ST>(k, 0);
+  for (int i = 0; i < ey; ++i) r *= nhat<ST>(k, 1);
+  if (ST::D == 3)
+    for (int i = 0; i < ez; ++i) r *= nhat<ST>(k, 2);
+  return r;
+}
+
+// absolute direction weight in 3D (exact for spherical degree <= 7); folded in the shell factors in 2D
+template <class ST>
+RLBM_HD constexpr double dir_weight(int k) {
+  if (ST::D == 2) return 1.0;
+  const int z = nnz_dir<ST>(k);
+  return z == 1 ? 1.0 / 21.0 : (z == 2 ? 4.0 / 105.0 : 9.0 / 280.0);
+}
+
+template <typename A>
+__device__ __forceinline__ A tab(const double &d, const float &f) {
+  if constexpr (sizeof(A) == 8) return d;
+  else return f;
+}
+
+// Byte offsets of the upstream neighbours (-1, 0, +1) along each axis.
+struct Offs {
+  uint32_t x[3], y[3], z[3];
+};
+
+// Pre-collision populations of a product rule (pull + multilinear interpolation).
+// Tap weights are mag^{n_far} (1 - mag)^{n_near}, mag = v_j / sqrt(number of
+// non-zero direction components), n_far the number of taps one site upstream.
+template <class ST, typename S>
+__device__ __forceinline__ void pull_prod(const Tables *__restrict__ tb, const S *__restrict__ fin, int64_t sites,
+                                          const Offs &o, S (&f)[ST::Q]) {
+  typedef S A;
+  constexpr int D = ST::D, ND = ST::NDIR, KR = ST::NSHELL;
+#pragma unroll
+  for (int j = 0; j < KR; ++j) {
+    const A v = tab<A>(tb->sv[j], tb->svf[j]);
+    A pw[4][4];
+#pragma unroll
+    for (int z = 1; z <= D; ++z) {
+      const A mag = v * (A)kInvNorm[z];
+      const A cm = (A)1 - mag;
+      // pw[z][nf] = mag^nf (1-mag)^(z-nf)
+#pragma unroll
+      for (int nf = 0; nf <= z; ++nf) {
+        A r = 1;
+#pragma unroll
+        for (int t = 0; t < nf; ++t) r *= mag;
+#pragma unroll
+        for (int t = nf; t < z; ++t) r *= cm;
+        pw[z][nf] = r;
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < ND; ++k) {
+      const int i = j * ND + k;
+      const char *plane = (const char *)(fin + (int64_t)i * sites);
+      const int dx = ST::dir(k, 0), dy = ST::dir(k, 1), dz = D == 3 ? ST::dir(k, D - 1) : 0;
+      const int z = (dx != 0) + (dy != 0) + (dz != 0);
+      A acc = 0;
+#pragma unroll
+      for (int tap = 0; tap < (1 << z); ++tap) {
+        int bit = 0, ox = 0, oy = 0, oz = 0, nfar = 0;
+        if (dx != 0) {
+          const int c = (tap >> bit++) & 1;
+          ox = dx > 0 ? (c ? 0 : -1) : (c ? 1 : 0);
+          nfar += ox != 0;
+        }
+        if (dy != 0) {
+          const int c = (tap >> bit++) & 1;
+          oy = dy > 0 ? (c ? 0 : -1) : (c ? 1 : 0);
+          nfar += oy != 0;
+        }
+        if (dz != 0) {
+          const int c = (tap >> bit++) & 1;
+          oz = dz > 0 ? (c ? 0 : -1) : (c ? 1 : 0);
+          nfar += oz != 0;
+        }
+        const uint32_t off = o.x[ox + 1] + o.y[oy + 1] + o.z[oz + 1];
+        acc += pw[z][nfar] * *(const S *)(plane + off);
+      }
+      f[i] = acc;
+    }
+  }
+}
+
+template <class ST, int N, typename S, bool DEV, bool RELAX>
+__device__ __forceinline__ Macro<ST::D> collide_prod(const Tables *__restrict__ tb, S (&f)[ST::Q], double tau) {
+  constexpr int D = ST::D, ND = ST::NDIR, NPD = ND / 2, KR = ST::NSHELL;
+  using B = BasisDef<D, N>;
+  constexpr AngTable<D, N> AT{};
+  typedef S A;
+  // ---- step 1: moments ----
+  A N0 = 0, T00 = 0, Na[D], T0a[D], Tab[D * (D + 1) / 2];
+#pragma unroll
+  for (int a = 0; a < D; ++a) Na[a] = T0a[a] = 0;
+#pragma unroll
+  for (int a = 0; a < D * (D + 1) / 2; ++a) Tab[a] = 0;
+#pragma unroll
+  for (int j = 0; j < KR; ++j) {
+    A S0 = 0, Sa[D], Sab[D * (D + 1) / 2];
+#pragma unroll
+    for (int a = 0; a < D; ++a) Sa[a] = 0;
+#pragma unroll
+    for (int a = 0; a < D * (D + 1) / 2; ++a) Sab[a] = 0;
+#pragma unroll
+    for (int q = 0; q < NPD; ++q) {
+      const int k = 2 * q;
+      const A s = f[j * ND + k] + f[j * ND + k + 1];
+      const A d = f[j * ND + k] - f[j * ND + k + 1];
+      S0 += s;
+#pragma unroll
+      for (int a = 0; a < D; ++a) {
+        const double c = nhat<ST>(k, a);
+        if (c == 1.0) Sa[a] += d;
+        else if (c == -1.0) Sa[a] -= d;
+        else if (c != 0.0) Sa[a] += (A)c * d;
+      }
+      int ab = 0;
+#pragma unroll
+      for (int a = 0; a < D; ++a)
+#pragma unroll
+        for (int b = a; b < D; ++b) {
+          const double c = nhat<ST>(k, a) * nhat<ST>(k, b);
+          if (c == 1.0) Sab[ab] += s;
+          else if (c != 0.0) Sab[ab] += (A)c * s;
+          ++ab;
+        }
+    }
+    const A p0 = tab<A>(tb->smom[j][0], tb->smomf[j][0]);
+    const A pm = tab<A>(tb->smom[j][1], tb->smomf[j][1]);
+    const A p00 = tab<A>(tb->smom[j][2], tb->smomf[j][2]);
+    const A p0m = tab<A>(tb->smom[j][3], tb->smomf[j][3]);
+    const A pmm = tab<A>(tb->smom[j][4], tb->smomf[j][4]);
+    N0 += p0 * S0;
+    T00 += p00 * S0;
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+      Na[a] += pm * Sa[a];
+      T0a[a] += p0m * Sa[a];
+    }
+#pragma unroll
+    for (int a = 0; a < D * (D + 1) / 2; ++a) Tab[a] += pmm * Sab[a];
+  }
+  double Nv[D + 1], T[D + 1][D + 1];
+  Nv[0] = N0;
+  T[0][0] = T00;
+  {
+    int ab = 0;
+#pragma unroll
+    for (int a = 1; a <= D; ++a) {
+      Nv[a] = Na[a - 1];
+      T[0][a] = T[a][0] = T0a[a - 1];
+#pragma unroll
+      for (int b = a; b <= D; ++b) {
+        T[a][b] = T[b][a] = Tab[ab];
+        ++ab;
+      }
+    }
+  }
+  if constexpr (DEV) {
+    int s = 0;
+#pragma unroll
+    for (int a = 0; a <= D; ++a) {
+      Nv[a] += tb->Nref[a];
+#pragma unroll
+      for (int b = a; b <= D; ++b) {
+        T[a][b] += tb->Tref[s];
+        if (a != b) T[b][a] = T[a][b];
+        ++s;
+      }
+    }
+  }
+  // ---- steps 2-4 ----
+  Macro<ST::D> mac;
+  mac.ok = landau_frame<D, 3>(T, mac.eps, mac.U);
+  mac.n = lorentz_dot<D>(mac.U, Nv);
+  const double m = tb->m;
+  Ratios rr;
+  if constexpr (D == 2) {
+    mac.ok = temperature_2d(mac.eps / mac.n, m, mac.T) && mac.ok;
+    rr = ratios_2d(m / mac.T);
+  } else {
+    double r;
+    mac.ok = temperature_3d(tb, mac.eps / mac.n, m, mac.T, r) && mac.ok;
+    rr = ratios_3d(m / mac.T, r);
+  }
+  mac.ok = mac.ok && mac.n > 0.0 && mac.eps > 0.0;
+  if constexpr (!RELAX) return mac;
+  // ---- step 5: a' = G^{-1} M over parity blocks ----
+  double Md[B::NM];
+  basis_moments<D, N>(mac.n, mac.T, mac.U, rr, Md);
+  if constexpr (DEV) {
+#pragma unroll
+    for (int k = 0; k < B::NM; ++k) Md[k] -= tb->Mref[k];
+  }
+  // moments of the shifted monomials (p^0 - m) p^e = p^0 p^e - m p^e
+#pragma unroll
+  for (int q = 0; q < AT.n; ++q)
+    if (AT.m1[q] >= 0) Md[AT.m1[q]] -= m * Md[AT.m0[q]];
+  // projection coefficients on the orthonormal polynomials J = Linv psi
+  // (Eq. mj-projection-coefficients), then a' = Linv^T a so that
+  // f^eq_i = w_i psi(p_i)^T a' = w_i sum_k a_k J_k(p_i)
+  double ak[B::NM];
+#pragma unroll
+  for (int r = 0; r < B::NM; ++r) {
+    double acc = 0.0;
+#pragma unroll
+    for (int c = 0; c <= r; ++c)
+      if (AT.cls[r] == AT.cls[c]) acc += tb->Linv[r][c] * Md[c];
+    ak[r] = acc;
+  }
+  A ap[B::NM];
+#pragma unroll
+  for (int c = 0; c < B::NM; ++c) {
+    double acc = 0.0;
+#pragma unroll
+    for (int r = c; r < B::NM; ++r)
+      if (AT.cls[r] == AT.cls[c]) acc += tb->Linv[r][c] * ak[r];
+    ap[c] = (A)acc;
+  }
+  // ---- step 8 ingredients: Omega_jk = a0 - v_j (n_k . U)/tau ----
+  const double itau = 1.0 / tau;
+  const A a0 = (A)(mac.U[0] * itau);
+  A nU[NPD];
+#pragma unroll
+  for (int q = 0; q < NPD; ++q) {
+    double acc = 0.0;
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+      const double c = nhat<ST>(2 * q, a);
+      if (c != 0.0) acc += c * mac.U[a + 1];
+    }
+    nU[q] = (A)(acc * itau);
+  }
+#pragma unroll
+  for (int j = 0; j < KR; ++j) {
+    A ce[20];
+#pragma unroll
+    for (int q = 0; q < AT.n; ++q) {
+      const int l = AT.e[q][0] + AT.e[q][1] + AT.e[q][2];
+      A acc = 0;
+      if (AT.m0[q] >= 0) acc += ap[AT.m0[q]] * tab<A>(tb->sfeq[j][0][l], tb->sfeqf[j][0][l]);
+      if (AT.m1[q] >= 0) acc += ap[AT.m1[q]] * tab<A>(tb->sfeq[j][1][l], tb->sfeqf[j][1][l]);
+      ce[q] = acc;
+    }
+    const A v = tab<A>(tb->sv[j], tb->svf[j]);
+#pragma unroll
+    for (int qp = 0; qp < NPD; ++qp) {
+      const int k = 2 * qp;
+      A E = 0, O = 0;
+#pragma unroll
+      for (int q = 0; q < AT.n; ++q) {
+        const double c = nhat_pow<ST>(k, AT.e[q][0], AT.e[q][1], AT.e[q][2]) * dir_weight<ST>(k);
+        const bool odd = (AT.e[q][0] + AT.e[q][1] + AT.e[q][2]) & 1;
+        if (c == 0.0) continue;
+        if (odd) O += (A)c * ce[q];
+        else E += (A)c * ce[q];
+      }
+      const A b = v * nU[qp];
+      const A om0 = a0 - b, om1 = a0 + b;
+      const int i = j * ND + k;
+      const A f0 = f[i], f1 = f[i + 1];
+      f[i] = f0 + om0 * ((E + O) - f0);
+      f[i + 1] = f1 + om1 * ((E - O) - f1);
+    }
+  }
+  return mac;
+}
+
+}  // namespace rlbm

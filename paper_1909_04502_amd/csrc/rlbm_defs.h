@@ -168,6 +168,53 @@ struct Tables {
   double Nref[4];
   double Tref[10];
   double Mref[kMaxNM];
+  // product rules, per shell j: speed |p|/p^0, moment factors and
+  // equilibrium factors W_j (p^0 - m)^a |p|^l (W_j the shell weight; in 2D
+  // the direction weight 1/8 is folded in)
+  double sv[kMaxShell];
+  double smom[kMaxShell][5];       // p0, |p|, p0^2, p0 |p|, |p|^2
+  double sfeq[kMaxShell][2][4];
+  double Linv[kMaxNM][kMaxNM];     // product rules: inverse Cholesky factor of the Gram matrix of (p^0 - m)^a p^e
+  float svf[kMaxShell];
+  float smomf[kMaxShell][5];
+  float sfeqf[kMaxShell][2][4];
+};
+
+// Angular structure of the basis for product rules: each basis monomial
+// p0^a p^e is grouped by its angular multi-index e; m0[q] / m1[q] are the
+// basis indices with a = 0 / a = 1 (-1 if absent) of angular monomial q.
+template <int D, int N>
+struct AngTable {
+  int n = 0;
+  int e[20][3] = {};
+  int m0[20] = {};
+  int m1[20] = {};
+  int cls[kMaxNM] = {};   // parity class (e_x mod 2, e_y mod 2, e_z mod 2) of each basis monomial
+  constexpr AngTable() {
+    using B = BasisDef<D, N>;
+    for (int m = 0; m < B::NM; ++m) {
+      int a = 0, ee[3] = {0, 0, 0};
+      for (int s = 0; s < 3; ++s) {
+        int ix = B::idx[m][s];
+        if (ix == 0) ++a;
+        else if (ix > 0) ++ee[ix - 1];
+      }
+      cls[m] = (ee[0] & 1) | ((ee[1] & 1) << 1) | ((ee[2] & 1) << 2);
+      int f = -1;
+      for (int q = 0; q < n; ++q)
+        if (e[q][0] == ee[0] && e[q][1] == ee[1] && e[q][2] == ee[2]) f = q;
+      if (f < 0) {
+        f = n++;
+        e[f][0] = ee[0];
+        e[f][1] = ee[1];
+        e[f][2] = ee[2];
+        m0[f] = -1;
+        m1[f] = -1;
+      }
+      if (a == 0) m0[f] = m;
+      else m1[f] = m;
+    }
+  }
 };
 
 }  // namespace rlbm
