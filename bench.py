@@ -35,6 +35,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--no-copy", action="store_true")
     return ap.parse_args()
 
 
@@ -54,15 +56,58 @@ def time_steps(lat, fa, fb, warmup, steps):
     return e0.elapsed_time(e1) / steps * 1e-3       # seconds per step
 
 
-def make_lattice(L, storage):
+def make_lattice(L, storage, autotune=True):
     import torch
     import workloads as W
     from paper_1909_04502_amd import rlbm as R
     n, T, u = W.taylor_green_2d(L, L, 0.1, density_sigma=1e-3, seed=2)
     lat = R.Lattice(d=2, zeta=1.0, order=3, kind="product", extent=(L, L), storage=storage, tau=0.8)
+    tune = lat.autotune(steps=10) if autotune else None
     fa = lat.init(torch.tensor(n), torch.tensor(T), torch.tensor(u))
     fb = lat.new_state()
-    return lat, fa, fb
+    return lat, fa, fb, tune
+
+
+def library_source_sha():
+    import glob
+    import hashlib
+    files = []
+    for pat in ("*.hip", "*.h", "*.cpp"):
+        files += sorted(glob.glob(os.path.join(ROOT, "paper_1909_04502_amd", "csrc", pat)))
+    h = hashlib.sha256()
+    for f in files:
+        h.update(open(f, "rb").read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(name):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if it matches this source."""
+    path = os.path.join(ROOT, "profiles", name)
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    if rec.get("source_sha256_prefix") != library_source_sha():
+        return None
+    return rec["traffic_bytes"]
+
+
+def copy_bandwidth(nbytes, reps=20):
+    """Device-to-device copy of nbytes (read + write), the measured bandwidth reference."""
+    import torch
+    a = torch.empty(nbytes // 8, dtype=torch.float64, device="cuda").fill_(1.0)
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    t = e0.elapsed_time(e1) / reps * 1e-3
+    return 2 * nbytes / t / 1e9
 
 
 def cpu_baseline(seconds):
@@ -97,7 +142,7 @@ def main():
     L = args.size
     Q = 32
     sites = L * L
-    lat, fa, fb = make_lattice(L, "f64")
+    lat, fa, fb, tune = make_lattice(L, "f64", not args.no_autotune)
     t = time_steps(lat, fa, fb, args.warmup, args.steps)
     mlups = sites / t / 1e6
     bytes_step = 2 * Q * 8 * sites
@@ -119,20 +164,29 @@ def main():
                                f"tau=0.8, density noise 1e-3 (seed 2)",
                    "sites": sites, "Q": Q, "storage": "f64"},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": measured_traffic("traffic_k_step_prod2d_f64_1024x1024.json"),
                      "kernel": "k_step<Stencil<PROD2D,4>,3,double>", "algorithmic_bytes_per_site": 2 * Q * 8},
     }
+    if tune is not None:
+        out["autotune"] = {"variant": lat.variant, "ms_per_step": [round(x, 5) for x in tune]}
     del lat, fa, fb
     torch.cuda.empty_cache()
     if not args.no_variants:
-        lat, fa, fb = make_lattice(L, "f32dev")
+        lat, fa, fb, tune32 = make_lattice(L, "f32dev", not args.no_autotune)
         t32 = time_steps(lat, fa, fb, args.warmup, args.steps)
         b32 = 2 * Q * 4 * sites
         out["variants"] = {"f32dev": {"MLUPS": round(sites / t32 / 1e6, 2), "ms_per_step": round(t32 * 1e3, 5),
                                       "achieved_GBs": round(b32 / t32 / 1e9, 1),
-                                      "frac": round(b32 / t32 / 1e9 / HBM_PEAK_GBS, 4)}}
+                                      "frac": round(b32 / t32 / 1e9 / HBM_PEAK_GBS, 4),
+                                      "variant": lat.variant,
+                                      "autotune_ms": [round(x, 5) for x in tune32] if tune32 else None}}
         del lat, fa, fb
         torch.cuda.empty_cache()
+    if not args.no_copy:
+        cb = copy_bandwidth(Q * 8 * sites)
+        out["roofline"]["copy_GBs"] = round(cb, 1)
+        out["roofline"]["frac_of_copy"] = round(achieved / cb, 4)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.cpu_seconds)
     print(json.dumps(out), flush=True)

@@ -176,6 +176,20 @@ rlbm_status rlbm_moments(rlbm_lattice *h, const void *f, const rlbm_fields *out,
 /* Drain the stream and report a deferred device error (clears the flag). */
 rlbm_status rlbm_sync(rlbm_lattice *h, hipStream_t stream);
 
+/* ------------------------------------------------------- launch variants */
+
+/* The step kernel has rlbm_variant_count() launch variants (block shape,
+ * register / occupancy target, XCD-aware tile order); results do not depend
+ * on the variant.  rlbm_autotune times every variant for `steps` steps on
+ * scratch buffers of the lattice's size (allocated and freed inside the
+ * call; the caller's buffers are not touched), selects the fastest and
+ * returns after synchronising the stream.  ms_out (host, may be NULL)
+ * receives rlbm_variant_count() milliseconds per step. */
+int32_t rlbm_variant_count(void);
+rlbm_status rlbm_set_variant(rlbm_lattice *h, int32_t variant);
+rlbm_status rlbm_get_variant(const rlbm_lattice *h, int32_t *variant);
+rlbm_status rlbm_autotune(rlbm_lattice *h, int32_t steps, float *ms_out, hipStream_t stream);
+
 #ifdef __cplusplus
 }
 #endif

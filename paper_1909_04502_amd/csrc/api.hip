@@ -16,6 +16,7 @@ struct rlbm_lattice {
   rlbm::Tables *d_tables = nullptr;
   int *d_err = nullptr;
   int stencil = 0;
+  int variant = 1;
   int64_t sites = 0;
   std::string last_error;
 };
@@ -58,7 +59,13 @@ rlbm::LaunchArgs base_args(const rlbm_lattice *h, hipStream_t stream) {
   a.tau_field = h->cfg.tau_field;
   a.err = h->d_err;
   a.stream = stream;
+  a.variant = h->variant;
   return a;
+}
+
+__global__ void k_fill(double *p, double v, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
 }
 
 }  // namespace
@@ -108,6 +115,9 @@ rlbm_status rlbm_create(const rlbm_config *cfg, rlbm_lattice **out) {
   const int64_t nz = m.d == 3 ? cfg->extent[2] : 1;
   const int64_t sites = cfg->extent[0] * cfg->extent[1] * nz;
   if (m.d == 3 && nz > 65535) return fail(RLBM_ERR_UNSUPPORTED, "nz > 65535");
+  // kernels address a population plane with 32-bit byte offsets
+  if (sites * (cfg->storage == RLBM_F64 ? 8 : 4) >= (int64_t(1) << 32))
+    return fail(RLBM_ERR_UNSUPPORTED, "a population plane must stay below 4 GiB");
 
   rlbm_lattice *h = new (std::nothrow) rlbm_lattice();
   if (!h) return fail(RLBM_ERR_DEVICE, "out of host memory");
@@ -221,6 +231,74 @@ rlbm_status rlbm_sync(rlbm_lattice *h, hipStream_t stream) {
     return fail(RLBM_ERR_NONPHYSICAL, "a kernel met a non-physical state");
   }
   return RLBM_OK;
+}
+
+int32_t rlbm_variant_count(void) { return rlbm::kNumVariants; }
+
+rlbm_status rlbm_set_variant(rlbm_lattice *h, int32_t v) {
+  if (!h || v < 0 || v >= rlbm::kNumVariants) return fail(RLBM_ERR_INVALID_ARG, "bad variant");
+  h->variant = v;
+  return RLBM_OK;
+}
+
+rlbm_status rlbm_get_variant(const rlbm_lattice *h, int32_t *v) {
+  if (!h || !v) return fail(RLBM_ERR_INVALID_ARG, "null argument");
+  *v = h->variant;
+  return RLBM_OK;
+}
+
+rlbm_status rlbm_autotune(rlbm_lattice *h, int32_t steps, float *ms_out, hipStream_t stream) {
+  if (!h || steps < 1) return fail(RLBM_ERR_INVALID_ARG, "bad argument");
+  const int d = h->cfg.model.d;
+  const int64_t bytes = (int64_t)(h->cfg.storage == RLBM_F64 ? 8 : 4) * h->quad.Q * h->sites;
+  void *fa = nullptr, *fb = nullptr;
+  double *fields = nullptr;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  hipError_t he = hipMalloc(&fa, bytes);
+  if (he == hipSuccess) he = hipMalloc(&fb, bytes);
+  if (he == hipSuccess) he = hipMalloc(&fields, sizeof(double) * h->sites * (d + 2));
+  if (he == hipSuccess) he = hipEventCreate(&e0);
+  if (he == hipSuccess) he = hipEventCreate(&e1);
+  rlbm_status st = RLBM_OK;
+  if (he == hipSuccess) {
+    // a rest state n = 1, T = 1, u = 0: the step executes the same instructions for any state
+    const int64_t nf = h->sites * 2;
+    hipLaunchKernelGGL(k_fill, dim3((unsigned)((nf + 255) / 256)), dim3(256), 0, stream, fields, 1.0, nf);
+    hipLaunchKernelGGL(k_fill, dim3((unsigned)((h->sites * d + 255) / 256)), dim3(256), 0, stream,
+                       fields + nf, 0.0, h->sites * d);
+    he = hipGetLastError();
+  }
+  if (he == hipSuccess)
+    st = rlbm_init(h, fields, fields + h->sites, fields + 2 * h->sites, nullptr, 0.0, fa, nullptr, stream);
+  const int saved = h->variant;
+  float best = 1e30f;
+  int best_v = saved;
+  for (int v = 0; he == hipSuccess && st == RLBM_OK && v < rlbm::kNumVariants; ++v) {
+    h->variant = v;
+    st = rlbm_step(h, fa, fb, 2, nullptr, stream);
+    if (st == RLBM_OK) he = hipEventRecord(e0, stream);
+    if (he == hipSuccess && st == RLBM_OK) st = rlbm_step(h, fa, fb, steps, nullptr, stream);
+    if (he == hipSuccess && st == RLBM_OK) he = hipEventRecord(e1, stream);
+    if (he == hipSuccess) he = hipEventSynchronize(e1);
+    float ms = 0.0f;
+    if (he == hipSuccess) he = hipEventElapsedTime(&ms, e0, e1);
+    ms /= steps;
+    if (ms_out) ms_out[v] = ms;
+    if (he == hipSuccess && ms < best) {
+      best = ms;
+      best_v = v;
+    }
+  }
+  h->variant = (he == hipSuccess && st == RLBM_OK) ? best_v : saved;
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  (void)hipStreamSynchronize(stream);
+  if (fa) (void)hipFree(fa);
+  if (fb) (void)hipFree(fb);
+  if (fields) (void)hipFree(fields);
+  if (st != RLBM_OK) return st;
+  if (he != hipSuccess) return fail(RLBM_ERR_DEVICE, hipGetErrorString(he));
+  return rlbm_sync(h, stream);
 }
 
 }  // extern "C"

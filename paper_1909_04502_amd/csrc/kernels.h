@@ -14,8 +14,20 @@ struct FieldPtrs {
   int any;
 };
 
+// Launch variants of the step kernel: block shape, occupancy target
+// (minimum waves per SIMD the compiler must allow, 0 = its choice) and tile
+// order (1 = each XCD walks a contiguous band of tiles).
+struct Variant {
+  int bx, by, occ, xcd;
+};
+constexpr int kNumVariants = 10;
+constexpr Variant kVariants[kNumVariants] = {
+    {64, 4, 0, 0}, {64, 4, 0, 1}, {64, 4, 3, 1}, {64, 4, 4, 1}, {64, 2, 0, 1},
+    {64, 1, 0, 1}, {128, 2, 0, 1}, {32, 8, 0, 1}, {64, 4, 4, 0}, {64, 2, 4, 1}};
+
 struct LaunchArgs {
   int op = 0;
+  int variant = 1;
   int stencil = 0, order = 0, storage = 0;
   int nx = 0, ny = 0, nz = 1;
   const Tables *tb = nullptr;      // device pointer

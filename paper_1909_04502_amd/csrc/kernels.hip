@@ -300,14 +300,33 @@ __device__ __forceinline__ void store_site(S *__restrict__ fout, int64_t sites, 
   for (int i = 0; i < ST::Q; ++i) *(S *)((char *)(fout + (int64_t)i * sites) + site_off) = f[i];
 }
 
-template <class ST, int N, typename S, bool DEV>
-__global__ void __launch_bounds__(256) k_step(const Tables *__restrict__ tb, const S *__restrict__ fin,
+// Site of this thread.  Blocks form a 1D grid over tiles of blockDim.x x
+// blockDim.y sites (x fastest, then y, then z).  The hardware deals
+// consecutive blocks round-robin to the 8 XCDs; with xcd != 0 the block id is
+// remapped so that each XCD receives a contiguous range of tiles, i.e. a band
+// of neighbouring rows whose halo rows stay in that XCD's L2.
+__device__ __forceinline__ bool site_coords(const Tables *__restrict__ tb, int xcd, int &x, int &y, int &z) {
+  const uint32_t gx = (tb->nx + blockDim.x - 1) / blockDim.x;
+  const uint32_t gy = (tb->ny + blockDim.y - 1) / blockDim.y;
+  const uint32_t nb = gridDim.x;
+  uint32_t t = blockIdx.x;
+  if (xcd) {
+    const uint32_t q = nb / 8, r = nb % 8, k = t % 8, l = t / 8;
+    t = k * q + (k < r ? k : r) + l;
+  }
+  const uint32_t tx = t % gx, ty = (t / gx) % gy, tz = t / (gx * gy);
+  x = tx * blockDim.x + threadIdx.x;
+  y = ty * blockDim.y + threadIdx.y;
+  z = tz;
+  return x < tb->nx && y < tb->ny;
+}
+
+template <class ST, int N, typename S, bool DEV, int OCC>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(OCC > 0 ? OCC : 1, 8))) k_step(const Tables *__restrict__ tb, const S *__restrict__ fin,
                                               S *__restrict__ fout, const void *__restrict__ tau_field,
-                                              FieldPtrs last, int *err) {
-  const int x = blockIdx.x * blockDim.x + threadIdx.x;
-  const int y = blockIdx.y * blockDim.y + threadIdx.y;
-  const int z = blockIdx.z;
-  if (x >= tb->nx || y >= tb->ny) return;
+                                              FieldPtrs last, int *err, int xcd) {
+  int x, y, z;
+  if (!site_coords(tb, xcd, x, y, z)) return;
   const int64_t sites = tb->sites;
   const int64_t site = ((int64_t)z * tb->ny + y) * tb->nx + x;
   S f[ST::Q];
@@ -322,10 +341,8 @@ __global__ void __launch_bounds__(256) k_step(const Tables *__restrict__ tb, con
 template <class ST, int N, typename S, bool DEV>
 __global__ void __launch_bounds__(256) k_moments(const Tables *__restrict__ tb, const S *__restrict__ fin,
                                                  FieldPtrs out, int *err) {
-  const int x = blockIdx.x * blockDim.x + threadIdx.x;
-  const int y = blockIdx.y * blockDim.y + threadIdx.y;
-  const int z = blockIdx.z;
-  if (x >= tb->nx || y >= tb->ny) return;
+  int x, y, z;
+  if (!site_coords(tb, 0, x, y, z)) return;
   const int64_t sites = tb->sites;
   const int64_t site = ((int64_t)z * tb->ny + y) * tb->nx + x;
   S f[ST::Q];
@@ -343,10 +360,8 @@ __global__ void __launch_bounds__(256) k_init(const Tables *__restrict__ tb, con
                                               const void *__restrict__ tau_field, FieldPtrs fields0, int *err) {
   constexpr int D = ST::D, Q = ST::Q, NP = Q / 2;
   using B = BasisDef<D, N>;
-  const int x = blockIdx.x * blockDim.x + threadIdx.x;
-  const int y = blockIdx.y * blockDim.y + threadIdx.y;
-  const int z = blockIdx.z;
-  if (x >= tb->nx || y >= tb->ny) return;
+  int x, y, z;
+  if (!site_coords(tb, 0, x, y, z)) return;
   const int64_t sites = tb->sites;
   const int64_t site = ((int64_t)z * tb->ny + y) * tb->nx + x;
   double U[D + 1], uu = 0.0;
@@ -402,13 +417,21 @@ __global__ void __launch_bounds__(256) k_init(const Tables *__restrict__ tb, con
 // ---------------------------------------------------------------------------
 template <class ST, int N, typename S, bool DEV>
 static hipError_t launch_t(const LaunchArgs &a) {
-  const int bx = 64, by = 4;
-  dim3 block(bx, by, 1);
-  dim3 grid((a.nx + bx - 1) / bx, (a.ny + by - 1) / by, a.nz);
+  const Variant vr = kVariants[(a.op == OP_STEP && a.variant >= 0 && a.variant < kNumVariants) ? a.variant : 0];
+  dim3 block(vr.bx, vr.by, 1);
+  const long nb = (long)((a.nx + vr.bx - 1) / vr.bx) * ((a.ny + vr.by - 1) / vr.by) * a.nz;
+  dim3 grid((unsigned)nb, 1, 1);
   switch (a.op) {
     case OP_STEP:
-      hipLaunchKernelGGL((k_step<ST, N, S, DEV>), grid, block, 0, a.stream, a.tb, (const S *)a.fin, (S *)a.fout,
-                         a.tau_field, a.fields, a.err);
+      if (vr.occ == 3)
+        hipLaunchKernelGGL((k_step<ST, N, S, DEV, 3>), grid, block, 0, a.stream, a.tb, (const S *)a.fin,
+                           (S *)a.fout, a.tau_field, a.fields, a.err, vr.xcd);
+      else if (vr.occ == 4)
+        hipLaunchKernelGGL((k_step<ST, N, S, DEV, 4>), grid, block, 0, a.stream, a.tb, (const S *)a.fin,
+                           (S *)a.fout, a.tau_field, a.fields, a.err, vr.xcd);
+      else
+        hipLaunchKernelGGL((k_step<ST, N, S, DEV, 0>), grid, block, 0, a.stream, a.tb, (const S *)a.fin,
+                           (S *)a.fout, a.tau_field, a.fields, a.err, vr.xcd);
       break;
     case OP_MOMENTS:
       hipLaunchKernelGGL((k_moments<ST, N, S, DEV>), grid, block, 0, a.stream, a.tb, (const S *)a.fin, a.fields,

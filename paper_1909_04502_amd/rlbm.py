@@ -93,6 +93,14 @@ def lib():
     L.rlbm_moments.argtypes = [c_void_p, c_void_p, POINTER(Fields), c_void_p]
     L.rlbm_sync.restype = st
     L.rlbm_sync.argtypes = [c_void_p, c_void_p]
+    L.rlbm_variant_count.restype = c_int32
+    L.rlbm_variant_count.argtypes = []
+    L.rlbm_set_variant.restype = st
+    L.rlbm_set_variant.argtypes = [c_void_p, c_int32]
+    L.rlbm_get_variant.restype = st
+    L.rlbm_get_variant.argtypes = [c_void_p, POINTER(c_int32)]
+    L.rlbm_autotune.restype = st
+    L.rlbm_autotune.argtypes = [c_void_p, c_int32, c_void_p, c_void_p]
     _lib = L
     _check_single_hip_runtime()
     return L
@@ -231,3 +239,21 @@ class Lattice:
 
     def sync(self):
         _check(lib().rlbm_sync(self.h, _stream()))
+
+    # launch variants -----------------------------------------------------
+    @property
+    def variant(self):
+        v = c_int32(0)
+        _check(lib().rlbm_get_variant(self.h, ctypes.byref(v)))
+        return v.value
+
+    @variant.setter
+    def variant(self, v):
+        _check(lib().rlbm_set_variant(self.h, int(v)))
+
+    def autotune(self, steps=5):
+        """Time every launch variant on scratch buffers; keep the fastest. Returns ms per step per variant."""
+        n = lib().rlbm_variant_count()
+        ms = (ctypes.c_float * n)()
+        _check(lib().rlbm_autotune(self.h, int(steps), ms, _stream()))
+        return list(ms)

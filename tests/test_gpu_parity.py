@@ -218,3 +218,23 @@ def test_full_size_sampled_parity_and_conservation(storage):
     post = ol.collide(sample)
     got = nxt.cpu()[:, ys, xs]
     assert rel(got, post) < FP64_TOL
+
+
+def test_launch_variants_agree():
+    """Every launch variant computes the same update (to rounding) on a ragged lattice."""
+    from paper_1909_04502_amd import rlbm as R
+    gl, ol, (n, T, u, xi, amp) = setup_case("c2_ragged")
+    fa0 = gl.init(n, T, u, xi, amp)
+    ref = None
+    for v in range(R.lib().rlbm_variant_count()):
+        print(f"[case] variant {v}", flush=True)
+        gl.variant = v
+        res = gl.step(fa0.clone(), gl.new_state(), 3)
+        gl.sync()
+        if ref is None:
+            ref = res.cpu()
+        else:
+            assert rel(res, ref) < 1e-14, v
+    ms = gl.autotune(steps=2)
+    assert len(ms) == R.lib().rlbm_variant_count() and all(m > 0 for m in ms)
+    assert 0 <= gl.variant < len(ms)
