@@ -176,6 +176,30 @@ rlbm_status rlbm_moments(rlbm_lattice *h, const void *f, const rlbm_fields *out,
 /* Drain the stream and report a deferred device error (clears the flag). */
 rlbm_status rlbm_sync(rlbm_lattice *h, hipStream_t stream);
 
+/* ------------------------------------------------------------ reverse mode
+ *
+ * Hand-written adjoint of the update (not part of the paper; it lets tau or
+ * the initial fields be calibrated against a target flow).  With B_0 = C(f_0),
+ * F_t = S(B_{t-1}), B_t = C(F_t) (S streaming, C collision, as above) and a
+ * loss L on the macroscopic fields of F_{T+1} = S(B_T), the adjoint buffers
+ * lam_t = dL/dF_t (same element type and layout as a state) obey
+ *   lam_{T+1} = rlbm_moments_vjp(B_T, dL/dfields),
+ *   lam_t     = rlbm_adjoint_step(B_{t-1}, lam_{t+1}),   t = T .. 1,
+ * and rlbm_init_vjp(fields, lam_1) gives dL/du0 (and dL/dn0, dL/dT0).
+ * dtau_accum (device [sites] doubles, or NULL) is incremented by each call's
+ * contribution to dL/dtau(x) (per-site tau field or scalar tau alike).
+ * Implemented for the 2D product rules with periodic boundaries; other
+ * lattices return RLBM_ERR_UNSUPPORTED.  Every forward quantity of a site is
+ * recomputed from the given state; the Landau eigenpair is differentiated
+ * implicitly (exact derivative of the converged eigenpair). */
+rlbm_status rlbm_adjoint_step(rlbm_lattice *h, const void *f_prev, const void *lam_next, void *lam,
+                              double *dtau_accum, hipStream_t stream);
+rlbm_status rlbm_moments_vjp(rlbm_lattice *h, const void *f, const rlbm_fields *grad, void *lam,
+                             hipStream_t stream);
+rlbm_status rlbm_init_vjp(rlbm_lattice *h, const double *n0, const double *T0, const double *u0,
+                          const double *noise, double noise_amp, const void *lam1, double *du0,
+                          double *dn0, double *dT0, double *dtau_accum, hipStream_t stream);
+
 /* ------------------------------------------------------- launch variants */
 
 /* The step kernel has rlbm_variant_count() launch variants (block shape,

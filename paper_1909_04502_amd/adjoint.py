@@ -1,0 +1,70 @@
+"""Differentiable RLBM runs: a torch.autograd.Function over the C-ABI kernels.
+
+Forward: f_0 from (n0, T0, u0), B_0 = C(f_0), B_t = C(S(B_{t-1})) for
+t = 1..T, returning the four-velocity of F_{T+1} = S(B_T).  Every `every`
+steps the state is checkpointed.  Backward: lam_{T+1} from rlbm_moments_vjp,
+then segment by segment (last first) the states of the segment are
+recomputed from its checkpoint and lam_t = rlbm_adjoint_step(B_{t-1},
+lam_{t+1}) runs down to the segment start; finally rlbm_init_vjp gives
+dL/du0.  dL/dtau(x) is accumulated by every reverse kernel.  Memory: the
+checkpoints plus one segment of states.
+"""
+from __future__ import annotations
+
+import torch
+
+from .rlbm import Lattice
+
+
+class _Run(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, tau_field, u0, lat, n0, T0, nsteps, every, noise, amp):
+        if lat.tau_field is None:
+            raise ValueError("the lattice must be created with a tau_field tensor")
+        lat.tau_field.copy_(tau_field.detach().to(lat.tau_field.dtype))
+        u0d = u0.detach().to(torch.float64)
+        cur = lat.init(n0, T0, u0d, noise, amp)
+        nxt = lat.new_state()
+        ckpt = {0: cur.clone()}
+        for t in range(1, nsteps + 1):
+            lat.step(cur, nxt, 1)
+            cur, nxt = nxt, cur
+            if t % every == 0 and t < nsteps:
+                ckpt[t] = cur.clone()
+        final = cur
+        fields = lat.moments(final)
+        ctx.lat, ctx.ckpt, ctx.final = lat, ckpt, final
+        ctx.args = (n0, T0, u0d, noise, amp, nsteps, every)
+        ctx.tau_dtype = tau_field.dtype
+        return fields["U"]
+
+    @staticmethod
+    def backward(ctx, gU):
+        lat = ctx.lat
+        n0, T0, u0d, noise, amp, nsteps, every = ctx.args
+        lam = lat.moments_vjp(ctx.final, gU=gU.contiguous())
+        dtau = torch.zeros(lat.grid_shape, dtype=torch.float64, device="cuda")
+        for s in sorted(ctx.ckpt, reverse=True):
+            e = min(s + every, nsteps)
+            states = [ctx.ckpt[s]]
+            for _ in range(s + 1, e):                      # B_{s+1} .. B_{e-1}
+                nxt = lat.new_state()
+                lat.step(states[-1], nxt, 1)
+                states.append(nxt)
+            for t in range(e, s, -1):                      # lam_t from B_{t-1} and lam_{t+1}
+                lam = lat.adjoint_step(states[t - 1 - s], lam, dtau=dtau)
+            del states
+        du0 = lat.init_vjp(n0, T0, u0d, lam, noise, amp, dtau=dtau)
+        lat.sync()
+        return dtau.to(ctx.tau_dtype), du0, None, None, None, None, None, None, None
+
+
+def run(lat: Lattice, tau_field, u0, n0, T0, nsteps: int, every: int = 45, noise=None, amp: float = 0.0):
+    """Four-velocity U (d+1, grid) of the final state, differentiable in tau_field and u0."""
+    return _Run.apply(tau_field, u0, lat, n0, T0, nsteps, every, noise, amp)
+
+
+def velocity_loss(U, target_u):
+    """L = 1/2 sum_x |u - u_target|^2 with the three-velocity u = U^a / U^0."""
+    u = U[1:] / U[0]
+    return 0.5 * ((u - target_u) ** 2).sum()

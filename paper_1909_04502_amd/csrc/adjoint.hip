@@ -1,0 +1,208 @@
+// adjoint.hip -- reverse-mode kernels of the RLBM step (HIP, gfx950).
+//
+// State sequence: B_0 = C(f_0), F_t = S(B_{t-1}), B_t = C(F_t) (S streaming,
+// C collision).  Adjoints lam_t = dL/dF_t obey
+//   lam_t = J_C(F_t)^T S^T lam_{t+1},   dL/dtau += (dC/dtau)^T S^T lam_{t+1},
+// and the loss on the macroscopic fields of F_{T+1} = S(B_T) seeds
+// lam_{T+1} = J_macro(F_{T+1})^T g.  Each kernel recomputes the forward
+// values of its site from the stored state (no per-site tape is kept).
+#include <hip/hip_runtime.h>
+
+#include "adjoint_math.h"
+#include "kernels.h"
+
+namespace rlbm {
+
+__device__ __forceinline__ bool site_xyz(const Tables *__restrict__ tb, int &x, int &y, int &z) {
+  const uint32_t gx = (tb->nx + 63) / 64, gy = (tb->ny + 3) / 4;
+  const uint32_t t = blockIdx.x;
+  x = (t % gx) * 64 + threadIdx.x;
+  y = ((t / gx) % gy) * 4 + threadIdx.y;
+  z = t / (gx * gy);
+  return x < tb->nx && y < tb->ny;
+}
+
+__device__ __forceinline__ int wrap_p(int v, int n) {
+  v = v < 0 ? v + n : v;
+  return v >= n ? v - n : v;
+}
+
+template <class ST, typename S>
+__device__ __forceinline__ Offs offs_periodic(const Tables *__restrict__ tb, int x, int y, int z) {
+  Offs o;
+  const uint32_t nx = tb->nx, nxy = (uint32_t)tb->nx * tb->ny;
+#pragma unroll
+  for (int d = -1; d <= 1; ++d) {
+    o.x[d + 1] = (uint32_t)wrap_p(x + d, tb->nx) * (uint32_t)sizeof(S);
+    o.y[d + 1] = (uint32_t)wrap_p(y + d, tb->ny) * nx * (uint32_t)sizeof(S);
+    o.z[d + 1] = ST::D == 3 ? (uint32_t)wrap_p(z + d, tb->nz) * nxy * (uint32_t)sizeof(S) : 0u;
+  }
+  return o;
+}
+
+template <typename S>
+__device__ __forceinline__ double tau_at(const Tables *__restrict__ tb, const void *tau_field, int64_t site) {
+  return tau_field == nullptr ? tb->tau : (double)((const S *)tau_field)[site];
+}
+
+__device__ __forceinline__ void set_err(int *err) { *(volatile int *)err = 1; }
+
+// lam_t(x) = J_C(F_t(x))^T (S^T lam_{t+1})(x), F_t = S(B_{t-1}); dtau(x) += dL/dtau(x)
+template <class ST, int N, typename S, bool DEV>
+__global__ void __launch_bounds__(256) k_adjoint(const Tables *__restrict__ tb, const S *__restrict__ Bprev,
+                                                 const S *__restrict__ lam_next, S *__restrict__ lam,
+                                                 const void *__restrict__ tau_field, double *__restrict__ dtau,
+                                                 int *err) {
+  int x, y, z;
+  if (!site_xyz(tb, x, y, z)) return;
+  const int64_t sites = tb->sites;
+  const int64_t site = ((int64_t)z * tb->ny + y) * tb->nx + x;
+  const Offs o = offs_periodic<ST, S>(tb, x, y, z);
+  S f[ST::Q], mu[ST::Q];
+  pull_prod<ST, S, false>(tb, Bprev, sites, o, f);
+  pull_prod<ST, S, true>(tb, lam_next, sites, o, mu);
+  double taub;
+  if (!collide_vjp<ST, N, S, DEV>(tb, f, mu, tau_at<S>(tb, tau_field, site), taub)) set_err(err);
+  const uint32_t so = (uint32_t)site * (uint32_t)sizeof(S);
+#pragma unroll
+  for (int i = 0; i < ST::Q; ++i) *(S *)((char *)(lam + (int64_t)i * sites) + so) = f[i];
+  if (dtau != nullptr) dtau[site] += taub;
+}
+
+// lam_{T+1}(x) = J_macro(F(x))^T g(x), F = S(B); g = (dL/dn, dL/deps, dL/dT, dL/dU)
+template <class ST, int N, typename S, bool DEV>
+__global__ void __launch_bounds__(256) k_moments_vjp(const Tables *__restrict__ tb, const S *__restrict__ B,
+                                                     FieldPtrs g, S *__restrict__ lam, int *err) {
+  constexpr int D = ST::D;
+  int x, y, z;
+  if (!site_xyz(tb, x, y, z)) return;
+  const int64_t sites = tb->sites;
+  const int64_t site = ((int64_t)z * tb->ny + y) * tb->nx + x;
+  const Offs o = offs_periodic<ST, S>(tb, x, y, z);
+  S f[ST::Q];
+  pull_prod<ST, S, false>(tb, B, sites, o, f);
+  double Nv[D + 1], T[D + 1][D + 1];
+  moments_prod<ST, S, DEV>(tb, f, Nv, T);
+  Macro<D> mac;
+  mac.ok = landau_frame<D, 3>(T, mac.eps, mac.U);
+  mac.n = lorentz_dot<D>(mac.U, Nv);
+  mac.ok = temperature_2d(mac.eps / mac.n, tb->m, mac.T) && mac.ok && mac.n > 0.0 && mac.eps > 0.0;
+  if (!mac.ok) set_err(err);
+  double Ub[D + 1];
+#pragma unroll
+  for (int a = 0; a <= D; ++a) Ub[a] = g.U ? g.U[a * sites + site] : 0.0;
+  const double nb = g.n ? g.n[site] : 0.0, eb = g.eps ? g.eps[site] : 0.0, Tb = g.T ? g.T[site] : 0.0;
+  S out[ST::Q];
+#pragma unroll
+  for (int i = 0; i < ST::Q; ++i) out[i] = 0;
+  macro_vjp<ST, S>(tb, Nv, T, mac, nb, eb, Tb, Ub, out);
+  const uint32_t so = (uint32_t)site * (uint32_t)sizeof(S);
+#pragma unroll
+  for (int i = 0; i < ST::Q; ++i) *(S *)((char *)(lam + (int64_t)i * sites) + so) = out[i];
+}
+
+// Reverse of the initial condition B_0 = C(f_0), f_0 = f^eq(n0, T0, U(u0)) (1 + amp xi):
+// du0 (and dn0, dT0 when requested) from lam_1 = dL/dF_1; dtau(x) += dL/dtau(x).
+template <class ST, int N, typename S, bool DEV>
+__global__ void __launch_bounds__(256) k_init_vjp(const Tables *__restrict__ tb, const double *__restrict__ n0,
+                                                  const double *__restrict__ T0, const double *__restrict__ u0,
+                                                  const double *__restrict__ noise, double amp,
+                                                  const S *__restrict__ lam1, const void *__restrict__ tau_field,
+                                                  double *__restrict__ du0, double *__restrict__ dn0,
+                                                  double *__restrict__ dT0, double *__restrict__ dtau, int *err) {
+  constexpr int D = ST::D, Q = ST::Q;
+  using B = BasisDef<D, N>;
+  int x, y, z;
+  if (!site_xyz(tb, x, y, z)) return;
+  const int64_t sites = tb->sites;
+  const int64_t site = ((int64_t)z * tb->ny + y) * tb->nx + x;
+  double U[D + 1], u[D], uu = 0.0;
+#pragma unroll
+  for (int a = 0; a < D; ++a) {
+    u[a] = u0[a * sites + site];
+    uu += u[a] * u[a];
+  }
+  const double gam = 1.0 / sqrt(1.0 - uu);
+  U[0] = gam;
+#pragma unroll
+  for (int a = 0; a < D; ++a) U[a + 1] = gam * u[a];
+  const double n = n0[site], T = T0[site];
+  const RatiosD rd = ratios_2d_d(tb->m / T);
+  Ratios rr;
+  rr.r0 = rd.r0;
+  rr.r2 = rd.r2;
+  rr.r3 = rd.r3;
+  double M[B::NM];
+  basis_moments<D, N>(n, T, U, rr, M);
+  double fe[Q];
+  feq_prod<ST, N, double, false>(tb, M, fe);
+  S f[Q];
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    const double sc = noise ? 1.0 + amp * noise[(int64_t)i * sites + site] : 1.0;
+    const double fi = fe[i] * sc;
+    f[i] = DEV ? (S)(fi - tb->fref[i]) : (S)fi;
+  }
+  const Offs o = offs_periodic<ST, S>(tb, x, y, z);
+  S mu[Q];
+  pull_prod<ST, S, true>(tb, lam1, sites, o, mu);
+  double taub;
+  if (!collide_vjp<ST, N, S, DEV>(tb, f, mu, tau_at<S>(tb, tau_field, site), taub)) set_err(err);
+  if (dtau != nullptr) dtau[site] += taub;
+  // f now holds dL/df_0; through the noise factor to dL/df^eq
+  double g[Q];
+#pragma unroll
+  for (int i = 0; i < Q; ++i) g[i] = (double)f[i] * (noise ? 1.0 + amp * noise[(int64_t)i * sites + site] : 1.0);
+  double Mb[B::NM];
+  feq_vjp<ST, N, double>(tb, g, Mb);
+  double nb = 0.0, Tb = 0.0, Ub[D + 1];
+#pragma unroll
+  for (int a = 0; a <= D; ++a) Ub[a] = 0.0;
+  basis_moments_vjp<D, N>(n, T, U, tb->m, rd, Mb, nb, Tb, Ub);
+  // U = gamma (1, u):  dL/du_b = gamma Ub^b + gamma^3 u_b (Ub^0 + sum_a Ub^a u_a)
+  double s = Ub[0];
+#pragma unroll
+  for (int a = 0; a < D; ++a) s += Ub[a + 1] * u[a];
+  if (du0 != nullptr) {
+#pragma unroll
+    for (int a = 0; a < D; ++a) du0[a * sites + site] = gam * Ub[a + 1] + gam * gam * gam * u[a] * s;
+  }
+  if (dn0 != nullptr) dn0[site] = nb;
+  if (dT0 != nullptr) dT0[site] = Tb;
+}
+
+template <class ST, int N, typename S, bool DEV>
+static hipError_t launch_adj_t(const AdjointArgs &a) {
+  dim3 block(64, 4, 1);
+  const long nb = (long)((a.nx + 63) / 64) * ((a.ny + 3) / 4) * a.nz;
+  dim3 grid((unsigned)nb, 1, 1);
+  switch (a.op) {
+    case ADJ_STEP:
+      hipLaunchKernelGGL((k_adjoint<ST, N, S, DEV>), grid, block, 0, a.stream, a.tb, (const S *)a.state,
+                         (const S *)a.lam_in, (S *)a.lam_out, a.tau_field, a.dtau, a.err);
+      break;
+    case ADJ_MOMENTS:
+      hipLaunchKernelGGL((k_moments_vjp<ST, N, S, DEV>), grid, block, 0, a.stream, a.tb, (const S *)a.state,
+                         a.grads, (S *)a.lam_out, a.err);
+      break;
+    case ADJ_INIT:
+      hipLaunchKernelGGL((k_init_vjp<ST, N, S, DEV>), grid, block, 0, a.stream, a.tb, a.n0, a.T0, a.u0, a.noise,
+                         a.amp, (const S *)a.lam_in, a.tau_field, a.du0, a.dn0, a.dT0, a.dtau, a.err);
+      break;
+    default:
+      return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_adjoint(const AdjointArgs &a) {
+  if (a.stencil != ST_PROD2D) return hipErrorInvalidValue;
+  if (a.order == 2) {
+    if (a.storage == 0) return launch_adj_t<Stencil<ST_PROD2D, 3>, 2, double, false>(a);
+    return launch_adj_t<Stencil<ST_PROD2D, 3>, 2, float, true>(a);
+  }
+  if (a.storage == 0) return launch_adj_t<Stencil<ST_PROD2D, 4>, 3, double, false>(a);
+  return launch_adj_t<Stencil<ST_PROD2D, 4>, 3, float, true>(a);
+}
+
+}  // namespace rlbm

@@ -233,6 +233,81 @@ rlbm_status rlbm_sync(rlbm_lattice *h, hipStream_t stream) {
   return RLBM_OK;
 }
 
+static rlbm_status adjoint_supported(const rlbm_lattice *h) {
+  if (h->stencil != rlbm::ST_PROD2D)
+    return fail(RLBM_ERR_UNSUPPORTED, "reverse mode is implemented for the 2D product rules");
+  for (int a = 0; a < 2; ++a)
+    if (h->cfg.bc[a] != RLBM_PERIODIC) return fail(RLBM_ERR_UNSUPPORTED, "reverse mode needs periodic boundaries");
+  return RLBM_OK;
+}
+
+static rlbm::AdjointArgs adj_args(const rlbm_lattice *h, hipStream_t stream) {
+  rlbm::AdjointArgs a;
+  a.stencil = h->stencil;
+  a.order = h->cfg.model.order;
+  a.storage = h->cfg.storage;
+  a.nx = (int)h->cfg.extent[0];
+  a.ny = (int)h->cfg.extent[1];
+  a.nz = 1;
+  a.tb = h->d_tables;
+  a.tau_field = h->cfg.tau_field;
+  a.err = h->d_err;
+  a.stream = stream;
+  return a;
+}
+
+rlbm_status rlbm_adjoint_step(rlbm_lattice *h, const void *f_prev, const void *lam_next, void *lam,
+                              double *dtau_accum, hipStream_t stream) {
+  if (!h || !f_prev || !lam_next || !lam) return fail(RLBM_ERR_INVALID_ARG, "null argument");
+  if (lam == lam_next || lam == f_prev) return fail(RLBM_ERR_INVALID_ARG, "lam must not alias its inputs");
+  rlbm_status st = adjoint_supported(h);
+  if (st != RLBM_OK) return st;
+  rlbm::AdjointArgs a = adj_args(h, stream);
+  a.op = rlbm::ADJ_STEP;
+  a.state = f_prev;
+  a.lam_in = lam_next;
+  a.lam_out = lam;
+  a.dtau = dtau_accum;
+  hipError_t he = rlbm::launch_adjoint(a);
+  return he == hipSuccess ? RLBM_OK : fail(RLBM_ERR_DEVICE, hipGetErrorString(he));
+}
+
+rlbm_status rlbm_moments_vjp(rlbm_lattice *h, const void *f, const rlbm_fields *grad, void *lam,
+                             hipStream_t stream) {
+  if (!h || !f || !grad || !lam) return fail(RLBM_ERR_INVALID_ARG, "null argument");
+  rlbm_status st = adjoint_supported(h);
+  if (st != RLBM_OK) return st;
+  rlbm::AdjointArgs a = adj_args(h, stream);
+  a.op = rlbm::ADJ_MOMENTS;
+  a.state = f;
+  a.lam_out = lam;
+  a.grads = field_ptrs(grad);
+  hipError_t he = rlbm::launch_adjoint(a);
+  return he == hipSuccess ? RLBM_OK : fail(RLBM_ERR_DEVICE, hipGetErrorString(he));
+}
+
+rlbm_status rlbm_init_vjp(rlbm_lattice *h, const double *n0, const double *T0, const double *u0,
+                          const double *noise, double noise_amp, const void *lam1, double *du0, double *dn0,
+                          double *dT0, double *dtau_accum, hipStream_t stream) {
+  if (!h || !n0 || !T0 || !u0 || !lam1) return fail(RLBM_ERR_INVALID_ARG, "null argument");
+  rlbm_status st = adjoint_supported(h);
+  if (st != RLBM_OK) return st;
+  rlbm::AdjointArgs a = adj_args(h, stream);
+  a.op = rlbm::ADJ_INIT;
+  a.n0 = n0;
+  a.T0 = T0;
+  a.u0 = u0;
+  a.noise = noise;
+  a.amp = noise_amp;
+  a.lam_in = lam1;
+  a.du0 = du0;
+  a.dn0 = dn0;
+  a.dT0 = dT0;
+  a.dtau = dtau_accum;
+  hipError_t he = rlbm::launch_adjoint(a);
+  return he == hipSuccess ? RLBM_OK : fail(RLBM_ERR_DEVICE, hipGetErrorString(he));
+}
+
 int32_t rlbm_variant_count(void) { return rlbm::kNumVariants; }
 
 rlbm_status rlbm_set_variant(rlbm_lattice *h, int32_t v) {

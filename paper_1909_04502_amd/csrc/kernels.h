@@ -43,4 +43,27 @@ struct LaunchArgs {
 
 hipError_t launch(const LaunchArgs &a);
 
+enum AdjOp : int { ADJ_STEP = 0, ADJ_MOMENTS = 1, ADJ_INIT = 2 };
+
+struct AdjointArgs {
+  int op = 0;
+  int stencil = 0, order = 0, storage = 0;
+  int nx = 0, ny = 0, nz = 1;
+  const Tables *tb = nullptr;
+  const void *state = nullptr;      // B_{t-1} (step) or B_T (moments)
+  const void *lam_in = nullptr;     // lam_{t+1} (step) or lam_1 (init)
+  void *lam_out = nullptr;
+  const void *tau_field = nullptr;
+  double *dtau = nullptr;
+  FieldPtrs grads = {nullptr, nullptr, nullptr, nullptr, 0};
+  const double *n0 = nullptr, *T0 = nullptr, *u0 = nullptr, *noise = nullptr;
+  double amp = 0.0;
+  double *du0 = nullptr, *dn0 = nullptr, *dT0 = nullptr;
+  int *err = nullptr;
+  hipStream_t stream = 0;
+};
+
+// reverse-mode kernels (2D product rules, periodic boundaries)
+hipError_t launch_adjoint(const AdjointArgs &a);
+
 }  // namespace rlbm

@@ -70,7 +70,10 @@ struct Offs {
 // Pre-collision populations of a product rule (pull + multilinear interpolation).
 // Tap weights are mag^{n_far} (1 - mag)^{n_near}, mag = v_j / sqrt(number of
 // non-zero direction components), n_far the number of taps one site upstream.
-template <class ST, typename S>
+// With TRANSPOSE the taps are mirrored (offset -o, same weight): this applies
+// the transpose of the streaming operator on a periodic grid (the adjoint
+// gather dL/dB(y) = sum_taps w dL/dF(y - o)).
+template <class ST, typename S, bool TRANSPOSE = false>
 __device__ __forceinline__ void pull_prod(const Tables *__restrict__ tb, const S *__restrict__ fin, int64_t sites,
                                           const Offs &o, S (&f)[ST::Q]) {
   typedef S A;
@@ -118,6 +121,11 @@ __device__ __forceinline__ void pull_prod(const Tables *__restrict__ tb, const S
           const int c = (tap >> bit++) & 1;
           oz = dz > 0 ? (c ? 0 : -1) : (c ? 1 : 0);
           nfar += oz != 0;
+        }
+        if (TRANSPOSE) {
+          ox = -ox;
+          oy = -oy;
+          oz = -oz;
         }
         const uint32_t off = o.x[ox + 1] + o.y[oy + 1] + o.z[oz + 1];
         acc += pw[z][nfar] * *(const S *)(plane + off);

@@ -93,6 +93,13 @@ def lib():
     L.rlbm_moments.argtypes = [c_void_p, c_void_p, POINTER(Fields), c_void_p]
     L.rlbm_sync.restype = st
     L.rlbm_sync.argtypes = [c_void_p, c_void_p]
+    L.rlbm_adjoint_step.restype = st
+    L.rlbm_adjoint_step.argtypes = [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]
+    L.rlbm_moments_vjp.restype = st
+    L.rlbm_moments_vjp.argtypes = [c_void_p, c_void_p, POINTER(Fields), c_void_p, c_void_p]
+    L.rlbm_init_vjp.restype = st
+    L.rlbm_init_vjp.argtypes = [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_double, c_void_p,
+                                c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]
     L.rlbm_variant_count.restype = c_int32
     L.rlbm_variant_count.argtypes = []
     L.rlbm_set_variant.restype = st
@@ -239,6 +246,43 @@ class Lattice:
 
     def sync(self):
         _check(lib().rlbm_sync(self.h, _stream()))
+
+    # reverse mode --------------------------------------------------------
+    def adjoint_step(self, f_prev, lam_next, lam=None, dtau=None):
+        """lam_t = J_C(S f_prev)^T S^T lam_next; dtau (double [grid]) accumulates dL/dtau."""
+        lam = torch.empty_like(lam_next) if lam is None else lam
+        _check(lib().rlbm_adjoint_step(self.h, _ptr(f_prev), _ptr(lam_next), _ptr(lam), _ptr(dtau), _stream()))
+        return lam
+
+    def moments_vjp(self, f, gn=None, geps=None, gT=None, gU=None, lam=None):
+        """dL/dF of the streamed populations of f given dL/d(n, eps, T, U) (any may be None)."""
+        g = self.grid_shape
+
+        def dev(t, shape):
+            return None if t is None else self._dev64(t, shape)
+        gn, geps, gT = dev(gn, g), dev(geps, g), dev(gT, g)
+        gU = dev(gU, (self.d + 1,) + g)
+        fs = Fields(n=_ptr(gn), eps=_ptr(geps), T=_ptr(gT), U=_ptr(gU))
+        lam = self.new_state() if lam is None else lam
+        _check(lib().rlbm_moments_vjp(self.h, _ptr(f), ctypes.byref(fs), _ptr(lam), _stream()))
+        self._keep_vjp = (gn, geps, gT, gU)
+        return lam
+
+    def init_vjp(self, n0, T0, u0, lam1, noise=None, amp=0.0, dtau=None, want_n_T=False):
+        """dL/du0 (and dL/dn0, dL/dT0) of the initial condition given lam_1."""
+        g = self.grid_shape
+        n0 = self._dev64(n0, g)
+        T0 = self._dev64(T0, g)
+        u0 = self._dev64(u0, (self.d,) + g)
+        if noise is not None:
+            noise = self._dev64(noise, (self.Q,) + g)
+        du0 = torch.empty((self.d,) + g, dtype=torch.float64, device="cuda")
+        dn0 = torch.empty(g, dtype=torch.float64, device="cuda") if want_n_T else None
+        dT0 = torch.empty(g, dtype=torch.float64, device="cuda") if want_n_T else None
+        _check(lib().rlbm_init_vjp(self.h, _ptr(n0), _ptr(T0), _ptr(u0), _ptr(noise), float(amp), _ptr(lam1),
+                                   _ptr(du0), _ptr(dn0), _ptr(dT0), _ptr(dtau), _stream()))
+        self._keep_vjp = (n0, T0, u0, noise)
+        return (du0, dn0, dT0) if want_n_T else du0
 
     # launch variants -----------------------------------------------------
     @property
