@@ -37,6 +37,9 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--no-copy", action="store_true")
+    ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--batch-count", type=int, default=256)
     return ap.parse_args()
 
 
@@ -108,6 +111,110 @@ def copy_bandwidth(nbytes, reps=20):
     torch.cuda.synchronize()
     t = e0.elapsed_time(e1) / reps * 1e-3
     return 2 * nbytes / t / 1e9
+
+
+def batched(count, warmup, steps):
+    """Many lattices (sides 64..512, tau in [0.6, 2], zeta in [0, 5], seed 4; Taylor-Green u0 = 0.05):
+    one persistent launch per step (graph-replayed) against one launch per lattice per step."""
+    import torch
+    import workloads as W
+    from paper_1909_04502_amd import rlbm as R
+    specs = W.batch_specs(count, seed=4)
+    b = R.Batch(specs, order=3, storage="f64")
+    ns, Ts, us = [], [], []
+    for i, sp in enumerate(specs):
+        n, T, u = W.taylor_green_2d(*sp["extent"], 0.05, density_sigma=1e-3, seed=100 + i)
+        ns.append(n), Ts.append(T), us.append(u)
+    fa = b.init(ns, Ts, us)
+    fb = b.new_state()
+    del ns, Ts, us
+    tune = b.autotune(fa, fb, steps=4)
+    stream = torch.cuda.current_stream()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    res = {}
+    for graph in (True, False):
+        b.step(fa, fb, warmup, graph=graph)
+        b.step(fa, fb, steps, graph=graph)          # captures (graph) outside the timed region
+        torch.cuda.synchronize()
+        e0.record(stream)
+        b.step(fa, fb, steps, graph=graph)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        res["graph" if graph else "eager"] = e0.elapsed_time(e1) / steps * 1e-3
+    b.sync()
+    # one launch per lattice per step, the same kernels' solo path
+    views = [(m, b.view(fa, l), b.view(fb, l)) for l, m in enumerate(b.members)]
+    ps = max(2, steps // 5)
+    for m, va, vb in views:
+        m.step(va, vb, 2)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(ps):
+        for m, va, vb in views:
+            m.step(va, vb, 1)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    t_solo = e0.elapsed_time(e1) / ps * 1e-3
+    b.sync()
+    sites = b.total_sites
+    Q = b.Q
+    t = res["graph"]
+    out = {"lattices": count, "sites": sites, "MLUPS": round(sites / t / 1e6, 2), "ms_per_step": round(t * 1e3, 4),
+           "eager_ms_per_step": round(res["eager"] * 1e3, 4),
+           "per_lattice_launches_ms_per_step": round(t_solo * 1e3, 4),
+           "speedup_vs_per_lattice": round(t_solo / t, 3),
+           "achieved_GBs": round(2 * Q * 8 * sites / t / 1e9, 1),
+           "frac": round(2 * Q * 8 * sites / t / 1e9 / HBM_PEAK_GBS, 4),
+           "variant": b.variant, "autotune_ms": [round(x, 4) for x in tune],
+           "workload": f"{count} lattices, sides U{{64..512}}, tau U[0.6,2], zeta U[0,5] (seed 4), N=3, f64"}
+    del b, fa, fb, views
+    torch.cuda.empty_cache()
+    return out
+
+
+def adjoint_leg(L, warmup, steps):
+    """Reverse step (rlbm_adjoint_step) against the forward step, 512 x 512 float-deviation storage with
+    a tau field; algorithmic bytes of the reverse step: read B_{t-1} and lam_{t+1}, write lam_t (3 Q s per
+    site) plus the dL/dtau accumulator (16 B per site)."""
+    import numpy as np
+    import torch
+    import workloads as W
+    from paper_1909_04502_amd import rlbm as R
+    n, T, u = W.taylor_green_2d(L, L, 0.1, density_sigma=1e-3, seed=2)
+    tau = torch.tensor(0.8 + 0.2 * np.random.default_rng(4).uniform(-1, 1, (L, L)))
+    lat = R.Lattice(d=2, zeta=1.0, order=3, extent=(L, L), storage="f32dev", tau=0.8, tau_field=tau)
+    fa = lat.init(torch.tensor(n), torch.tensor(T), torch.tensor(u))
+    fb = lat.new_state()
+    t_fwd = time_steps(lat, fa, fb, warmup, steps)
+    lam_a = torch.randn_like(fa) * 1e-3
+    lam_b = torch.empty_like(fa)
+    dtau = torch.zeros((L, L), dtype=torch.float64, device="cuda")
+    for _ in range(warmup):
+        lat.adjoint_step(fa, lam_a, lam_b, dtau)
+        lam_a, lam_b = lam_b, lam_a
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(steps):
+        lat.adjoint_step(fa, lam_a, lam_b, dtau)
+        lam_a, lam_b = lam_b, lam_a
+    e1.record(stream)
+    torch.cuda.synchronize()
+    lat.sync()
+    t_adj = e0.elapsed_time(e1) / steps * 1e-3
+    sites = L * L
+    Q = lat.Q
+    ab = (3 * Q * 4 + 16) * sites
+    out = {"workload": f"{L}x{L} zeta=1 N=3 f32dev with tau field", "forward_ms": round(t_fwd * 1e3, 5),
+           "adjoint_ms": round(t_adj * 1e3, 5), "adjoint_over_forward": round(t_adj / t_fwd, 3),
+           "adjoint_MLUPS": round(sites / t_adj / 1e6, 2), "adjoint_achieved_GBs": round(ab / t_adj / 1e9, 1),
+           "adjoint_frac": round(ab / t_adj / 1e9 / HBM_PEAK_GBS, 4)}
+    del lat, fa, fb, lam_a, lam_b
+    torch.cuda.empty_cache()
+    return out
 
 
 def cpu_baseline(seconds):
@@ -183,6 +290,10 @@ def main():
                                       "autotune_ms": [round(x, 5) for x in tune32] if tune32 else None}}
         del lat, fa, fb
         torch.cuda.empty_cache()
+    if not args.no_adjoint:
+        out["adjoint"] = adjoint_leg(512, args.warmup, args.steps)
+    if not args.no_batch:
+        out["batched"] = batched(args.batch_count, max(2, args.warmup // 4), max(4, args.steps // 10))
     if not args.no_copy:
         cb = copy_bandwidth(Q * 8 * sites)
         out["roofline"]["copy_GBs"] = round(cb, 1)

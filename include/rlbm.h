@@ -200,6 +200,40 @@ rlbm_status rlbm_init_vjp(rlbm_lattice *h, const double *n0, const double *T0, c
                           const double *noise, double noise_amp, const void *lam1, double *du0,
                           double *dn0, double *dT0, double *dtau_accum, hipStream_t stream);
 
+/* ----------------------------------------------------------------- batches
+ *
+ * Many independent 2D product-rule lattices (different extents, zeta and
+ * scalar tau; one order and storage) advanced by one persistent launch per
+ * step.  The state of a batch is one flat device buffer: lattice l owns the
+ * elements [elem_off[l], elem_off[l] + Q * sites_l) in its own SoA layout.
+ * Field arrays of a batch are concatenated per lattice: n0, T0, n, eps, T at
+ * site_off[l]; u0 as [2][sites_l] at 2 site_off[l]; U as [3][sites_l] at
+ * 3 site_off[l].  rlbm_batch_lattice exposes the member handles (their own
+ * rlbm_step is the per-lattice reference path). */
+typedef struct rlbm_batch rlbm_batch;   /* opaque */
+rlbm_status rlbm_batch_create(const rlbm_config *cfgs, int32_t nlat, rlbm_batch **out);
+rlbm_status rlbm_batch_destroy(rlbm_batch *b);
+rlbm_status rlbm_batch_layout(const rlbm_batch *b, int64_t *total_elems, int64_t *total_sites,
+                              int64_t *elem_off /* [nlat] or NULL */, int64_t *site_off /* [nlat] or NULL */);
+rlbm_status rlbm_batch_lattice(const rlbm_batch *b, int32_t l, rlbm_lattice **h);
+rlbm_status rlbm_batch_init(rlbm_batch *b, const double *n0, const double *T0, const double *u0, void *f_out,
+                            hipStream_t stream);
+/* nsteps steps of every lattice, ping-ponging as rlbm_step.  With use_graph != 0
+ * the launches are captured once into a HIP graph (cached for the same
+ * buffers, step count and variant) and the graph is replayed on `stream`. */
+rlbm_status rlbm_batch_step(rlbm_batch *b, void *f_a, void *f_b, int32_t nsteps, int32_t use_graph,
+                            hipStream_t stream);
+rlbm_status rlbm_batch_moments(rlbm_batch *b, const void *f, const rlbm_fields *out, hipStream_t stream);
+rlbm_status rlbm_batch_sync(rlbm_batch *b, hipStream_t stream);
+/* Batch launch variants: tile shape x persistent grid size.  rlbm_batch_autotune
+ * times each on the caller's state (an even number of steps per variant, so the
+ * evolved state ends in f_a) and keeps the fastest. */
+int32_t rlbm_batch_variant_count(void);
+rlbm_status rlbm_batch_set_variant(rlbm_batch *b, int32_t variant);
+rlbm_status rlbm_batch_get_variant(const rlbm_batch *b, int32_t *variant);
+rlbm_status rlbm_batch_autotune(rlbm_batch *b, void *f_a, void *f_b, int32_t steps, float *ms_out,
+                                hipStream_t stream);
+
 /* ------------------------------------------------------- launch variants */
 
 /* The step kernel has rlbm_variant_count() launch variants (block shape,

@@ -5,6 +5,7 @@
 #include <cstring>
 #include <new>
 #include <string>
+#include <vector>
 
 #include "../../include/rlbm.h"
 #include "kernels.h"
@@ -19,6 +20,24 @@ struct rlbm_lattice {
   int variant = 1;
   int64_t sites = 0;
   std::string last_error;
+};
+
+struct rlbm_batch {
+  std::vector<rlbm_lattice *> lats;
+  std::vector<int64_t> elem_off, site_off;
+  int64_t total_elems = 0, total_sites = 0;
+  rlbm::Tables *d_tabs = nullptr;
+  int64_t *d_off = nullptr;
+  int2 *d_tiles = nullptr;
+  int ntiles = 0;
+  int *d_err = nullptr;
+  int stencil = 0, order = 0, storage = 0, elem = 8;
+  int variant = 0;
+  // cached launch graph of the last (f_a, f_b, nsteps, variant)
+  hipStream_t cap_stream = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  const void *g_fa = nullptr, *g_fb = nullptr;
+  int g_n = -1, g_variant = -1;
 };
 
 namespace {
@@ -309,6 +328,267 @@ rlbm_status rlbm_init_vjp(rlbm_lattice *h, const double *n0, const double *T0, c
 }
 
 int32_t rlbm_variant_count(void) { return rlbm::kNumVariants; }
+
+// ------------------------------------------------------------------ batches
+static const int kBatchGrid[3] = {512, 1024, 2048};
+static const int kNumBatchVariants = 12;   // 4 tile shapes x 3 grid sizes
+
+static hipError_t batch_build_tiles(rlbm_batch *b) {
+  const int tv = b->variant % 4;
+  const int bx = rlbm::kBatchTiles[tv][0], by = rlbm::kBatchTiles[tv][1];
+  std::vector<int2> tl;
+  for (size_t l = 0; l < b->lats.size(); ++l) {
+    const int nx = (int)b->lats[l]->cfg.extent[0], ny = (int)b->lats[l]->cfg.extent[1];
+    const int n = ((nx + bx - 1) / bx) * ((ny + by - 1) / by);
+    for (int t = 0; t < n; ++t) tl.push_back(make_int2((int)l, t));
+  }
+  if (b->d_tiles) (void)hipFree(b->d_tiles);
+  b->d_tiles = nullptr;
+  b->ntiles = (int)tl.size();
+  hipError_t he = hipMalloc(&b->d_tiles, sizeof(int2) * tl.size());
+  if (he == hipSuccess) he = hipMemcpy(b->d_tiles, tl.data(), sizeof(int2) * tl.size(), hipMemcpyHostToDevice);
+  return he;
+}
+
+rlbm_status rlbm_batch_destroy(rlbm_batch *b) {
+  if (!b) return RLBM_OK;
+  if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
+  if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
+  for (auto *h : b->lats) rlbm_destroy(h);
+  if (b->d_tabs) (void)hipFree(b->d_tabs);
+  if (b->d_off) (void)hipFree(b->d_off);
+  if (b->d_tiles) (void)hipFree(b->d_tiles);
+  if (b->d_err) (void)hipFree(b->d_err);
+  delete b;
+  return RLBM_OK;
+}
+
+rlbm_status rlbm_batch_create(const rlbm_config *cfgs, int32_t nlat, rlbm_batch **out) {
+  if (!cfgs || !out || nlat < 1) return fail(RLBM_ERR_INVALID_ARG, "bad argument");
+  *out = nullptr;
+  for (int l = 0; l < nlat; ++l) {
+    const rlbm_config &c = cfgs[l];
+    if (c.model.d != 2 || c.model.kind != RLBM_QUAD_PRODUCT || c.model.order != cfgs[0].model.order ||
+        c.storage != cfgs[0].storage)
+      return fail(RLBM_ERR_UNSUPPORTED, "a batch holds 2D product-rule lattices of one order and storage");
+    if (c.tau_field != nullptr) return fail(RLBM_ERR_UNSUPPORTED, "batched lattices take a scalar tau");
+  }
+  rlbm_batch *b = new (std::nothrow) rlbm_batch();
+  if (!b) return fail(RLBM_ERR_DEVICE, "out of host memory");
+  b->stencil = rlbm::ST_PROD2D;
+  b->order = cfgs[0].model.order;
+  b->storage = cfgs[0].storage;
+  b->elem = b->storage == RLBM_F64 ? 8 : 4;
+  for (int l = 0; l < nlat; ++l) {
+    rlbm_lattice *h = nullptr;
+    rlbm_status st = rlbm_create(&cfgs[l], &h);
+    if (st != RLBM_OK) {
+      rlbm_batch_destroy(b);
+      return st;
+    }
+    b->lats.push_back(h);
+    b->elem_off.push_back(b->total_elems);
+    b->site_off.push_back(b->total_sites);
+    b->total_elems += (int64_t)h->quad.Q * h->sites;
+    b->total_sites += h->sites;
+  }
+  hipError_t he = hipMalloc(&b->d_tabs, sizeof(rlbm::Tables) * nlat);
+  for (int l = 0; he == hipSuccess && l < nlat; ++l)
+    he = hipMemcpy(b->d_tabs + l, b->lats[l]->d_tables, sizeof(rlbm::Tables), hipMemcpyDeviceToDevice);
+  if (he == hipSuccess) he = hipMalloc(&b->d_off, sizeof(int64_t) * nlat);
+  if (he == hipSuccess)
+    he = hipMemcpy(b->d_off, b->elem_off.data(), sizeof(int64_t) * nlat, hipMemcpyHostToDevice);
+  if (he == hipSuccess) he = hipMalloc(&b->d_err, sizeof(int));
+  if (he == hipSuccess) he = hipMemset(b->d_err, 0, sizeof(int));
+  if (he == hipSuccess) he = batch_build_tiles(b);
+  if (he == hipSuccess) he = hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking);
+  if (he == hipSuccess) he = hipDeviceSynchronize();
+  if (he != hipSuccess) {
+    rlbm_batch_destroy(b);
+    return fail(RLBM_ERR_DEVICE, hipGetErrorString(he));
+  }
+  *out = b;
+  return RLBM_OK;
+}
+
+rlbm_status rlbm_batch_layout(const rlbm_batch *b, int64_t *total_elems, int64_t *total_sites, int64_t *elem_off,
+                              int64_t *site_off) {
+  if (!b) return fail(RLBM_ERR_INVALID_ARG, "null argument");
+  if (total_elems) *total_elems = b->total_elems;
+  if (total_sites) *total_sites = b->total_sites;
+  for (size_t l = 0; l < b->lats.size(); ++l) {
+    if (elem_off) elem_off[l] = b->elem_off[l];
+    if (site_off) site_off[l] = b->site_off[l];
+  }
+  return RLBM_OK;
+}
+
+rlbm_status rlbm_batch_lattice(const rlbm_batch *b, int32_t l, rlbm_lattice **h) {
+  if (!b || !h || l < 0 || l >= (int32_t)b->lats.size()) return fail(RLBM_ERR_INVALID_ARG, "bad argument");
+  *h = b->lats[l];
+  return RLBM_OK;
+}
+
+rlbm_status rlbm_batch_init(rlbm_batch *b, const double *n0, const double *T0, const double *u0, void *f_out,
+                            hipStream_t stream) {
+  if (!b || !n0 || !T0 || !u0 || !f_out) return fail(RLBM_ERR_INVALID_ARG, "null argument");
+  for (size_t l = 0; l < b->lats.size(); ++l) {
+    const int64_t so = b->site_off[l];
+    rlbm_status st = rlbm_init(b->lats[l], n0 + so, T0 + so, u0 + 2 * so, nullptr, 0.0,
+                               (char *)f_out + b->elem_off[l] * b->elem, nullptr, stream);
+    if (st != RLBM_OK) return st;
+  }
+  return RLBM_OK;
+}
+
+rlbm_status rlbm_batch_moments(rlbm_batch *b, const void *f, const rlbm_fields *out, hipStream_t stream) {
+  if (!b || !f || !out) return fail(RLBM_ERR_INVALID_ARG, "null argument");
+  for (size_t l = 0; l < b->lats.size(); ++l) {
+    const int64_t so = b->site_off[l];
+    rlbm_fields o;
+    o.n = out->n ? out->n + so : nullptr;
+    o.eps = out->eps ? out->eps + so : nullptr;
+    o.T = out->T ? out->T + so : nullptr;
+    o.U = out->U ? out->U + 3 * so : nullptr;
+    rlbm_status st = rlbm_moments(b->lats[l], (const char *)f + b->elem_off[l] * b->elem, &o, stream);
+    if (st != RLBM_OK) return st;
+  }
+  return RLBM_OK;
+}
+
+static hipError_t batch_enqueue(rlbm_batch *b, void *f_a, void *f_b, int32_t nsteps, hipStream_t stream) {
+  rlbm::BatchArgs a;
+  a.stencil = b->stencil;
+  a.order = b->order;
+  a.storage = b->storage;
+  a.tile = b->variant % 4;
+  a.blocks = kBatchGrid[b->variant / 4];
+  a.tabs = b->d_tabs;
+  a.elem_off = b->d_off;
+  a.tiles = b->d_tiles;
+  a.ntiles = b->ntiles;
+  a.err = b->d_err;
+  a.stream = stream;
+  for (int32_t s = 0; s < nsteps; ++s) {
+    a.fin = (s & 1) ? f_b : f_a;
+    a.fout = (s & 1) ? f_a : f_b;
+    hipError_t he = rlbm::launch_batch(a);
+    if (he != hipSuccess) return he;
+  }
+  return hipSuccess;
+}
+
+rlbm_status rlbm_batch_step(rlbm_batch *b, void *f_a, void *f_b, int32_t nsteps, int32_t use_graph,
+                            hipStream_t stream) {
+  if (!b || !f_a || !f_b || nsteps < 0) return fail(RLBM_ERR_INVALID_ARG, "bad argument");
+  const int64_t bytes = b->total_elems * b->elem;
+  const char *pa = (const char *)f_a, *pb = (const char *)f_b;
+  if (pa < pb + bytes && pb < pa + bytes) return fail(RLBM_ERR_INVALID_ARG, "f_a and f_b overlap");
+  if (nsteps == 0) return RLBM_OK;
+  hipError_t he = hipSuccess;
+  if (!use_graph) {
+    he = batch_enqueue(b, f_a, f_b, nsteps, stream);
+  } else {
+    if (!(b->gexec && b->g_fa == f_a && b->g_fb == f_b && b->g_n == nsteps && b->g_variant == b->variant)) {
+      if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
+      b->gexec = nullptr;
+      hipGraph_t g = nullptr;
+      he = hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal);
+      if (he == hipSuccess) {
+        hipError_t he2 = batch_enqueue(b, f_a, f_b, nsteps, b->cap_stream);
+        he = hipStreamEndCapture(b->cap_stream, &g);
+        if (he == hipSuccess) he = he2;
+      }
+      if (he == hipSuccess) he = hipGraphInstantiate(&b->gexec, g, nullptr, nullptr, 0);
+      if (g) (void)hipGraphDestroy(g);
+      if (he == hipSuccess) {
+        b->g_fa = f_a;
+        b->g_fb = f_b;
+        b->g_n = nsteps;
+        b->g_variant = b->variant;
+      }
+    }
+    if (he == hipSuccess) he = hipGraphLaunch(b->gexec, stream);
+  }
+  return he == hipSuccess ? RLBM_OK : fail(RLBM_ERR_DEVICE, hipGetErrorString(he));
+}
+
+rlbm_status rlbm_batch_sync(rlbm_batch *b, hipStream_t stream) {
+  if (!b) return fail(RLBM_ERR_INVALID_ARG, "null argument");
+  hipError_t he = hipStreamSynchronize(stream);
+  if (he != hipSuccess) return fail(RLBM_ERR_DEVICE, hipGetErrorString(he));
+  int flag = 0;
+  he = hipMemcpy(&flag, b->d_err, sizeof(int), hipMemcpyDeviceToHost);
+  if (he != hipSuccess) return fail(RLBM_ERR_DEVICE, hipGetErrorString(he));
+  rlbm_status st = RLBM_OK;
+  for (auto *h : b->lats) {
+    rlbm_status s2 = rlbm_sync(h, stream);
+    if (s2 != RLBM_OK) st = s2;
+  }
+  if (flag) {
+    int zero = 0;
+    (void)hipMemcpy(b->d_err, &zero, sizeof(int), hipMemcpyHostToDevice);
+    return fail(RLBM_ERR_NONPHYSICAL, "a kernel met a non-physical state");
+  }
+  return st;
+}
+
+int32_t rlbm_batch_variant_count(void) { return kNumBatchVariants; }
+
+rlbm_status rlbm_batch_set_variant(rlbm_batch *b, int32_t v) {
+  if (!b || v < 0 || v >= kNumBatchVariants) return fail(RLBM_ERR_INVALID_ARG, "bad variant");
+  const int old_tile = b->variant % 4;
+  b->variant = v;
+  if (v % 4 != old_tile) {
+    hipError_t he = batch_build_tiles(b);
+    if (he != hipSuccess) return fail(RLBM_ERR_DEVICE, hipGetErrorString(he));
+  }
+  return RLBM_OK;
+}
+
+rlbm_status rlbm_batch_get_variant(const rlbm_batch *b, int32_t *v) {
+  if (!b || !v) return fail(RLBM_ERR_INVALID_ARG, "null argument");
+  *v = b->variant;
+  return RLBM_OK;
+}
+
+rlbm_status rlbm_batch_autotune(rlbm_batch *b, void *f_a, void *f_b, int32_t steps, float *ms_out,
+                                hipStream_t stream) {
+  // Times every variant on the caller's buffers: f_a must hold a valid state; f_a and f_b are
+  // overwritten by an even number of steps per variant (the result stays in f_a).
+  if (!b || !f_a || !f_b || steps < 1) return fail(RLBM_ERR_INVALID_ARG, "bad argument");
+  const int ev = 2 * ((steps + 1) / 2);
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  hipError_t he = hipEventCreate(&e0);
+  if (he == hipSuccess) he = hipEventCreate(&e1);
+  float best = 1e30f;
+  int best_v = b->variant;
+  for (int v = 0; he == hipSuccess && v < kNumBatchVariants; ++v) {
+    if (rlbm_batch_set_variant(b, v) != RLBM_OK) {
+      he = hipErrorUnknown;
+      break;
+    }
+    he = batch_enqueue(b, f_a, f_b, 2, stream);
+    if (he == hipSuccess) he = hipEventRecord(e0, stream);
+    if (he == hipSuccess) he = batch_enqueue(b, f_a, f_b, ev, stream);
+    if (he == hipSuccess) he = hipEventRecord(e1, stream);
+    if (he == hipSuccess) he = hipEventSynchronize(e1);
+    float ms = 0.0f;
+    if (he == hipSuccess) he = hipEventElapsedTime(&ms, e0, e1);
+    ms /= ev;
+    if (ms_out) ms_out[v] = ms;
+    if (he == hipSuccess && ms < best) {
+      best = ms;
+      best_v = v;
+    }
+  }
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  if (he != hipSuccess) return fail(RLBM_ERR_DEVICE, hipGetErrorString(he));
+  rlbm_status st = rlbm_batch_set_variant(b, best_v);
+  if (st != RLBM_OK) return st;
+  return rlbm_batch_sync(b, stream);
+}
 
 rlbm_status rlbm_set_variant(rlbm_lattice *h, int32_t v) {
   if (!h || v < 0 || v >= rlbm::kNumVariants) return fail(RLBM_ERR_INVALID_ARG, "bad variant");

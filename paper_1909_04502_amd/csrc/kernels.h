@@ -66,4 +66,21 @@ struct AdjointArgs {
 // reverse-mode kernels (2D product rules, periodic boundaries)
 hipError_t launch_adjoint(const AdjointArgs &a);
 
+// Batched step: tile shapes (0: 64x4, 1: 64x2, 2: 128x2, 3: 32x8) and grid sizes
+constexpr int kBatchTiles[4][2] = {{64, 4}, {64, 2}, {128, 2}, {32, 8}};
+struct BatchArgs {
+  int stencil = 0, order = 0, storage = 0;
+  int tile = 0;                  // index into kBatchTiles
+  int blocks = 0;                // persistent grid size (multiple of 8)
+  const Tables *tabs = nullptr;  // [nlat] device
+  const int64_t *elem_off = nullptr;
+  const int2 *tiles = nullptr;   // [ntiles] (lattice, tile index)
+  int ntiles = 0;
+  const void *fin = nullptr;
+  void *fout = nullptr;
+  int *err = nullptr;
+  hipStream_t stream = 0;
+};
+hipError_t launch_batch(const BatchArgs &a);
+
 }  // namespace rlbm

@@ -108,6 +108,30 @@ def lib():
     L.rlbm_get_variant.argtypes = [c_void_p, POINTER(c_int32)]
     L.rlbm_autotune.restype = st
     L.rlbm_autotune.argtypes = [c_void_p, c_int32, c_void_p, c_void_p]
+    L.rlbm_batch_create.restype = st
+    L.rlbm_batch_create.argtypes = [POINTER(Config), c_int32, POINTER(c_void_p)]
+    L.rlbm_batch_destroy.restype = st
+    L.rlbm_batch_destroy.argtypes = [c_void_p]
+    L.rlbm_batch_layout.restype = st
+    L.rlbm_batch_layout.argtypes = [c_void_p, POINTER(c_int64), POINTER(c_int64), c_void_p, c_void_p]
+    L.rlbm_batch_lattice.restype = st
+    L.rlbm_batch_lattice.argtypes = [c_void_p, c_int32, POINTER(c_void_p)]
+    L.rlbm_batch_init.restype = st
+    L.rlbm_batch_init.argtypes = [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]
+    L.rlbm_batch_step.restype = st
+    L.rlbm_batch_step.argtypes = [c_void_p, c_void_p, c_void_p, c_int32, c_int32, c_void_p]
+    L.rlbm_batch_moments.restype = st
+    L.rlbm_batch_moments.argtypes = [c_void_p, c_void_p, POINTER(Fields), c_void_p]
+    L.rlbm_batch_sync.restype = st
+    L.rlbm_batch_sync.argtypes = [c_void_p, c_void_p]
+    L.rlbm_batch_variant_count.restype = c_int32
+    L.rlbm_batch_variant_count.argtypes = []
+    L.rlbm_batch_set_variant.restype = st
+    L.rlbm_batch_set_variant.argtypes = [c_void_p, c_int32]
+    L.rlbm_batch_get_variant.restype = st
+    L.rlbm_batch_get_variant.argtypes = [c_void_p, POINTER(c_int32)]
+    L.rlbm_batch_autotune.restype = st
+    L.rlbm_batch_autotune.argtypes = [c_void_p, c_void_p, c_void_p, c_int32, c_void_p, c_void_p]
     _lib = L
     _check_single_hip_runtime()
     return L
@@ -148,8 +172,9 @@ class Lattice:
     """One lattice: handle of the C ABI plus the torch-side shapes."""
 
     def __init__(self, d=2, zeta=1.0, order=3, kind="product", extent=(64, 64), bc=None, storage="f64",
-                 tau=0.8, tau_field=None, n_ref=1.0):
+                 tau=0.8, tau_field=None, n_ref=1.0, _handle=None):
         L = lib()
+        self._owned = _handle is None
         self.d = d
         self.extent = tuple(int(e) for e in extent)
         if bc is None:
@@ -172,8 +197,11 @@ class Lattice:
         cfg.tau_field = tau_field.data_ptr() if tau_field is not None else None
         cfg.n_ref = float(n_ref)
         self.cfg = cfg
-        h = c_void_p()
-        _check(L.rlbm_create(ctypes.byref(cfg), ctypes.byref(h)))
+        if _handle is None:
+            h = c_void_p()
+            _check(L.rlbm_create(ctypes.byref(cfg), ctypes.byref(h)))
+        else:
+            h = _handle                     # a member of a batch: the batch owns it
         self.h = h
         info = Info()
         _check(L.rlbm_get_info(h, ctypes.byref(info)))
@@ -184,9 +212,9 @@ class Lattice:
 
     def __del__(self):
         h = getattr(self, "h", None)
-        if h is not None and h.value is not None and _lib is not None:
+        if getattr(self, "_owned", False) and h is not None and h.value is not None and _lib is not None:
             _lib.rlbm_destroy(h)
-            self.h = None
+        self.h = None
 
     # ------------------------------------------------------------------
     def new_state(self):
@@ -300,4 +328,120 @@ class Lattice:
         n = lib().rlbm_variant_count()
         ms = (ctypes.c_float * n)()
         _check(lib().rlbm_autotune(self.h, int(steps), ms, _stream()))
+        return list(ms)
+
+
+class Batch:
+    """Many 2D product-rule lattices advanced by one persistent launch per step (rlbm_batch_*).
+
+    ``specs`` is a list of dicts with keys extent, zeta, tau (and optional bc).
+    The state is one flat tensor of ``total_elems`` elements; ``view(f, l)``
+    is lattice l's (Q, ny, nx) part of it.  ``member(l)`` is a non-owning
+    Lattice over the same handle (its step is the per-lattice launch path)."""
+
+    def __init__(self, specs, order=3, storage="f64"):
+        L = lib()
+        self.storage = storage
+        self.dtype = torch.float64 if storage == "f64" else torch.float32
+        n = len(specs)
+        cfgs = (Config * n)()
+        self.specs = [dict(s) for s in specs]
+        for i, sp in enumerate(self.specs):
+            c = cfgs[i]
+            c.model = _model(2, sp["zeta"], order, "product")
+            ext = (int(sp["extent"][0]), int(sp["extent"][1]), 1)
+            bc = sp.get("bc", ("periodic", "periodic"))
+            for a in range(3):
+                c.extent[a] = ext[a]
+                c.bc[a] = BC[bc[a]] if a < 2 else 0
+            c.storage = STORAGE[storage]
+            c.tau = float(sp["tau"])
+            c.tau_field = None
+            c.n_ref = 1.0
+        h = c_void_p()
+        _check(L.rlbm_batch_create(cfgs, n, ctypes.byref(h)))
+        self.h = h
+        self.count = n
+        te, ts = c_int64(0), c_int64(0)
+        eo = (c_int64 * n)()
+        so = (c_int64 * n)()
+        _check(L.rlbm_batch_layout(h, ctypes.byref(te), ctypes.byref(ts), eo, so))
+        self.total_elems, self.total_sites = te.value, ts.value
+        self.elem_off, self.site_off = list(eo), list(so)
+        self.members = []
+        for i, sp in enumerate(self.specs):
+            mh = c_void_p()
+            _check(L.rlbm_batch_lattice(h, i, ctypes.byref(mh)))
+            self.members.append(Lattice(d=2, zeta=sp["zeta"], order=order, extent=sp["extent"],
+                                        bc=sp.get("bc"), storage=storage, tau=sp["tau"], _handle=mh))
+        self.Q = self.members[0].Q
+
+    def __del__(self):
+        h = getattr(self, "h", None)
+        for m in getattr(self, "members", []):
+            m.h = None
+        if h is not None and h.value is not None and _lib is not None:
+            _lib.rlbm_batch_destroy(h)
+        self.h = None
+
+    def new_state(self):
+        return torch.empty((self.total_elems,), dtype=self.dtype, device="cuda")
+
+    def view(self, f, l):
+        nx, ny = self.members[l].extent
+        o = self.elem_off[l]
+        return f[o:o + self.Q * nx * ny].view(self.Q, ny, nx)
+
+    def init(self, n0s, T0s, u0s, out=None):
+        """Initial post-collision state from per-lattice fields (lists of [ny, nx] / [2, ny, nx] arrays)."""
+        cat = lambda xs: torch.cat([torch.as_tensor(x, dtype=torch.float64).reshape(-1) for x in xs]).to("cuda")
+        n0, T0, u0 = cat(n0s), cat(T0s), cat(u0s)
+        assert n0.numel() == self.total_sites and u0.numel() == 2 * self.total_sites
+        out = self.new_state() if out is None else out
+        _check(lib().rlbm_batch_init(self.h, _ptr(n0), _ptr(T0), _ptr(u0), _ptr(out), _stream()))
+        self._keep = (n0, T0, u0)
+        return out
+
+    def step(self, f_a, f_b, nsteps, graph=True):
+        assert f_a.dtype == self.dtype and f_b.dtype == self.dtype
+        assert f_a.numel() == self.total_elems and f_b.numel() == self.total_elems
+        _check(lib().rlbm_batch_step(self.h, _ptr(f_a), _ptr(f_b), int(nsteps), int(bool(graph)), _stream()))
+        return f_b if nsteps % 2 == 1 else f_a
+
+    def moments(self, f):
+        """Per-lattice fields of the streamed state: list of dicts (views of concatenated arrays)."""
+        S = self.total_sites
+        dev = "cuda"
+        flat = {k: torch.empty(S, dtype=torch.float64, device=dev) for k in ("n", "eps", "T")}
+        flat["U"] = torch.empty(3 * S, dtype=torch.float64, device=dev)
+        fs = Fields(n=flat["n"].data_ptr(), eps=flat["eps"].data_ptr(), T=flat["T"].data_ptr(),
+                    U=flat["U"].data_ptr())
+        _check(lib().rlbm_batch_moments(self.h, _ptr(f), ctypes.byref(fs), _stream()))
+        out = []
+        for l, m in enumerate(self.members):
+            nx, ny = m.extent
+            so, ns = self.site_off[l], nx * ny
+            d = {k: flat[k][so:so + ns].view(ny, nx) for k in ("n", "eps", "T")}
+            d["U"] = flat["U"][3 * so:3 * so + 3 * ns].view(3, ny, nx)
+            out.append(d)
+        return out
+
+    def sync(self):
+        _check(lib().rlbm_batch_sync(self.h, _stream()))
+
+    @property
+    def variant(self):
+        v = c_int32(0)
+        _check(lib().rlbm_batch_get_variant(self.h, ctypes.byref(v)))
+        return v.value
+
+    @variant.setter
+    def variant(self, v):
+        _check(lib().rlbm_batch_set_variant(self.h, int(v)))
+
+    def autotune(self, f_a, f_b, steps=4):
+        """Time every batch variant on (f_a, f_b) (state ends in f_a); keep the fastest."""
+        n = lib().rlbm_batch_variant_count()
+        ms = (ctypes.c_float * n)()
+        _check(lib().rlbm_batch_autotune(self.h, _ptr(f_a), _ptr(f_b), int(steps), ms, _stream()))
         return list(ms)

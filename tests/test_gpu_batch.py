@@ -1,0 +1,145 @@
+"""Batched lattices (one persistent launch per step for many lattices).
+
+Each lattice of a batch must evolve exactly as it does alone (per-lattice
+launches of the same library) and as the oracle says; the graph-replayed
+path must equal the eagerly launched one on every replay.
+"""
+import numpy as np
+import pytest
+import torch
+
+import workloads as W
+from oracle import lattice as OL
+from oracle import quadrature as qd
+
+pytestmark = pytest.mark.gpu
+
+SPECS = [
+    {"extent": (64, 48), "zeta": 1.0, "tau": 0.8},
+    {"extent": (70, 33), "zeta": 0.0, "tau": 1.7},
+    {"extent": (5, 3), "zeta": 4.0, "tau": 0.6},
+    {"extent": (130, 9), "zeta": 2.5, "tau": 1.1, "bc": ("open", "periodic")},
+    {"extent": (1, 1), "zeta": 0.5, "tau": 2.0},
+    {"extent": (33, 65), "zeta": 5.0, "tau": 0.9, "bc": ("periodic", "open")},
+]
+
+
+def rel(a, b):
+    a = a.detach().cpu().to(torch.float64)
+    b = b.detach().cpu().to(torch.float64)
+    return ((a - b).abs().max() / b.abs().max()).item()
+
+
+def fields(specs, u0=0.08):
+    ns, Ts, us = [], [], []
+    for i, sp in enumerate(specs):
+        nx, ny = sp["extent"]
+        n, T, u = W.taylor_green_2d(nx, ny, u0, density_sigma=1e-3, seed=10 + i)
+        ns.append(n), Ts.append(T), us.append(u)
+    return ns, Ts, us
+
+
+def make(specs, storage="f64", order=3):
+    from paper_1909_04502_amd import rlbm as R
+    b = R.Batch(specs, order=order, storage=storage)
+    ns, Ts, us = fields(specs)
+    return b, ns, Ts, us
+
+
+@pytest.mark.parametrize("storage,order", [("f64", 3), ("f64", 2), ("f32dev", 3)])
+def test_batch_equals_each_lattice_alone(storage, order):
+    print(f"[case] batch vs solo {storage} N={order}", flush=True)
+    b, ns, Ts, us = make(SPECS, storage, order)
+    fa = b.init(ns, Ts, us)
+    f0 = fa.clone()
+    nsteps = 5
+    res = b.step(fa, b.new_state(), nsteps, graph=False)
+    b.sync()
+    tol = 1e-14 if storage == "f64" else 1e-6
+    for l, m in enumerate(b.members):
+        solo = m.step(b.view(f0, l).clone(), m.new_state(), nsteps)
+        m.sync()
+        assert rel(b.view(res, l), solo) < tol, l
+
+
+def test_batch_members_match_oracle():
+    print("[case] batch vs oracle", flush=True)
+    b, ns, Ts, us = make(SPECS)
+    fa = b.init(ns, Ts, us)
+    nsteps = 4
+    res = b.step(fa, b.new_state(), nsteps)
+    mom = b.moments(res)
+    b.sync()
+    for l in (0, 2, 3, 4, 5):
+        sp = SPECS[l]
+        bc = sp.get("bc", ("periodic", "periodic"))
+        ol = OL.Lattice(qd.product_2d(sp["zeta"], 3), sp["tau"], sp["extent"], bc=bc)
+        fs = ol.collide(ol.init(torch.tensor(ns[l]), torch.tensor(Ts[l]), torch.tensor(us[l])))
+        for _ in range(nsteps):
+            fs = ol.collide(ol.stream(fs))
+        assert rel(b.view(res, l), fs) < 1e-12, l
+        ref = ol.macro(ol.stream(fs))
+        for k in ("n", "eps", "T"):
+            assert rel(mom[l][k], ref[k]) < 1e-12, (l, k)
+
+
+def test_graph_replays_match_eager():
+    """Replays of the captured step graph, with eager work between them, equal eager launches."""
+    print("[case] batch graph replays", flush=True)
+    b, ns, Ts, us = make(SPECS)
+    f0 = b.init(ns, Ts, us)
+    ea, eb = f0.clone(), b.new_state()
+    ref = [f0.clone()]
+    for _ in range(3):
+        r = b.step(ea, eb, 3, graph=False)
+        ref.append(r.clone())
+        if r is not ea:
+            ea, eb = eb, ea
+    ga, gb = f0.clone(), b.new_state()
+    for rep in range(3):
+        r = b.step(ga, gb, 3, graph=True)       # same buffers and count: the cached graph
+        b.sync()
+        junk = torch.randn(1000, device="cuda").sum().item()   # eager work between replays
+        assert np.isfinite(junk)
+        assert rel(r, ref[rep + 1]) == 0.0, rep
+        if r is not ga:
+            ga.copy_(r)
+
+
+def test_batch_variants_agree_and_autotune():
+    from paper_1909_04502_amd import rlbm as R
+    b, ns, Ts, us = make(SPECS)
+    f0 = b.init(ns, Ts, us)
+    ref = None
+    for v in range(R.lib().rlbm_batch_variant_count()):
+        print(f"[case] batch variant {v}", flush=True)
+        b.variant = v
+        r = b.step(f0.clone(), b.new_state(), 3, graph=(v % 2 == 0))
+        b.sync()
+        if ref is None:
+            ref = r.cpu()
+        else:
+            assert rel(r, ref) < 1e-14, v
+    fa, fb = f0.clone(), b.new_state()
+    ms = b.autotune(fa, fb, steps=2)
+    assert len(ms) == R.lib().rlbm_batch_variant_count() and all(m > 0 for m in ms)
+    assert 0 <= b.variant < len(ms)
+
+
+def test_batch_workload_sampled():
+    """The batched benchmark workload (256 lattices, sides 64..512): each of a sample of
+    lattices equals its solo run after 3 steps."""
+    print("[case] batch workload", flush=True)
+    from paper_1909_04502_amd import rlbm as R
+    specs = W.batch_specs(256, seed=4)
+    b = R.Batch(specs, order=3, storage="f64")
+    ns, Ts, us = fields(specs, u0=0.05)
+    f0 = b.init(ns, Ts, us)
+    res = b.step(f0.clone(), b.new_state(), 3)
+    b.sync()
+    g = np.random.default_rng(1)
+    for l in g.choice(len(specs), 8, replace=False):
+        m = b.members[int(l)]
+        solo = m.step(b.view(f0, int(l)).clone(), m.new_state(), 3)
+        m.sync()
+        assert rel(b.view(res, int(l)), solo) < 1e-14, int(l)

@@ -67,3 +67,27 @@ def test_create_validates_before_touching_the_device(rlbm_lib):
     cfg.storage = 7
     assert rlbm_lib.rlbm_create(ctypes.byref(cfg), ctypes.byref(h)) == R.ERR_INVALID_ARG
     assert rlbm_lib.rlbm_step(None, None, None, 1, None, None) == R.ERR_INVALID_ARG
+
+
+def test_batch_create_validates_before_touching_the_device(rlbm_lib):
+    """Mixed orders, storages, 3D or product/UR mixes and tau fields are refused up front."""
+    from paper_1909_04502_amd import rlbm as R
+
+    def cfg(d=2, order=3, kind=1, storage=0, tau_field=None):
+        c = R.Config()
+        c.model = R.Model(d=d, order=order, kind=kind, pad_=0, zeta=1.0)
+        c.extent[0], c.extent[1], c.extent[2] = 8, 8, (8 if d == 3 else 1)
+        c.storage = storage
+        c.tau = 0.8
+        c.tau_field = tau_field
+        c.n_ref = 1.0
+        return c
+
+    h = ctypes.c_void_p()
+    for pair in [(cfg(), cfg(order=2)), (cfg(), cfg(storage=1)), (cfg(d=3), cfg(d=3)),
+                 (cfg(kind=0, order=2), cfg(kind=0, order=2)), (cfg(), cfg(tau_field=1024))]:
+        arr = (R.Config * 2)(*pair)
+        st = rlbm_lib.rlbm_batch_create(arr, 2, ctypes.byref(h))
+        assert st == R.ERR_UNSUPPORTED
+    assert rlbm_lib.rlbm_batch_create(None, 2, ctypes.byref(h)) == R.ERR_INVALID_ARG
+    assert rlbm_lib.rlbm_batch_variant_count() == 12

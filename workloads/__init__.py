@@ -59,5 +59,11 @@ def batch_lattices(count: int, seed: int, side_range=(64, 512), tau_range=(0.6, 
     return sides, taus, zetas
 
 
+def batch_specs(count: int, seed: int, **kw):
+    """batch_lattices as a list of {extent: (side, side), tau, zeta} dicts."""
+    sides, taus, zetas = batch_lattices(count, seed, **kw)
+    return [{"extent": (int(s), int(s)), "tau": float(t), "zeta": float(z)} for s, t, z in zip(sides, taus, zetas)]
+
+
 def random_field(shape, seed: int, lo: float = -1.0, hi: float = 1.0) -> np.ndarray:
     return rng(seed).uniform(lo, hi, size=tuple(shape))
