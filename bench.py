@@ -40,6 +40,8 @@ def parse():
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--batch-count", type=int, default=256)
+    ap.add_argument("--no-3d", action="store_true")
+    ap.add_argument("--size-3d", type=int, default=256)
     return ap.parse_args()
 
 
@@ -217,6 +219,31 @@ def adjoint_leg(L, warmup, steps):
     return out
 
 
+def shock_tube_3d(L, warmup, steps, autotune=True):
+    """3D shock tube: zeta = 1, N = 3, Q = 104, L^3 with open x and periodic y, z, tau = 0.6, left state
+    n = 8/3, T = 1.5 for x < L/2, right n = 1, T = 1, u = 0; float-deviation storage (832 B per site)."""
+    import torch
+    import workloads as W
+    from paper_1909_04502_amd import rlbm as R
+    n, T, u = W.riemann_3d(L, L, L, L // 2, 8.0 / 3.0, 1.5, 1.0, 1.0)
+    lat = R.Lattice(d=3, zeta=1.0, order=3, extent=(L, L, L), bc=("open", "periodic", "periodic"),
+                    storage="f32dev", tau=0.6)
+    tune = lat.autotune(steps=3) if autotune else None
+    fa = lat.init(torch.tensor(n), torch.tensor(T), torch.tensor(u))
+    del n, T, u
+    fb = lat.new_state()
+    t = time_steps(lat, fa, fb, warmup, steps)
+    sites = L ** 3
+    b = 2 * lat.Q * 4 * sites
+    out = {"workload": f"3D shock tube {L}^3, zeta=1 N=3 Q={lat.Q}, open x, tau=0.6, f32dev",
+           "MLUPS": round(sites / t / 1e6, 2), "ms_per_step": round(t * 1e3, 4),
+           "achieved_GBs": round(b / t / 1e9, 1), "frac": round(b / t / 1e9 / HBM_PEAK_GBS, 4),
+           "variant": lat.variant, "autotune_ms": [round(x, 4) for x in tune] if tune else None}
+    del lat, fa, fb
+    torch.cuda.empty_cache()
+    return out
+
+
 def cpu_baseline(seconds):
     """The FP64 oracle (as it stands) on a 128 x 128 lattice of the same workload, on this host's cores."""
     import torch
@@ -292,6 +319,9 @@ def main():
         torch.cuda.empty_cache()
     if not args.no_adjoint:
         out["adjoint"] = adjoint_leg(512, args.warmup, args.steps)
+    if not args.no_3d:
+        out["shock_tube_3d"] = shock_tube_3d(args.size_3d, max(2, args.warmup // 4), max(4, args.steps // 10),
+                                             not args.no_autotune)
     if not args.no_batch:
         out["batched"] = batched(args.batch_count, max(2, args.warmup // 4), max(4, args.steps // 10))
     if not args.no_copy:

@@ -172,7 +172,8 @@ __device__ __forceinline__ double cheb_r(const Tables *__restrict__ tb, double z
     b2 = b1;
     b1 = b0;
   }
-  return s * b1 - b2 + tb->cheb[0];
+  // the series fits h = r (z + 2) / z, which stays O(1) from z -> 0 (r ~ z/2) to z -> inf (r -> 1)
+  return (s * b1 - b2 + tb->cheb[0]) * (z / (z + 2.0));
 }
 
 __device__ __forceinline__ bool temperature_3d(const Tables *__restrict__ tb, double e, double m, double &T,

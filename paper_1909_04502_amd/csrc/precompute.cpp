@@ -312,7 +312,7 @@ int build_eos_fit(double m, Tables &t, std::string &err) {
   for (int k = 0; k < n; ++k) {
     ld s = cosl(pi * (k + 0.5L) / n);
     ld z = expl(0.5L * (hi + lo) + 0.5L * (hi - lo) * s);
-    fk[k] = bessel_k(1.0L, z) / bessel_k(2.0L, z);
+    fk[k] = bessel_k(1.0L, z) / bessel_k(2.0L, z) * (z + 2.0L) / z;
   }
   for (int j = 0; j < n; ++j) {
     ld c = 0.0L;
@@ -328,7 +328,7 @@ int build_eos_fit(double m, Tables &t, std::string &err) {
   for (int k = 0; k <= 64; ++k) {
     ld s = -1.0L + 2.0L * k / 64.0L;
     ld z = expl(0.5L * (hi + lo) + 0.5L * (hi - lo) * s);
-    ld ref = bessel_k(1.0L, z) / bessel_k(2.0L, z);
+    ld ref = bessel_k(1.0L, z) / bessel_k(2.0L, z) * (z + 2.0L) / z;
     ld b1 = 0.0L, b2 = 0.0L;
     for (int j = n - 1; j >= 1; --j) {
       ld b0 = 2.0L * s * b1 - b2 + (ld)t.cheb[j];
@@ -336,7 +336,7 @@ int build_eos_fit(double m, Tables &t, std::string &err) {
       b1 = b0;
     }
     ld got = s * b1 - b2 + (ld)t.cheb[0];
-    if (fabsl(got - ref) > 4e-16L * fabsl(ref)) {
+    if (fabsl(got - ref) > 5e-16L * fabsl(ref)) {
       err = "equation-of-state fit failed";
       return RLBM_ERR_QUADRATURE;
     }

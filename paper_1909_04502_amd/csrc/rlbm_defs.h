@@ -145,7 +145,8 @@ struct Tables {
   double tau;                   // relaxation time (when no field)
   double inv_tau;
   double n_ref;
-  // EOS helper for d = 3: Chebyshev fit of r(z) = K1(z)/K2(z) on [z_lo, z_hi]
+  // EOS helper for d = 3: Chebyshev series in log z of h(z) = r(z) (z + 2) / z, r = K1(z)/K2(z),
+  // on [log z_lo, log z_hi]
   double cheb_lo, cheb_hi;
   double cheb[48];
   int32_t cheb_n, pad1;

@@ -91,3 +91,22 @@ def test_batch_create_validates_before_touching_the_device(rlbm_lib):
         assert st == R.ERR_UNSUPPORTED
     assert rlbm_lib.rlbm_batch_create(None, 2, ctypes.byref(h)) == R.ERR_INVALID_ARG
     assert rlbm_lib.rlbm_batch_variant_count() == 12
+
+
+@pytest.mark.parametrize("d,order,zetas", [(2, 3, (0.0, 0.01, 1.0, 5.0, 15.0)), (2, 2, (0.0, 30.0)),
+                                          (3, 3, (0.0, 0.01, 0.3, 1.0, 5.0, 10.0)), (3, 2, (0.05, 30.0))])
+def test_tables_build_over_the_zeta_range(rlbm_lib, d, order, zetas):
+    """Host precompute (quadrature, projection checks, the d = 3 Chebyshev EOS fit) succeeds over the
+    supported zeta range: without a device, rlbm_create then stops at the first device call."""
+    import torch
+    from paper_1909_04502_amd import rlbm as R
+    if torch.cuda.is_available():
+        pytest.skip("checks the host stage only where no device is present")
+    for z in zetas:
+        c = R.Config()
+        c.model = R.Model(d=d, order=order, kind=1, pad_=0, zeta=z)
+        c.extent[0], c.extent[1], c.extent[2] = 4, 4, (4 if d == 3 else 1)
+        c.tau, c.n_ref = 0.8, 1.0
+        h = ctypes.c_void_p()
+        st = rlbm_lib.rlbm_create(ctypes.byref(c), ctypes.byref(h))
+        assert st == R.ERR_DEVICE, (z, st, rlbm_lib.rlbm_last_error())
