@@ -142,6 +142,8 @@ rlbm_status rlbm_create(const rlbm_config *cfg, rlbm_lattice **out) {
   if (!h) return fail(RLBM_ERR_DEVICE, "out of host memory");
   h->cfg = *cfg;
   h->stencil = stencil_of(m);
+  // 3D kernels keep ~100 populations in registers: default to the occupancy-2 build, untiled order
+  if (m.d == 3) h->variant = 2;
   h->sites = sites;
   std::string err;
   int rc = rlbm::build_quadrature(m.d, m.zeta, m.order, m.kind, h->quad, err);

@@ -123,8 +123,9 @@ __device__ __forceinline__ bool landau_frame(const double (&T)[D + 1][D + 1], do
 // d = 2: G_2 = (z^2 + 3z + 3)/(z + 1), so e = eps/n solves
 //   2 T^2 + (2m - e) T + m^2 - e m = 0;
 // the positive root is taken in the form that avoids cancellation.
-// d = 3: G_3 = z r + 4 with r = K1/K2 from a Chebyshev fit in log z; Newton
-// iterations on e(T) = T (G_3(m/T) - 1), r' = r^2 + 3 r/z - 1.
+// d = 3: G_3 = z r + 4 with r = K1/K2 from a Chebyshev fit in log z, so that
+// e = eps/n = m r(m/T) + 3 T; its inverse T(e) is a second fit (built on the
+// host from the first by Newton's method).
 // ---------------------------------------------------------------------------
 // Macroscopic state of a site (double).
 template <int D>
@@ -159,23 +160,28 @@ __device__ __forceinline__ Ratios ratios_2d(double z) {
   return r;
 }
 
-__device__ __forceinline__ double cheb_r(const Tables *__restrict__ tb, double z, bool &inrange) {
-  // Clenshaw on s in [-1, 1], s affine in log z
-  const double lz = log(z);
-  double s = (2.0 * lz - (tb->cheb_lo + tb->cheb_hi)) / (tb->cheb_hi - tb->cheb_lo);
-  inrange = s >= -1.0 && s <= 1.0;
-  s = fmin(1.0, fmax(-1.0, s));
+__device__ __forceinline__ double cheb_eval(const double *__restrict__ c, double s) {
   double b1 = 0.0, b2 = 0.0;
-  const int n = tb->cheb_n;
-  for (int k = n - 1; k >= 1; --k) {
-    double b0 = 2.0 * s * b1 - b2 + tb->cheb[k];
+#pragma unroll 4
+  for (int k = kEosTerms - 1; k >= 1; --k) {
+    double b0 = 2.0 * s * b1 - b2 + c[k];
     b2 = b1;
     b1 = b0;
   }
-  // the series fits h = r (z + 2) / z, which stays O(1) from z -> 0 (r ~ z/2) to z -> inf (r -> 1)
-  return (s * b1 - b2 + tb->cheb[0]) * (z / (z + 2.0));
+  return s * b1 - b2 + c[0];
 }
 
+__device__ __forceinline__ double cheb_r(const Tables *__restrict__ tb, double z, bool &inrange) {
+  // Clenshaw on s in [-1, 1], s affine in log z; the series fits h = r (z + 2) / z, which stays
+  // O(1) from z -> 0 (r ~ z/2) to z -> inf (r -> 1)
+  double s = (2.0 * log(z) - (tb->cheb_lo + tb->cheb_hi)) / (tb->cheb_hi - tb->cheb_lo);
+  inrange = s >= -1.0 && s <= 1.0;
+  s = fmin(1.0, fmax(-1.0, s));
+  return cheb_eval(tb->cheb, s) * (z / (z + 2.0));
+}
+
+// d = 3: T from e = eps/n through the fitted inverse T = (e - m) u(log(e - m)), then r = K1/K2 at
+// z = m/T.  Both fits hold to ~1e-15 on T in [1/4, 4]; outside that range the site is flagged.
 __device__ __forceinline__ bool temperature_3d(const Tables *__restrict__ tb, double e, double m, double &T,
                                                double &r_out) {
   if (m == 0.0) {
@@ -183,28 +189,15 @@ __device__ __forceinline__ bool temperature_3d(const Tables *__restrict__ tb, do
     r_out = 0.0;
     return e > 0.0;
   }
-  // kinetic energy per particle e - m = T (G - 1 - z) lies in [1.5 T, 3 T]
-  T = (e - m) * (1.0 / 2.2);
-  bool ok = e > m;
-  double r = 0.0;
-#pragma unroll 1
-  for (int it = 0; it < 8; ++it) {
-    const double z = m / T;
-    bool inr;
-    r = cheb_r(tb, z, inr);
-    const double G = z * r + 4.0;
-    const double rp = r * r + 3.0 * r / z - 1.0;
-    const double f = T * (G - 1.0) - e;
-    const double fp = G - 1.0 - z * (r + z * rp);
-    T -= f / fp;
-  }
-  {
-    bool inr;
-    r = cheb_r(tb, m / T, inr);
-    ok = ok && inr && T > 0.0;
-  }
-  r_out = r;
-  return ok;
+  const double d = e - m;
+  bool ok = d > 0.0;
+  double s = (2.0 * log(d) - (tb->chebT_lo + tb->chebT_hi)) / (tb->chebT_hi - tb->chebT_lo);
+  ok = ok && s >= -1.0 && s <= 1.0;
+  s = fmin(1.0, fmax(-1.0, s));
+  T = d * cheb_eval(tb->chebT, s);
+  bool inr;
+  r_out = cheb_r(tb, m / T, inr);
+  return ok && inr && T > 0.0;
 }
 
 __device__ __forceinline__ Ratios ratios_3d(double z, double r) {
@@ -227,6 +220,18 @@ __device__ __forceinline__ Ratios ratios_3d(double z, double r) {
 //   deg 0: n r0 / T, deg 1: n U^a, deg 2: n T (r2 U^a U^b - eta^ab),
 //   deg 3: n T^2 (r3 U^a U^b U^c - r2 (eta^ab U^c + eta^ac U^b + eta^bc U^a)).
 // ---------------------------------------------------------------------------
+// The same moment for one basis index k (k a compile-time constant after unrolling).
+template <int D, int N>
+__device__ __forceinline__ double basis_moment(int k, double n, double T, const double (&U)[D + 1], const Ratios &r) {
+  using B = BasisDef<D, N>;
+  const int a = B::idx[k][0], b = B::idx[k][1], c = B::idx[k][2];
+  if (a < 0) return n * r.r0 / T;
+  if (b < 0) return n * U[a];
+  if (c < 0) return n * T * (r.r2 * U[a] * U[b] - eta_c(a, b));
+  return n * T * T *
+         (r.r3 * U[a] * U[b] * U[c] - r.r2 * (eta_c(a, b) * U[c] + eta_c(a, c) * U[b] + eta_c(b, c) * U[a]));
+}
+
 template <int D, int N>
 __device__ __forceinline__ void basis_moments(double n, double T, const double (&U)[D + 1], const Ratios &r,
                                               double (&M)[BasisDef<D, N>::NM]) {

@@ -22,8 +22,8 @@ struct Variant {
 };
 constexpr int kNumVariants = 10;
 constexpr Variant kVariants[kNumVariants] = {
-    {64, 4, 0, 0}, {64, 4, 0, 1}, {64, 4, 3, 1}, {64, 4, 4, 1}, {64, 2, 0, 1},
-    {64, 1, 0, 1}, {128, 2, 0, 1}, {32, 8, 0, 1}, {64, 4, 4, 0}, {64, 2, 4, 1}};
+    {64, 4, 0, 0}, {64, 4, 0, 1}, {64, 4, 2, 0}, {64, 4, 2, 1}, {64, 2, 0, 1},
+    {64, 1, 0, 1}, {128, 2, 0, 1}, {32, 8, 0, 1}, {64, 4, 3, 1}, {64, 2, 2, 0}};
 
 struct LaunchArgs {
   int op = 0;

@@ -423,11 +423,11 @@ static hipError_t launch_t(const LaunchArgs &a) {
   dim3 grid((unsigned)nb, 1, 1);
   switch (a.op) {
     case OP_STEP:
-      if (vr.occ == 3)
-        hipLaunchKernelGGL((k_step<ST, N, S, DEV, 3>), grid, block, 0, a.stream, a.tb, (const S *)a.fin,
+      if (vr.occ == 2)
+        hipLaunchKernelGGL((k_step<ST, N, S, DEV, 2>), grid, block, 0, a.stream, a.tb, (const S *)a.fin,
                            (S *)a.fout, a.tau_field, a.fields, a.err, vr.xcd);
-      else if (vr.occ == 4)
-        hipLaunchKernelGGL((k_step<ST, N, S, DEV, 4>), grid, block, 0, a.stream, a.tb, (const S *)a.fin,
+      else if (vr.occ == 3)
+        hipLaunchKernelGGL((k_step<ST, N, S, DEV, 3>), grid, block, 0, a.stream, a.tb, (const S *)a.fin,
                            (S *)a.fout, a.tau_field, a.fields, a.err, vr.xcd);
       else
         hipLaunchKernelGGL((k_step<ST, N, S, DEV, 0>), grid, block, 0, a.stream, a.tb, (const S *)a.fin,

@@ -302,42 +302,89 @@ static int basis_ne(int d, int order) {
   return order == 2 ? BasisDef<3, 2>::NE : BasisDef<3, 3>::NE;
 }
 
-int build_eos_fit(double m, Tables &t, std::string &err) {
-  t.cheb_n = 0;
-  if (m == 0.0) return 0;
-  const int n = 44;
-  const ld lo = logl((ld)m / 4.0L), hi = logl((ld)m * 4.0L);
+// Chebyshev coefficients of f on [-1, 1] (n terms, long double nodes).
+template <class F>
+static void cheb_fit(int n, F f, double *coef) {
   const ld pi = 3.141592653589793238462643383279502884L;
-  ld fk[n];
-  for (int k = 0; k < n; ++k) {
-    ld s = cosl(pi * (k + 0.5L) / n);
-    ld z = expl(0.5L * (hi + lo) + 0.5L * (hi - lo) * s);
-    fk[k] = bessel_k(1.0L, z) / bessel_k(2.0L, z) * (z + 2.0L) / z;
-  }
+  ld fk[64];
+  for (int k = 0; k < n; ++k) fk[k] = f(cosl(pi * (k + 0.5L) / n));
   for (int j = 0; j < n; ++j) {
     ld c = 0.0L;
     for (int k = 0; k < n; ++k) c += fk[k] * cosl(pi * j * (k + 0.5L) / n);
     c *= 2.0L / n;
     if (j == 0) c *= 0.5L;
-    t.cheb[j] = (double)c;
+    coef[j] = (double)c;
   }
+}
+
+static ld cheb_eval(const double *coef, int n, ld s) {
+  ld b1 = 0.0L, b2 = 0.0L;
+  for (int j = n - 1; j >= 1; --j) {
+    ld b0 = 2.0L * s * b1 - b2 + (ld)coef[j];
+    b2 = b1;
+    b1 = b0;
+  }
+  return s * b1 - b2 + (ld)coef[0];
+}
+
+// r(z) = K1/K2 from the fitted series (what the kernels evaluate)
+static ld r_fitted(const Tables &t, ld z) {
+  const ld s = (2.0L * logl(z) - ((ld)t.cheb_lo + (ld)t.cheb_hi)) / ((ld)t.cheb_hi - (ld)t.cheb_lo);
+  return cheb_eval(t.cheb, t.cheb_n, s) * z / (z + 2.0L);
+}
+
+// e - m = m (r(m/T) - 1) + 3 T for d = 3 (e = eps/n = T (G_3 - 1), G_3 = z r + 4)
+static ld kinetic_fitted(const Tables &t, ld m, ld T) { return m * (r_fitted(t, m / T) - 1.0L) + 3.0L * T; }
+
+static ld temperature_fitted(const Tables &t, ld m, ld d) {
+  // Newton on kinetic(T) = d, kinetic' = 3 - z^2 r'(z), r' = r^2 + 3 r/z - 1
+  ld T = d / 2.2L;
+  for (int it = 0; it < 60; ++it) {
+    const ld z = m / T, r = r_fitted(t, z);
+    const ld rp = r * r + 3.0L * r / z - 1.0L;
+    const ld dT = (kinetic_fitted(t, m, T) - d) / (3.0L - z * z * rp);
+    T -= dT;
+    if (fabsl(dT) <= 1e-19L * T) break;
+  }
+  return T;
+}
+
+int build_eos_fit(double m, Tables &t, std::string &err) {
+  t.cheb_n = 0;
+  t.chebT_n = 0;
+  if (m == 0.0) return 0;
+  const int n = kEosTerms;
+  // r(z) = K1(z)/K2(z) through h = r (z + 2)/z on log z in [log(m/4), log(4m)] (T in [1/4, 4])
+  const ld lo = logl((ld)m / 4.0L), hi = logl((ld)m * 4.0L);
+  auto hfun = [&](ld s) {
+    const ld z = expl(0.5L * (hi + lo) + 0.5L * (hi - lo) * s);
+    return bessel_k(1.0L, z) / bessel_k(2.0L, z) * (z + 2.0L) / z;
+  };
+  cheb_fit(n, hfun, t.cheb);
   t.cheb_n = n;
   t.cheb_lo = (double)lo;
   t.cheb_hi = (double)hi;
-  // verify the fit between the nodes
   for (int k = 0; k <= 64; ++k) {
-    ld s = -1.0L + 2.0L * k / 64.0L;
-    ld z = expl(0.5L * (hi + lo) + 0.5L * (hi - lo) * s);
-    ld ref = bessel_k(1.0L, z) / bessel_k(2.0L, z) * (z + 2.0L) / z;
-    ld b1 = 0.0L, b2 = 0.0L;
-    for (int j = n - 1; j >= 1; --j) {
-      ld b0 = 2.0L * s * b1 - b2 + (ld)t.cheb[j];
-      b2 = b1;
-      b1 = b0;
-    }
-    ld got = s * b1 - b2 + (ld)t.cheb[0];
-    if (fabsl(got - ref) > 5e-16L * fabsl(ref)) {
+    const ld s = -1.0L + 2.0L * k / 64.0L, ref = hfun(s);
+    if (fabsl(cheb_eval(t.cheb, n, s) - ref) > 5e-16L * fabsl(ref)) {
       err = "equation-of-state fit failed";
+      return RLBM_ERR_QUADRATURE;
+    }
+  }
+  // inverse: T = (e - m) u(x), x = log(e - m), over the same temperature range
+  const ld xlo = logl(kinetic_fitted(t, m, 0.25L)), xhi = logl(kinetic_fitted(t, m, 4.0L));
+  auto ufun = [&](ld s) {
+    const ld d = expl(0.5L * (xhi + xlo) + 0.5L * (xhi - xlo) * s);
+    return temperature_fitted(t, m, d) / d;
+  };
+  cheb_fit(n, ufun, t.chebT);
+  t.chebT_n = n;
+  t.chebT_lo = (double)xlo;
+  t.chebT_hi = (double)xhi;
+  for (int k = 0; k <= 64; ++k) {
+    const ld s = -1.0L + 2.0L * k / 64.0L, ref = ufun(s);
+    if (fabsl(cheb_eval(t.chebT, n, s) - ref) > 1e-15L * fabsl(ref)) {
+      err = "inverse equation-of-state fit failed";
       return RLBM_ERR_QUADRATURE;
     }
   }

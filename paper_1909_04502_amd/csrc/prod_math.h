@@ -73,11 +73,23 @@ struct Offs {
 // With TRANSPOSE the taps are mirrored (offset -o, same weight): this applies
 // the transpose of the streaming operator on a periodic grid (the adjoint
 // gather dL/dB(y) = sum_taps w dL/dF(y - o)).
+// 3D: the 26 directions of a shell fall into groups of at most 16 taps (the
+// axes, the edges by fours, the corners by twos); the loads of group g may not
+// be issued before the populations of group g - 2 are complete, so at most two
+// groups of taps are in flight per wave instead of all of them.
+__device__ __forceinline__ constexpr bool group_start_3d(int k) {
+  return k == 0 || k == 6 || k == 10 || k == 14 || k == 18 || k == 20 || k == 22 || k == 24;
+}
+__device__ __forceinline__ constexpr int group_first_3d(int k) { return k < 6 ? 0 : k < 18 ? 6 + 4 * ((k - 6) / 4) : k & ~1; }
+
 template <class ST, typename S, bool TRANSPOSE = false>
 __device__ __forceinline__ void pull_prod(const Tables *__restrict__ tb, const S *__restrict__ fin, int64_t sites,
                                           const Offs &o, S (&f)[ST::Q]) {
   typedef S A;
   constexpr int D = ST::D, ND = ST::NDIR, KR = ST::NSHELL;
+  typedef const __attribute__((address_space(1))) char gchar;   // keeps the loads global after laundering
+  gchar *base = (gchar *)fin;
+  int last_end = -1, prev_end = -1;   // last population of the previous group and of the one before
 #pragma unroll
   for (int j = 0; j < KR; ++j) {
     const A v = tab<A>(tb->sv[j], tb->svf[j]);
@@ -100,7 +112,13 @@ __device__ __forceinline__ void pull_prod(const Tables *__restrict__ tb, const S
 #pragma unroll
     for (int k = 0; k < ND; ++k) {
       const int i = j * ND + k;
-      const char *plane = (const char *)(fin + (int64_t)i * sites);
+      if constexpr (D == 3) {
+        if (group_start_3d(k)) {
+          if (prev_end >= 0) asm volatile("" : "+s"(base) : "v"(f[prev_end]));
+          prev_end = last_end;
+        }
+      }
+      gchar *plane = base + (int64_t)i * sites * (int64_t)sizeof(S);
       const int dx = ST::dir(k, 0), dy = ST::dir(k, 1), dz = D == 3 ? ST::dir(k, D - 1) : 0;
       const int z = (dx != 0) + (dy != 0) + (dz != 0);
       A acc = 0;
@@ -128,9 +146,17 @@ __device__ __forceinline__ void pull_prod(const Tables *__restrict__ tb, const S
           oz = -oz;
         }
         const uint32_t off = o.x[ox + 1] + o.y[oy + 1] + o.z[oz + 1];
-        acc += pw[z][nfar] * *(const S *)(plane + off);
+        acc += pw[z][nfar] * *(const __attribute__((address_space(1))) S *)(plane + off);
       }
       f[i] = acc;
+      if constexpr (D == 3) {
+        if (k == ND - 1 || group_start_3d(k + 1)) {
+          // the group is complete here: its loads are consumed and their registers free
+#pragma unroll
+          for (int q = group_first_3d(k); q <= k; ++q) asm volatile("" : "+v"(f[j * ND + q]));
+          last_end = i;
+        }
+      }
     }
   }
 }
@@ -239,36 +265,73 @@ __device__ __forceinline__ Macro<ST::D> collide_prod(const Tables *__restrict__ 
   mac.ok = mac.ok && mac.n > 0.0 && mac.eps > 0.0;
   if constexpr (!RELAX) return mac;
   // ---- step 5: a' = G^{-1} M over parity blocks ----
-  double Md[B::NM];
-  basis_moments<D, N>(mac.n, mac.T, mac.U, rr, Md);
-  if constexpr (DEV) {
-#pragma unroll
-    for (int k = 0; k < B::NM; ++k) Md[k] -= tb->Mref[k];
-  }
-  // moments of the shifted monomials (p^0 - m) p^e = p^0 p^e - m p^e
-#pragma unroll
-  for (int q = 0; q < AT.n; ++q)
-    if (AT.m1[q] >= 0) Md[AT.m1[q]] -= m * Md[AT.m0[q]];
-  // projection coefficients on the orthonormal polynomials J = Linv psi
-  // (Eq. mj-projection-coefficients), then a' = Linv^T a so that
-  // f^eq_i = w_i psi(p_i)^T a' = w_i sum_k a_k J_k(p_i)
-  double ak[B::NM];
-#pragma unroll
-  for (int r = 0; r < B::NM; ++r) {
-    double acc = 0.0;
-#pragma unroll
-    for (int c = 0; c <= r; ++c)
-      if (AT.cls[r] == AT.cls[c]) acc += tb->Linv[r][c] * Md[c];
-    ak[r] = acc;
-  }
   A ap[B::NM];
+  if constexpr (D == 3) {
+    // class by class (moments, shift, L^{-1}, L^{-T}), so that only one block's
+    // temporaries are live next to the populations
+    constexpr ClassTable<D, N> CL{};
 #pragma unroll
-  for (int c = 0; c < B::NM; ++c) {
-    double acc = 0.0;
+    for (int c = 0; c < 8; ++c) {
+      constexpr int kMax = 8;
+      double mc[kMax], ak[kMax];
 #pragma unroll
-    for (int r = c; r < B::NM; ++r)
-      if (AT.cls[r] == AT.cls[c]) acc += tb->Linv[r][c] * ak[r];
-    ap[c] = (A)acc;
+      for (int t = 0; t < CL.cnt[c]; ++t) {
+        const int k = CL.idx[c][t];
+        mc[t] = basis_moment<D, N>(k, mac.n, mac.T, mac.U, rr);
+        if constexpr (DEV) mc[t] -= tb->Mref[k];
+      }
+      // moments of the shifted monomials (p^0 - m) p^e = p^0 p^e - m p^e
+#pragma unroll
+      for (int t = 0; t < CL.cnt[c]; ++t) {
+        const int pk = CL.partner[CL.idx[c][t]];
+        if (pk >= 0) mc[t] -= m * mc[CL.pos[pk]];
+      }
+#pragma unroll
+      for (int t = 0; t < CL.cnt[c]; ++t) {
+        double acc = 0.0;
+#pragma unroll
+        for (int u = 0; u <= t; ++u) acc += tb->Linv[CL.idx[c][t]][CL.idx[c][u]] * mc[u];
+        ak[t] = acc;
+      }
+#pragma unroll
+      for (int u = 0; u < CL.cnt[c]; ++u) {
+        double acc = 0.0;
+#pragma unroll
+        for (int t = u; t < CL.cnt[c]; ++t) acc += tb->Linv[CL.idx[c][t]][CL.idx[c][u]] * ak[t];
+        ap[CL.idx[c][u]] = (A)acc;
+      }
+    }
+  } else {
+    double Md[B::NM];
+    basis_moments<D, N>(mac.n, mac.T, mac.U, rr, Md);
+    if constexpr (DEV) {
+#pragma unroll
+      for (int k = 0; k < B::NM; ++k) Md[k] -= tb->Mref[k];
+    }
+    // moments of the shifted monomials (p^0 - m) p^e = p^0 p^e - m p^e
+#pragma unroll
+    for (int q = 0; q < AT.n; ++q)
+      if (AT.m1[q] >= 0) Md[AT.m1[q]] -= m * Md[AT.m0[q]];
+    // projection coefficients on the orthonormal polynomials J = Linv psi
+    // (Eq. mj-projection-coefficients), then a' = Linv^T a so that
+    // f^eq_i = w_i psi(p_i)^T a' = w_i sum_k a_k J_k(p_i)
+    double ak[B::NM];
+#pragma unroll
+    for (int r = 0; r < B::NM; ++r) {
+      double acc = 0.0;
+#pragma unroll
+      for (int c = 0; c <= r; ++c)
+        if (AT.cls[r] == AT.cls[c]) acc += tb->Linv[r][c] * Md[c];
+      ak[r] = acc;
+    }
+#pragma unroll
+    for (int c = 0; c < B::NM; ++c) {
+      double acc = 0.0;
+#pragma unroll
+      for (int r = c; r < B::NM; ++r)
+        if (AT.cls[r] == AT.cls[c]) acc += tb->Linv[r][c] * ak[r];
+      ap[c] = (A)acc;
+    }
   }
   // ---- step 8 ingredients: Omega_jk = a0 - v_j (n_k . U)/tau ----
   const double itau = 1.0 / tau;
@@ -283,6 +346,42 @@ __device__ __forceinline__ Macro<ST::D> collide_prod(const Tables *__restrict__ 
       if (c != 0.0) acc += c * mac.U[a + 1];
     }
     nU[q] = (A)(acc * itau);
+  }
+  if constexpr (D == 3) {
+    // Direction-major: f^eq_jk = sum_l (s0_jl P0_kl + s1_jl P1_kl) with the
+    // shell-independent angular sums P_kl = sum_{|e| = l} a'_{m(e)} w_k n_k^e,
+    // so only the 8 sums of one direction pair are live next to a'.
+#pragma unroll
+    for (int qp = 0; qp < NPD; ++qp) {
+      const int k = 2 * qp;
+      A P0[4] = {0, 0, 0, 0}, P1[4] = {0, 0, 0, 0};
+#pragma unroll
+      for (int q = 0; q < AT.n; ++q) {
+        const double c = nhat_pow<ST>(k, AT.e[q][0], AT.e[q][1], AT.e[q][2]) * dir_weight<ST>(k);
+        if (c == 0.0) continue;
+        const int l = AT.e[q][0] + AT.e[q][1] + AT.e[q][2];
+        if (AT.m0[q] >= 0) P0[l] += (A)c * ap[AT.m0[q]];
+        if (AT.m1[q] >= 0) P1[l] += (A)c * ap[AT.m1[q]];
+      }
+#pragma unroll
+      for (int j = 0; j < KR; ++j) {
+        A E = 0, O = 0;
+#pragma unroll
+        for (int l = 0; l <= N; ++l) {
+          const A t = tab<A>(tb->sfeq[j][0][l], tb->sfeqf[j][0][l]) * P0[l] +
+                      tab<A>(tb->sfeq[j][1][l], tb->sfeqf[j][1][l]) * P1[l];
+          if (l & 1) O += t;
+          else E += t;
+        }
+        const A b = tab<A>(tb->sv[j], tb->svf[j]) * nU[qp];
+        const A om0 = a0 - b, om1 = a0 + b;
+        const int i = j * ND + k;
+        const A f0 = f[i], f1 = f[i + 1];
+        f[i] = f0 + om0 * ((E + O) - f0);
+        f[i + 1] = f1 + om1 * ((E - O) - f1);
+      }
+    }
+    return mac;
   }
 #pragma unroll
   for (int j = 0; j < KR; ++j) {

@@ -136,6 +136,8 @@ constexpr int kMaxNE = 14, kMaxNO = 16, kMaxNM = 30;
 constexpr int kMaxShell = 4;
 constexpr int kNMom3 = 14;   // 4 (N^a) + 10 (T^ab) in 3D; 2D uses 3 + 6
 
+constexpr int kEosTerms = 44;   // Chebyshev terms of the d = 3 equation-of-state fits
+
 struct Tables {
   // geometry and physics
   int32_t nx, ny, nz, pad0;
@@ -149,7 +151,11 @@ struct Tables {
   // on [log z_lo, log z_hi]
   double cheb_lo, cheb_hi;
   double cheb[48];
-  int32_t cheb_n, pad1;
+  int32_t cheb_n, chebT_n;
+  // and the inverse of the equation of state: T = (e - m) u(x), x = log(e - m), u a Chebyshev
+  // series in x on [chebT_lo, chebT_hi] (e = eps/n; the same temperature range)
+  double chebT_lo, chebT_hi;
+  double chebT[48];
   // per pair of antipodal populations (even member 2pr):
   double c[kMaxPairs][3];       // velocity p^a / p^0
   double mom_e[kMaxPairs][8];   // even moment weights: p0, p0^2, p^a p^b (upper triangle)
@@ -215,6 +221,27 @@ struct AngTable {
       if (a == 0) m0[f] = m;
       else m1[f] = m;
     }
+  }
+};
+
+// Basis indices grouped by parity class (ascending within a class), the position
+// of each index inside its class, and for p0 p^e the index of p^e (else -1).
+template <int D, int N>
+struct ClassTable {
+  int cnt[8] = {};
+  int idx[8][kMaxNM] = {};
+  int pos[kMaxNM] = {};
+  int partner[kMaxNM] = {};
+  constexpr ClassTable() {
+    constexpr AngTable<D, N> AT{};
+    for (int m = 0; m < BasisDef<D, N>::NM; ++m) {
+      const int c = AT.cls[m];
+      pos[m] = cnt[c];
+      idx[c][cnt[c]++] = m;
+      partner[m] = -1;
+    }
+    for (int q = 0; q < AT.n; ++q)
+      if (AT.m1[q] >= 0) partner[AT.m1[q]] = AT.m0[q];
   }
 };
 
