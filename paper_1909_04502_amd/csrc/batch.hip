@@ -75,7 +75,7 @@ static hipError_t launch_batch_t(const BatchArgs &a) {
                          a.elem_off, a.tiles, a.ntiles, (const S *)a.fin, (S *)a.fout, a.err);
       break;
     default:
-      hipLaunchKernelGGL((k_step_batch<ST, N, S, DEV, 32, 8>), dim3(nb), dim3(32, 8), 0, a.stream, a.tabs,
+      hipLaunchKernelGGL((k_step_batch<ST, N, S, DEV, 256, 1>), dim3(nb), dim3(256, 1), 0, a.stream, a.tabs,
                          a.elem_off, a.tiles, a.ntiles, (const S *)a.fin, (S *)a.fout, a.err);
       break;
   }

@@ -67,6 +67,36 @@ __device__ __forceinline__ void adj_apply<3>(const double (&A)[4][4], const doub
   }
 }
 
+// y = adj(S) u for a symmetric 4 x 4 S, from the 2 x 2 minors of rows (0, 1) and (2, 3)
+// (Laplace expansion); only the upper triangle of the adjugate is formed.
+__device__ __forceinline__ void adj_apply_sym4(const double (&a)[4][4], const double (&u)[4], double (&y)[4]) {
+  const double s0 = a[0][0] * a[1][1] - a[0][1] * a[0][1];
+  const double s1 = a[0][0] * a[1][2] - a[0][1] * a[0][2];
+  const double s2 = a[0][0] * a[1][3] - a[0][1] * a[0][3];
+  const double s3 = a[0][1] * a[1][2] - a[1][1] * a[0][2];
+  const double s4 = a[0][1] * a[1][3] - a[1][1] * a[0][3];
+  const double s5 = a[0][2] * a[1][3] - a[1][2] * a[0][3];
+  const double c5 = a[2][2] * a[3][3] - a[2][3] * a[2][3];
+  const double c4 = a[1][2] * a[3][3] - a[1][3] * a[2][3];
+  const double c3 = a[1][2] * a[2][3] - a[1][3] * a[2][2];
+  const double c2 = a[0][2] * a[3][3] - a[0][3] * a[2][3];
+  const double c1 = a[0][2] * a[2][3] - a[0][3] * a[2][2];
+  const double b00 = a[1][1] * c5 - a[1][2] * c4 + a[1][3] * c3;
+  const double b01 = -a[0][1] * c5 + a[0][2] * c4 - a[0][3] * c3;
+  const double b02 = a[1][3] * s5 - a[2][3] * s4 + a[3][3] * s3;
+  const double b03 = -a[1][2] * s5 + a[2][2] * s4 - a[2][3] * s3;
+  const double b11 = a[0][0] * c5 - a[0][2] * c2 + a[0][3] * c1;
+  const double b12 = -a[0][3] * s5 + a[2][3] * s2 - a[3][3] * s1;
+  const double b13 = a[0][2] * s5 - a[2][2] * s2 + a[2][3] * s1;
+  const double b22 = a[0][3] * s4 - a[1][3] * s2 + a[3][3] * s0;
+  const double b23 = -a[0][2] * s4 + a[1][2] * s2 - a[2][3] * s0;
+  const double b33 = a[0][2] * s3 - a[1][2] * s1 + a[2][2] * s0;
+  y[0] = b00 * u[0] + b01 * u[1] + b02 * u[2] + b03 * u[3];
+  y[1] = b01 * u[0] + b11 * u[1] + b12 * u[2] + b13 * u[3];
+  y[2] = b02 * u[0] + b12 * u[1] + b22 * u[2] + b23 * u[3];
+  y[3] = b03 * u[0] + b13 * u[1] + b23 * u[2] + b33 * u[3];
+}
+
 template <int D>
 __device__ __forceinline__ double lorentz_dot(const double (&a)[D + 1], const double (&b)[D + 1]) {
   double s = a[0] * b[0];
@@ -105,13 +135,27 @@ __device__ __forceinline__ bool landau_frame(const double (&T)[D + 1][D + 1], do
     for (int k = 0; k <= D; ++k) U[k] *= s;
     eps = rayleigh<D>(T, U);
     if (it == ITERS) break;
-    double A[D + 1][D + 1];
-#pragma unroll
-    for (int a = 0; a <= D; ++a)
-#pragma unroll
-      for (int b = 0; b <= D; ++b) A[a][b] = T[a][b] * eta_c(b, b) - (a == b ? eps : 0.0);
     double y[D + 1];
-    adj_apply<D>(A, U, y);
+    if constexpr (D == 3) {
+      // M - eps I = (T - eps eta) eta, so adj(M - eps I) U = -eta adj(S) U with S = T - eps eta
+      // symmetric (the sign is fixed by the normalisation)
+      double S[4][4];
+#pragma unroll
+      for (int a = 0; a <= 3; ++a)
+#pragma unroll
+        for (int b = 0; b <= 3; ++b) S[a][b] = T[a][b] - (a == b ? eps * eta_c(a, a) : 0.0);
+      adj_apply_sym4(S, U, y);
+      y[1] = -y[1];
+      y[2] = -y[2];
+      y[3] = -y[3];
+    } else {
+      double A[D + 1][D + 1];
+#pragma unroll
+      for (int a = 0; a <= D; ++a)
+#pragma unroll
+        for (int b = 0; b <= D; ++b) A[a][b] = T[a][b] * eta_c(b, b) - (a == b ? eps : 0.0);
+      adj_apply<D>(A, U, y);
+    }
 #pragma unroll
     for (int k = 0; k <= D; ++k) U[k] = y[k];
   }

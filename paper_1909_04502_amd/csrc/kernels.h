@@ -14,16 +14,17 @@ struct FieldPtrs {
   int any;
 };
 
-// Launch variants of the step kernel: block shape, occupancy target
-// (minimum waves per SIMD the compiler must allow, 0 = its choice) and tile
-// order (1 = each XCD walks a contiguous band of tiles).
+// Launch variants of the step kernel: block shape bx x by x bz (2D lattices
+// fold bz into by), occupancy target (minimum waves per SIMD the compiler must
+// allow, 0 = its choice) and tile order (1 = each XCD walks a contiguous band
+// of tiles).
 struct Variant {
-  int bx, by, occ, xcd;
+  int bx, by, bz, occ, xcd;
 };
 constexpr int kNumVariants = 10;
 constexpr Variant kVariants[kNumVariants] = {
-    {64, 4, 0, 0}, {64, 4, 0, 1}, {64, 4, 2, 0}, {64, 4, 2, 1}, {64, 2, 0, 1},
-    {64, 1, 0, 1}, {128, 2, 0, 1}, {32, 8, 0, 1}, {64, 4, 3, 1}, {64, 2, 2, 0}};
+    {64, 4, 1, 0, 0}, {64, 4, 1, 0, 1}, {64, 4, 1, 2, 0}, {64, 2, 2, 2, 0},  {64, 2, 1, 0, 1},
+    {64, 1, 1, 0, 1}, {128, 2, 1, 0, 1}, {256, 1, 1, 0, 1}, {64, 4, 1, 3, 1}, {64, 1, 4, 2, 0}};
 
 struct LaunchArgs {
   int op = 0;
@@ -67,7 +68,7 @@ struct AdjointArgs {
 hipError_t launch_adjoint(const AdjointArgs &a);
 
 // Batched step: tile shapes (0: 64x4, 1: 64x2, 2: 128x2, 3: 32x8) and grid sizes
-constexpr int kBatchTiles[4][2] = {{64, 4}, {64, 2}, {128, 2}, {32, 8}};
+constexpr int kBatchTiles[4][2] = {{64, 4}, {64, 2}, {128, 2}, {256, 1}};
 struct BatchArgs {
   int stencil = 0, order = 0, storage = 0;
   int tile = 0;                  // index into kBatchTiles

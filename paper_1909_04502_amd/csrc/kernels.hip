@@ -301,10 +301,10 @@ __device__ __forceinline__ void store_site(S *__restrict__ fout, int64_t sites, 
 }
 
 // Site of this thread.  Blocks form a 1D grid over tiles of blockDim.x x
-// blockDim.y sites (x fastest, then y, then z).  The hardware deals
-// consecutive blocks round-robin to the 8 XCDs; with xcd != 0 the block id is
-// remapped so that each XCD receives a contiguous range of tiles, i.e. a band
-// of neighbouring rows whose halo rows stay in that XCD's L2.
+// blockDim.y x blockDim.z sites (x fastest, then y, then z).  The hardware
+// deals consecutive blocks round-robin to the 8 XCDs; with xcd != 0 the block
+// id is remapped so that each XCD receives a contiguous range of tiles, i.e. a
+// band of neighbouring rows whose halo rows stay in that XCD's L2.
 __device__ __forceinline__ bool site_coords(const Tables *__restrict__ tb, int xcd, int &x, int &y, int &z) {
   const uint32_t gx = (tb->nx + blockDim.x - 1) / blockDim.x;
   const uint32_t gy = (tb->ny + blockDim.y - 1) / blockDim.y;
@@ -317,8 +317,8 @@ __device__ __forceinline__ bool site_coords(const Tables *__restrict__ tb, int x
   const uint32_t tx = t % gx, ty = (t / gx) % gy, tz = t / (gx * gy);
   x = tx * blockDim.x + threadIdx.x;
   y = ty * blockDim.y + threadIdx.y;
-  z = tz;
-  return x < tb->nx && y < tb->ny;
+  z = tz * blockDim.z + threadIdx.z;
+  return x < tb->nx && y < tb->ny && z < tb->nz;
 }
 
 template <class ST, int N, typename S, bool DEV, int OCC>
@@ -334,7 +334,11 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(OCC > 
   const double tau = site_tau<S>(tb, tau_field, site);
   const Macro<ST::D> mac = collide_site<ST, N, S, DEV, true>(tb, f, tau);
   if (!mac.ok) flag_error(err);
-  store_site<ST, S>(fout, sites, (uint32_t)site * (uint32_t)sizeof(S), f);
+  // a fresh copy of the plane size for the store addresses: otherwise the compiler keeps the
+  // load phase's plane offsets alive (in spilled scalar registers) for reuse here
+  int64_t sites_st = sites;
+  if constexpr (ST::D == 3) asm volatile("" : "+s"(sites_st));
+  store_site<ST, S>(fout, sites_st, (uint32_t)site * (uint32_t)sizeof(S), f);
   if (last.any) write_fields<ST::D>(last, site, sites, mac);
 }
 
@@ -418,8 +422,9 @@ __global__ void __launch_bounds__(256) k_init(const Tables *__restrict__ tb, con
 template <class ST, int N, typename S, bool DEV>
 static hipError_t launch_t(const LaunchArgs &a) {
   const Variant vr = kVariants[(a.op == OP_STEP && a.variant >= 0 && a.variant < kNumVariants) ? a.variant : 0];
-  dim3 block(vr.bx, vr.by, 1);
-  const long nb = (long)((a.nx + vr.bx - 1) / vr.bx) * ((a.ny + vr.by - 1) / vr.by) * a.nz;
+  const int by = ST::D == 2 ? vr.by * vr.bz : vr.by, bz = ST::D == 2 ? 1 : vr.bz;
+  dim3 block(vr.bx, by, bz);
+  const long nb = (long)((a.nx + vr.bx - 1) / vr.bx) * ((a.ny + by - 1) / by) * ((a.nz + bz - 1) / bz);
   dim3 grid((unsigned)nb, 1, 1);
   switch (a.op) {
     case OP_STEP:

@@ -302,6 +302,15 @@ static int basis_ne(int d, int order) {
   return order == 2 ? BasisDef<3, 2>::NE : BasisDef<3, 3>::NE;
 }
 
+template <int D, int N>
+static void pack_linv(Tables &t) {
+  constexpr ClassTable<D, N> CL{};
+  static_assert(CL.packed <= kMaxPacked, "packed Linv table too small");
+  for (int c = 0; c < 8; ++c)
+    for (int i = 0; i < CL.cnt[c]; ++i)
+      for (int j = 0; j <= i; ++j) t.LinvP[CL.off[c] + i * (i + 1) / 2 + j] = t.Linv[CL.idx[c][i]][CL.idx[c][j]];
+}
+
 // Chebyshev coefficients of f on [-1, 1] (n terms, long double nodes).
 template <class F>
 static void cheb_fit(int n, F f, double *coef) {
@@ -586,6 +595,13 @@ int build_tables(const QuadHost &q, double tau, double n_ref, int storage, const
         y[a] = sd / Ls[a * NM + a];
       }
       for (int a = 0; a < NM; ++a) t.Linv[a][c] = (double)y[a];
+    }
+    if (d == 2) {
+      if (q.order == 2) pack_linv<2, 2>(t);
+      else pack_linv<2, 3>(t);
+    } else {
+      if (q.order == 2) pack_linv<3, 2>(t);
+      else pack_linv<3, 3>(t);
     }
   }
   if (q.kind == RLBM_QUAD_PRODUCT) {

@@ -75,8 +75,8 @@ struct Offs {
 // gather dL/dB(y) = sum_taps w dL/dF(y - o)).
 // 3D: the 26 directions of a shell fall into groups of at most 16 taps (the
 // axes, the edges by fours, the corners by twos); the loads of group g may not
-// be issued before the populations of group g - 2 are complete, so at most two
-// groups of taps are in flight per wave instead of all of them.
+// be issued before the populations of group g - 3 are complete, so at most
+// three groups of taps are in flight per wave instead of all of them.
 __device__ __forceinline__ constexpr bool group_start_3d(int k) {
   return k == 0 || k == 6 || k == 10 || k == 14 || k == 18 || k == 20 || k == 22 || k == 24;
 }
@@ -89,7 +89,11 @@ __device__ __forceinline__ void pull_prod(const Tables *__restrict__ tb, const S
   constexpr int D = ST::D, ND = ST::NDIR, KR = ST::NSHELL;
   typedef const __attribute__((address_space(1))) char gchar;   // keeps the loads global after laundering
   gchar *base = (gchar *)fin;
-  int last_end = -1, prev_end = -1;   // last population of the previous group and of the one before
+  // last populations of the previous groups (ends[0] most recent); group g waits for ends[kDepth - 1]
+  constexpr int kDepth = 3;
+  int ends[kDepth];
+#pragma unroll
+  for (int e = 0; e < kDepth; ++e) ends[e] = -1;
 #pragma unroll
   for (int j = 0; j < KR; ++j) {
     const A v = tab<A>(tb->sv[j], tb->svf[j]);
@@ -113,15 +117,13 @@ __device__ __forceinline__ void pull_prod(const Tables *__restrict__ tb, const S
     for (int k = 0; k < ND; ++k) {
       const int i = j * ND + k;
       if constexpr (D == 3) {
-        if (group_start_3d(k)) {
-          if (prev_end >= 0) asm volatile("" : "+s"(base) : "v"(f[prev_end]));
-          prev_end = last_end;
-        }
+        if (group_start_3d(k) && ends[kDepth - 1] >= 0) asm volatile("" : "+s"(base) : "v"(f[ends[kDepth - 1]]));
       }
       gchar *plane = base + (int64_t)i * sites * (int64_t)sizeof(S);
       const int dx = ST::dir(k, 0), dy = ST::dir(k, 1), dz = D == 3 ? ST::dir(k, D - 1) : 0;
       const int z = (dx != 0) + (dy != 0) + (dz != 0);
       A acc = 0;
+      {
 #pragma unroll
       for (int tap = 0; tap < (1 << z); ++tap) {
         int bit = 0, ox = 0, oy = 0, oz = 0, nfar = 0;
@@ -149,12 +151,15 @@ __device__ __forceinline__ void pull_prod(const Tables *__restrict__ tb, const S
         acc += pw[z][nfar] * *(const __attribute__((address_space(1))) S *)(plane + off);
       }
       f[i] = acc;
+      }
       if constexpr (D == 3) {
         if (k == ND - 1 || group_start_3d(k + 1)) {
           // the group is complete here: its loads are consumed and their registers free
 #pragma unroll
           for (int q = group_first_3d(k); q <= k; ++q) asm volatile("" : "+v"(f[j * ND + q]));
-          last_end = i;
+#pragma unroll
+          for (int e = kDepth - 1; e > 0; --e) ends[e] = ends[e - 1];
+          ends[0] = i;
         }
       }
     }
@@ -270,10 +275,16 @@ __device__ __forceinline__ Macro<ST::D> collide_prod(const Tables *__restrict__ 
     // class by class (moments, shift, L^{-1}, L^{-T}), so that only one block's
     // temporaries are live next to the populations
     constexpr ClassTable<D, N> CL{};
+    // the packed blocks are read class by class: laundering the table pointer on the previous
+    // block's result keeps the compiler from hoisting (and spilling) all 91 scalar loads
+    typedef const __attribute__((address_space(4))) double cdouble;
+    cdouble *lp = (cdouble *)tb->LinvP;
+    A prev = 0;
 #pragma unroll
     for (int c = 0; c < 8; ++c) {
       constexpr int kMax = 8;
       double mc[kMax], ak[kMax];
+      if (c > 0) asm volatile("" : "+s"(lp) : "v"(prev));
 #pragma unroll
       for (int t = 0; t < CL.cnt[c]; ++t) {
         const int k = CL.idx[c][t];
@@ -290,16 +301,19 @@ __device__ __forceinline__ Macro<ST::D> collide_prod(const Tables *__restrict__ 
       for (int t = 0; t < CL.cnt[c]; ++t) {
         double acc = 0.0;
 #pragma unroll
-        for (int u = 0; u <= t; ++u) acc += tb->Linv[CL.idx[c][t]][CL.idx[c][u]] * mc[u];
+        for (int u = 0; u <= t; ++u) acc += lp[CL.off[c] + t * (t + 1) / 2 + u] * mc[u];
         ak[t] = acc;
       }
+      // reload the block for the transposed pass rather than keep it in (spilled) scalar registers
+      asm volatile("" : "+s"(lp) : "v"(ak[CL.cnt[c] - 1]));
 #pragma unroll
       for (int u = 0; u < CL.cnt[c]; ++u) {
         double acc = 0.0;
 #pragma unroll
-        for (int t = u; t < CL.cnt[c]; ++t) acc += tb->Linv[CL.idx[c][t]][CL.idx[c][u]] * ak[t];
+        for (int t = u; t < CL.cnt[c]; ++t) acc += lp[CL.off[c] + t * (t + 1) / 2 + u] * ak[t];
         ap[CL.idx[c][u]] = (A)acc;
       }
+      prev = ap[CL.idx[c][0]];
     }
   } else {
     double Md[B::NM];

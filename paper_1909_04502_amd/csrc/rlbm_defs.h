@@ -136,7 +136,8 @@ constexpr int kMaxNE = 14, kMaxNO = 16, kMaxNM = 30;
 constexpr int kMaxShell = 4;
 constexpr int kNMom3 = 14;   // 4 (N^a) + 10 (T^ab) in 3D; 2D uses 3 + 6
 
-constexpr int kEosTerms = 44;   // Chebyshev terms of the d = 3 equation-of-state fits
+constexpr int kEosTerms = 44;
+constexpr int kMaxPacked = 96;   // packed class blocks of Linv (91 entries for d = 3, N = 3)   // Chebyshev terms of the d = 3 equation-of-state fits
 
 struct Tables {
   // geometry and physics
@@ -182,6 +183,7 @@ struct Tables {
   double smom[kMaxShell][5];       // p0, |p|, p0^2, p0 |p|, |p|^2
   double sfeq[kMaxShell][2][4];
   double Linv[kMaxNM][kMaxNM];     // product rules: inverse Cholesky factor of the Gram matrix of (p^0 - m)^a p^e
+  double LinvP[kMaxPacked];        // its parity-class blocks, packed lower triangles (ClassTable order)
   float svf[kMaxShell];
   float smomf[kMaxShell][5];
   float sfeqf[kMaxShell][2][4];
@@ -232,6 +234,8 @@ struct ClassTable {
   int idx[8][kMaxNM] = {};
   int pos[kMaxNM] = {};
   int partner[kMaxNM] = {};
+  int off[8] = {};   // start of class c's packed lower triangle
+  int packed = 0;
   constexpr ClassTable() {
     constexpr AngTable<D, N> AT{};
     for (int m = 0; m < BasisDef<D, N>::NM; ++m) {
@@ -242,6 +246,10 @@ struct ClassTable {
     }
     for (int q = 0; q < AT.n; ++q)
       if (AT.m1[q] >= 0) partner[AT.m1[q]] = AT.m0[q];
+    for (int c = 0; c < 8; ++c) {
+      off[c] = packed;
+      packed += cnt[c] * (cnt[c] + 1) / 2;
+    }
   }
 };
 
