@@ -35,7 +35,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
-    ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--autotune", action="store_true",
+                    help="autotune the launch variant of the single-lattice legs (default: the library's default)")
     ap.add_argument("--no-copy", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
@@ -276,7 +277,7 @@ def main():
     L = args.size
     Q = 32
     sites = L * L
-    lat, fa, fb, tune = make_lattice(L, "f64", not args.no_autotune)
+    lat, fa, fb, tune = make_lattice(L, "f64", args.autotune)
     t = time_steps(lat, fa, fb, args.warmup, args.steps)
     mlups = sites / t / 1e6
     bytes_step = 2 * Q * 8 * sites
@@ -307,7 +308,7 @@ def main():
     del lat, fa, fb
     torch.cuda.empty_cache()
     if not args.no_variants:
-        lat, fa, fb, tune32 = make_lattice(L, "f32dev", not args.no_autotune)
+        lat, fa, fb, tune32 = make_lattice(L, "f32dev", args.autotune)
         t32 = time_steps(lat, fa, fb, args.warmup, args.steps)
         b32 = 2 * Q * 4 * sites
         out["variants"] = {"f32dev": {"MLUPS": round(sites / t32 / 1e6, 2), "ms_per_step": round(t32 * 1e3, 5),
@@ -321,7 +322,7 @@ def main():
         out["adjoint"] = adjoint_leg(512, args.warmup, args.steps)
     if not args.no_3d:
         out["shock_tube_3d"] = shock_tube_3d(args.size_3d, max(2, args.warmup // 4), max(4, args.steps // 10),
-                                             not args.no_autotune)
+                                             args.autotune)
     if not args.no_batch:
         out["batched"] = batched(args.batch_count, max(2, args.warmup // 4), max(4, args.steps // 10))
     if not args.no_copy:

@@ -142,8 +142,10 @@ rlbm_status rlbm_create(const rlbm_config *cfg, rlbm_lattice **out) {
   if (!h) return fail(RLBM_ERR_DEVICE, "out of host memory");
   h->cfg = *cfg;
   h->stencil = stencil_of(m);
-  // 3D kernels keep ~100 populations in registers: default to the occupancy-2 build, untiled order
+  // default launch shapes (from autotuning sweeps on MI355X): 3D keeps ~100 populations in
+  // registers and takes the occupancy-2 build in untiled order; 2D double rows of 64 sites
   if (m.d == 3) h->variant = 2;
+  else if (m.kind == RLBM_QUAD_PRODUCT && cfg->storage == RLBM_F64) h->variant = 5;
   h->sites = sites;
   std::string err;
   int rc = rlbm::build_quadrature(m.d, m.zeta, m.order, m.kind, h->quad, err);
