@@ -42,6 +42,7 @@ def parse():
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--batch-count", type=int, default=256)
     ap.add_argument("--no-3d", action="store_true")
+    ap.add_argument("--no-onlattice", action="store_true")
     ap.add_argument("--size-3d", type=int, default=256)
     return ap.parse_args()
 
@@ -116,14 +117,15 @@ def copy_bandwidth(nbytes, reps=20):
     return 2 * nbytes / t / 1e9
 
 
-def batched(count, warmup, steps):
+def batched(count, warmup, steps, storage="f64"):
     """Many lattices (sides 64..512, tau in [0.6, 2], zeta in [0, 5], seed 4; Taylor-Green u0 = 0.05):
     one persistent launch per step (graph-replayed) against one launch per lattice per step."""
     import torch
     import workloads as W
     from paper_1909_04502_amd import rlbm as R
     specs = W.batch_specs(count, seed=4)
-    b = R.Batch(specs, order=3, storage="f64")
+    b = R.Batch(specs, order=3, storage=storage)
+    es = 8 if storage == "f64" else 4
     ns, Ts, us = [], [], []
     for i, sp in enumerate(specs):
         n, T, u = W.taylor_green_2d(*sp["extent"], 0.05, density_sigma=1e-3, seed=100 + i)
@@ -167,10 +169,10 @@ def batched(count, warmup, steps):
            "eager_ms_per_step": round(res["eager"] * 1e3, 4),
            "per_lattice_launches_ms_per_step": round(t_solo * 1e3, 4),
            "speedup_vs_per_lattice": round(t_solo / t, 3),
-           "achieved_GBs": round(2 * Q * 8 * sites / t / 1e9, 1),
-           "frac": round(2 * Q * 8 * sites / t / 1e9 / HBM_PEAK_GBS, 4),
+           "achieved_GBs": round(2 * Q * es * sites / t / 1e9, 1),
+           "frac": round(2 * Q * es * sites / t / 1e9 / HBM_PEAK_GBS, 4),
            "variant": b.variant, "autotune_ms": [round(x, 4) for x in tune],
-           "workload": f"{count} lattices, sides U{{64..512}}, tau U[0.6,2], zeta U[0,5] (seed 4), N=3, f64"}
+           "workload": f"{count} lattices, sides U{{64..512}}, tau U[0.6,2], zeta U[0,5] (seed 4), N=3, {storage}"}
     del b, fa, fb, views
     torch.cuda.empty_cache()
     return out
@@ -211,7 +213,28 @@ def adjoint_leg(L, warmup, steps):
     sites = L * L
     Q = lat.Q
     ab = (3 * Q * 4 + 16) * sites
+    # the whole differentiable run: forward with checkpoints every 45 steps, then the backward pass
+    # (segment recompute + reverse steps + the initial-condition VJP) through the autograd Function
+    from paper_1909_04502_amd import adjoint as A
+    nrun = 2000
+    _, _, ut = W.taylor_green_2d(L, L, 0.08, phase=(0.3, -0.2))
+    ut = torch.tensor(ut, device="cuda")
+    taug = tau.clone().cuda().requires_grad_(True)
+    u0g = torch.tensor(u).cuda().requires_grad_(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    U = A.run(lat, taug, u0g, torch.tensor(n), torch.tensor(T), nrun, every=45)
+    loss = A.velocity_loss(U, ut)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    loss.backward()
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
     out = {"workload": f"{L}x{L} zeta=1 N=3 f32dev with tau field", "forward_ms": round(t_fwd * 1e3, 5),
+           "run_steps": nrun, "run_checkpoint_every": 45,
+           "run_forward_ms_per_step": round((t1 - t0) / nrun * 1e3, 5),
+           "run_backward_ms_per_step": round((t2 - t1) / nrun * 1e3, 5),
+           "run_backward_over_forward": round((t2 - t1) / (t1 - t0), 3),
            "adjoint_ms": round(t_adj * 1e3, 5), "adjoint_over_forward": round(t_adj / t_fwd, 3),
            "adjoint_MLUPS": round(sites / t_adj / 1e6, 2), "adjoint_achieved_GBs": round(ab / t_adj / 1e9, 1),
            "adjoint_frac": round(ab / t_adj / 1e9 / HBM_PEAK_GBS, 4)}
@@ -241,6 +264,29 @@ def shock_tube_3d(L, warmup, steps, autotune=True):
            "achieved_GBs": round(b / t / 1e9, 1), "frac": round(b / t / 1e9 / HBM_PEAK_GBS, 4),
            "variant": lat.variant, "autotune_ms": [round(x, 4) for x in tune] if tune else None}
     del lat, fa, fb
+    torch.cuda.empty_cache()
+    return out
+
+
+def onlattice_leg(warmup, steps):
+    """The printed ultra-relativistic on-lattice rule (d = 2, zeta = 0, N = 2, Q = 28, integer shifts), FP64:
+    the 64 x 64 Taylor-Green configuration (u0 = 0.01, tau = 0.9, population noise 1e-6, seed 1; launch
+    bound at this size) and the same rule on 1024 x 1024 (448 algorithmic bytes per site)."""
+    import torch
+    import workloads as W
+    from paper_1909_04502_amd import rlbm as R
+    out = {}
+    for L in (64, 1024):
+        n, T, u = W.taylor_green_2d(L, L, 0.01, seed=2)
+        lat = R.Lattice(d=2, zeta=0.0, order=2, kind="ur_onlattice", extent=(L, L), tau=0.9)
+        xi = torch.tensor(W.population_noise(lat.Q, (L, L), seed=1))
+        fa = lat.init(torch.tensor(n), torch.tensor(T), torch.tensor(u), xi, 1e-6)
+        fb = lat.new_state()
+        t = time_steps(lat, fa, fb, warmup, steps)
+        b = 2 * lat.Q * 8 * L * L
+        out[f"{L}x{L}"] = {"MLUPS": round(L * L / t / 1e6, 2), "ms_per_step": round(t * 1e3, 5),
+                           "achieved_GBs": round(b / t / 1e9, 1), "frac": round(b / t / 1e9 / HBM_PEAK_GBS, 4)}
+        del lat, fa, fb
     torch.cuda.empty_cache()
     return out
 
@@ -325,6 +371,10 @@ def main():
                                              args.autotune)
     if not args.no_batch:
         out["batched"] = batched(args.batch_count, max(2, args.warmup // 4), max(4, args.steps // 10))
+        out["batched_f32dev"] = batched(args.batch_count, max(2, args.warmup // 4), max(4, args.steps // 10),
+                                        "f32dev")
+    if not args.no_onlattice:
+        out["onlattice_ur"] = onlattice_leg(args.warmup, args.steps)
     if not args.no_copy:
         cb = copy_bandwidth(Q * 8 * sites)
         out["roofline"]["copy_GBs"] = round(cb, 1)

@@ -164,7 +164,10 @@ rlbm_status rlbm_init(rlbm_lattice *h, const double *n0, const double *T0, const
 /* Advance nsteps >= 0 time steps, ping-ponging between f_a (input) and f_b.
  * The result is in f_b when nsteps is odd and in f_a when it is even.  f_a and
  * f_b must not overlap.  last (may be NULL) receives the macroscopic fields of
- * the pre-collision state of the final step's time level. */
+ * the pre-collision state of the final step's time level.  With nsteps >= 4 and
+ * last == NULL the launches are captured once into a HIP graph (kept by the
+ * handle for the same buffers, step count and launch variant) that is replayed
+ * on `stream`; a handle serves one stream at a time. */
 rlbm_status rlbm_step(rlbm_lattice *h, void *f_a, void *f_b, int32_t nsteps,
                       const rlbm_fields *last, hipStream_t stream);
 

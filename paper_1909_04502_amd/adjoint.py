@@ -26,10 +26,14 @@ class _Run(torch.autograd.Function):
         cur = lat.init(n0, T0, u0d, noise, amp)
         nxt = lat.new_state()
         ckpt = {0: cur.clone()}
-        for t in range(1, nsteps + 1):
-            lat.step(cur, nxt, 1)
-            cur, nxt = nxt, cur
-            if t % every == 0 and t < nsteps:
+        t = 0
+        while t < nsteps:                                  # one library call per checkpoint segment
+            k = min(every, nsteps - t)
+            res = lat.step(cur, nxt, k)
+            if res is nxt:
+                cur, nxt = nxt, cur
+            t += k
+            if t < nsteps:
                 ckpt[t] = cur.clone()
         final = cur
         fields = lat.moments(final)

@@ -20,7 +20,21 @@ struct rlbm_lattice {
   int variant = 1;
   int64_t sites = 0;
   std::string last_error;
+  // launch graphs of recent multi-step rlbm_step calls (buffers, step count, variant), least
+  // recently used replaced first
+  struct StepGraph {
+    hipGraphExec_t exec = nullptr;
+    const void *fa = nullptr, *fb = nullptr;
+    int n = -1, variant = -1;
+    uint64_t used = 0;
+  };
+  static constexpr int kGraphs = 4;
+  StepGraph graphs[kGraphs];
+  uint64_t graph_clock = 0;
+  hipStream_t cap_stream = nullptr;
 };
+
+constexpr int32_t kGraphMinSteps = 4;   // rlbm_step replays a cached graph from this many steps on
 
 struct rlbm_batch {
   std::vector<rlbm_lattice *> lats;
@@ -179,6 +193,9 @@ rlbm_status rlbm_create(const rlbm_config *cfg, rlbm_lattice **out) {
 
 rlbm_status rlbm_destroy(rlbm_lattice *h) {
   if (!h) return RLBM_OK;
+  for (auto &g : h->graphs)
+    if (g.exec) (void)hipGraphExecDestroy(g.exec);
+  if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
   if (h->d_tables) (void)hipFree(h->d_tables);
   if (h->d_err) (void)hipFree(h->d_err);
   delete h;
@@ -213,22 +230,65 @@ rlbm_status rlbm_init(rlbm_lattice *h, const double *n0, const double *T0, const
   return he == hipSuccess ? RLBM_OK : fail(RLBM_ERR_DEVICE, hipGetErrorString(he));
 }
 
-rlbm_status rlbm_step(rlbm_lattice *h, void *f_a, void *f_b, int32_t nsteps, const rlbm_fields *last,
-                      hipStream_t stream) {
-  if (!h || !f_a || !f_b || nsteps < 0) return fail(RLBM_ERR_INVALID_ARG, "bad argument");
-  const int64_t bytes = (int64_t)(h->cfg.storage == RLBM_F64 ? 8 : 4) * h->quad.Q * h->sites;
-  const char *pa = (const char *)f_a, *pb = (const char *)f_b;
-  if (pa < pb + bytes && pb < pa + bytes) return fail(RLBM_ERR_INVALID_ARG, "f_a and f_b overlap");
+static hipError_t step_launches(rlbm_lattice *h, void *f_a, void *f_b, int32_t nsteps, const rlbm_fields *last,
+                                hipStream_t stream) {
   rlbm::LaunchArgs a = base_args(h, stream);
   a.op = rlbm::OP_STEP;
   for (int32_t s = 0; s < nsteps; ++s) {
     a.fin = (s & 1) ? f_b : f_a;
     a.fout = (s & 1) ? f_a : f_b;
     a.fields = field_ptrs(s == nsteps - 1 ? last : nullptr);
-    hipError_t he = rlbm::launch(a);
-    if (he != hipSuccess) return fail(RLBM_ERR_DEVICE, hipGetErrorString(he));
+    const hipError_t he = rlbm::launch(a);
+    if (he != hipSuccess) return he;
   }
-  return RLBM_OK;
+  return hipSuccess;
+}
+
+rlbm_status rlbm_step(rlbm_lattice *h, void *f_a, void *f_b, int32_t nsteps, const rlbm_fields *last,
+                      hipStream_t stream) {
+  if (!h || !f_a || !f_b || nsteps < 0) return fail(RLBM_ERR_INVALID_ARG, "bad argument");
+  const int64_t bytes = (int64_t)(h->cfg.storage == RLBM_F64 ? 8 : 4) * h->quad.Q * h->sites;
+  const char *pa = (const char *)f_a, *pb = (const char *)f_b;
+  if (pa < pb + bytes && pb < pa + bytes) return fail(RLBM_ERR_INVALID_ARG, "f_a and f_b overlap");
+  if (nsteps >= kGraphMinSteps && last == nullptr) {
+    // many steps without field output: a cached HIP graph of the launches (no per-launch host cost)
+    hipError_t he = hipSuccess;
+    rlbm_lattice::StepGraph *sg = nullptr;
+    for (auto &g : h->graphs)
+      if (g.exec && g.fa == f_a && g.fb == f_b && g.n == nsteps && g.variant == h->variant) sg = &g;
+    if (!sg) {
+      sg = &h->graphs[0];
+      for (auto &g : h->graphs)
+        if (g.used < sg->used) sg = &g;
+      if (sg->exec) (void)hipGraphExecDestroy(sg->exec);
+      *sg = rlbm_lattice::StepGraph{};
+      if (!h->cap_stream) he = hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking);
+      hipGraph_t g = nullptr;
+      if (he == hipSuccess) he = hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal);
+      if (he == hipSuccess) {
+        const hipError_t he2 = step_launches(h, f_a, f_b, nsteps, nullptr, h->cap_stream);
+        he = hipStreamEndCapture(h->cap_stream, &g);
+        if (he == hipSuccess) he = he2;
+      }
+      if (he == hipSuccess) he = hipGraphInstantiate(&sg->exec, g, nullptr, nullptr, 0);
+      if (g) (void)hipGraphDestroy(g);
+      if (he == hipSuccess) {
+        sg->fa = f_a;
+        sg->fb = f_b;
+        sg->n = nsteps;
+        sg->variant = h->variant;
+      } else {
+        sg->exec = nullptr;
+      }
+    }
+    if (he == hipSuccess) {
+      sg->used = ++h->graph_clock;
+      he = hipGraphLaunch(sg->exec, stream);
+    }
+    return he == hipSuccess ? RLBM_OK : fail(RLBM_ERR_DEVICE, hipGetErrorString(he));
+  }
+  const hipError_t he = step_launches(h, f_a, f_b, nsteps, last, stream);
+  return he == hipSuccess ? RLBM_OK : fail(RLBM_ERR_DEVICE, hipGetErrorString(he));
 }
 
 rlbm_status rlbm_moments(rlbm_lattice *h, const void *f, const rlbm_fields *out, hipStream_t stream) {

@@ -16,15 +16,15 @@ struct FieldPtrs {
 
 // Launch variants of the step kernel: block shape bx x by x bz (2D lattices
 // fold bz into by), occupancy target (minimum waves per SIMD the compiler must
-// allow, 0 = its choice) and tile order (1 = each XCD walks a contiguous band
-// of tiles).
+// allow, 0 = its choice) and tile order (0 = as dealt, 1 = a contiguous band of
+// tiles per XCD, 2 = (y, z) patches per XCD in 3D, a band in 2D).
 struct Variant {
   int bx, by, bz, occ, xcd;
 };
 constexpr int kNumVariants = 10;
 constexpr Variant kVariants[kNumVariants] = {
-    {64, 4, 1, 0, 0}, {64, 4, 1, 0, 1}, {64, 4, 1, 2, 0}, {64, 2, 2, 2, 0},  {64, 2, 1, 0, 1},
-    {64, 1, 1, 0, 1}, {128, 2, 1, 0, 1}, {256, 1, 1, 0, 1}, {64, 4, 1, 3, 1}, {64, 1, 4, 2, 0}};
+    {64, 4, 1, 0, 0}, {64, 4, 1, 0, 1}, {64, 4, 1, 2, 0}, {64, 4, 1, 2, 2}, {64, 2, 1, 0, 1},
+    {64, 1, 1, 0, 1}, {128, 2, 1, 0, 1}, {256, 1, 1, 0, 1}, {64, 1, 1, 2, 2}, {64, 2, 2, 2, 2}};
 
 struct LaunchArgs {
   int op = 0;

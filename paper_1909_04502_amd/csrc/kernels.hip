@@ -18,6 +18,8 @@
 //    evaluated in double for every storage mode.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include <utility>
 
 #include "device_math.h"
@@ -301,20 +303,43 @@ __device__ __forceinline__ void store_site(S *__restrict__ fout, int64_t sites, 
 }
 
 // Site of this thread.  Blocks form a 1D grid over tiles of blockDim.x x
-// blockDim.y x blockDim.z sites (x fastest, then y, then z).  The hardware
-// deals consecutive blocks round-robin to the 8 XCDs; with xcd != 0 the block
-// id is remapped so that each XCD receives a contiguous range of tiles, i.e. a
-// band of neighbouring rows whose halo rows stay in that XCD's L2.
+// blockDim.y x blockDim.z sites.  The hardware deals consecutive blocks
+// round-robin to the 8 XCDs, each with its own L2.  Tile orders:
+//   xcd == 0: x fastest, then y, then z, as dealt;
+//   xcd == 1: each XCD receives a contiguous range of that order (a band of
+//             neighbouring rows whose halo rows stay in its L2);
+//   xcd == 2: (3D) the rows are grouped in patches of kPatch x kPatch rows in
+//             (y, z); XCD k takes patches k, k + 8, ... and walks each patch
+//             with x fastest, so the blocks in flight on an XCD cover one
+//             compact patch and read each other's y and z halo rows while
+//             they are still in its L2.  The grid then has 8 * ceil(patches /
+//             8) * tiles-per-patch blocks; those past the lattice return.
+constexpr int kPatch = 8;
+
 __device__ __forceinline__ bool site_coords(const Tables *__restrict__ tb, int xcd, int &x, int &y, int &z) {
   const uint32_t gx = (tb->nx + blockDim.x - 1) / blockDim.x;
   const uint32_t gy = (tb->ny + blockDim.y - 1) / blockDim.y;
   const uint32_t nb = gridDim.x;
   uint32_t t = blockIdx.x;
-  if (xcd) {
-    const uint32_t q = nb / 8, r = nb % 8, k = t % 8, l = t / 8;
-    t = k * q + (k < r ? k : r) + l;
+  uint32_t tx, ty, tz;
+  if (xcd == 2) {
+    const uint32_t py = max(1u, kPatch / blockDim.y), pz = max(1u, kPatch / blockDim.z);   // tile rows per patch
+    const uint32_t npy = (gy + py - 1) / py;
+    const uint32_t per = gx * py * pz;                                     // tiles per patch
+    const uint32_t k = t % 8, l = t / 8;
+    const uint32_t p = (l / per) * 8 + k, w = l % per;
+    tx = w % gx;
+    ty = (p % npy) * py + (w / gx) % py;
+    tz = (p / npy) * pz + w / (gx * py);
+  } else {
+    if (xcd) {
+      const uint32_t q = nb / 8, r = nb % 8, k = t % 8, l = t / 8;
+      t = k * q + (k < r ? k : r) + l;
+    }
+    tx = t % gx;
+    ty = (t / gx) % gy;
+    tz = t / (gx * gy);
   }
-  const uint32_t tx = t % gx, ty = (t / gx) % gy, tz = t / (gx * gy);
   x = tx * blockDim.x + threadIdx.x;
   y = ty * blockDim.y + threadIdx.y;
   z = tz * blockDim.z + threadIdx.z;
@@ -424,19 +449,26 @@ static hipError_t launch_t(const LaunchArgs &a) {
   const Variant vr = kVariants[(a.op == OP_STEP && a.variant >= 0 && a.variant < kNumVariants) ? a.variant : 0];
   const int by = ST::D == 2 ? vr.by * vr.bz : vr.by, bz = ST::D == 2 ? 1 : vr.bz;
   dim3 block(vr.bx, by, bz);
-  const long nb = (long)((a.nx + vr.bx - 1) / vr.bx) * ((a.ny + by - 1) / by) * ((a.nz + bz - 1) / bz);
+  const long gx = (a.nx + vr.bx - 1) / vr.bx, gy = (a.ny + by - 1) / by, gz = (a.nz + bz - 1) / bz;
+  const int order = (ST::D == 2 && vr.xcd == 2) ? 1 : vr.xcd;
+  long nb = gx * gy * gz;
+  if (order == 2) {
+    const long py = std::max(1, kPatch / by), pz = std::max(1, kPatch / bz);
+    const long npatch = ((gy + py - 1) / py) * ((gz + pz - 1) / pz);
+    nb = 8 * ((npatch + 7) / 8) * gx * py * pz;
+  }
   dim3 grid((unsigned)nb, 1, 1);
   switch (a.op) {
     case OP_STEP:
       if (vr.occ == 2)
         hipLaunchKernelGGL((k_step<ST, N, S, DEV, 2>), grid, block, 0, a.stream, a.tb, (const S *)a.fin,
-                           (S *)a.fout, a.tau_field, a.fields, a.err, vr.xcd);
+                           (S *)a.fout, a.tau_field, a.fields, a.err, order);
       else if (vr.occ == 3)
         hipLaunchKernelGGL((k_step<ST, N, S, DEV, 3>), grid, block, 0, a.stream, a.tb, (const S *)a.fin,
-                           (S *)a.fout, a.tau_field, a.fields, a.err, vr.xcd);
+                           (S *)a.fout, a.tau_field, a.fields, a.err, order);
       else
         hipLaunchKernelGGL((k_step<ST, N, S, DEV, 0>), grid, block, 0, a.stream, a.tb, (const S *)a.fin,
-                           (S *)a.fout, a.tau_field, a.fields, a.err, vr.xcd);
+                           (S *)a.fout, a.tau_field, a.fields, a.err, order);
       break;
     case OP_MOMENTS:
       hipLaunchKernelGGL((k_moments<ST, N, S, DEV>), grid, block, 0, a.stream, a.tb, (const S *)a.fin, a.fields,
