@@ -74,9 +74,10 @@ struct Offs {
 // the transpose of the streaming operator on a periodic grid (the adjoint
 // gather dL/dB(y) = sum_taps w dL/dF(y - o)).
 // 3D: the 26 directions of a shell fall into groups of at most 16 taps (the
-// axes, the edges by fours, the corners by twos); the loads of group g may not
-// be issued before the populations of group g - 3 are complete, so at most
-// three groups of taps are in flight per wave instead of all of them.
+// axes, the edges by fours, the corners by twos); the loads of group g depend
+// (through an empty asm on the plane base) on every population of group g - 3,
+// so at most three groups of taps are in flight per wave instead of all of
+// them, and the registers their loads occupy stay bounded.
 __device__ __forceinline__ constexpr bool group_start_3d(int k) {
   return k == 0 || k == 6 || k == 10 || k == 14 || k == 18 || k == 20 || k == 22 || k == 24;
 }
@@ -89,11 +90,12 @@ __device__ __forceinline__ void pull_prod(const Tables *__restrict__ tb, const S
   constexpr int D = ST::D, ND = ST::NDIR, KR = ST::NSHELL;
   typedef const __attribute__((address_space(1))) char gchar;   // keeps the loads global after laundering
   gchar *base = (gchar *)fin;
-  // last populations of the previous groups (ends[0] most recent); group g waits for ends[kDepth - 1]
+  // population ranges [first, last] of the previous groups (index 0 most recent); the loads of a
+  // group depend on every population of the group kDepth back
   constexpr int kDepth = 3;
-  int ends[kDepth];
+  int gfirst[kDepth], glast[kDepth];
 #pragma unroll
-  for (int e = 0; e < kDepth; ++e) ends[e] = -1;
+  for (int e = 0; e < kDepth; ++e) gfirst[e] = glast[e] = -1;
 #pragma unroll
   for (int j = 0; j < KR; ++j) {
     const A v = tab<A>(tb->sv[j], tb->svf[j]);
@@ -117,7 +119,10 @@ __device__ __forceinline__ void pull_prod(const Tables *__restrict__ tb, const S
     for (int k = 0; k < ND; ++k) {
       const int i = j * ND + k;
       if constexpr (D == 3) {
-        if (group_start_3d(k) && ends[kDepth - 1] >= 0) asm volatile("" : "+s"(base) : "v"(f[ends[kDepth - 1]]));
+        if (group_start_3d(k) && glast[kDepth - 1] >= 0) {
+#pragma unroll
+          for (int q = gfirst[kDepth - 1]; q <= glast[kDepth - 1]; ++q) asm volatile("" : "+s"(base) : "v"(f[q]));
+        }
       }
       gchar *plane = base + (int64_t)i * sites * (int64_t)sizeof(S);
       const int dx = ST::dir(k, 0), dy = ST::dir(k, 1), dz = D == 3 ? ST::dir(k, D - 1) : 0;
@@ -154,12 +159,13 @@ __device__ __forceinline__ void pull_prod(const Tables *__restrict__ tb, const S
       }
       if constexpr (D == 3) {
         if (k == ND - 1 || group_start_3d(k + 1)) {
-          // the group is complete here: its loads are consumed and their registers free
 #pragma unroll
-          for (int q = group_first_3d(k); q <= k; ++q) asm volatile("" : "+v"(f[j * ND + q]));
-#pragma unroll
-          for (int e = kDepth - 1; e > 0; --e) ends[e] = ends[e - 1];
-          ends[0] = i;
+          for (int e = kDepth - 1; e > 0; --e) {
+            gfirst[e] = gfirst[e - 1];
+            glast[e] = glast[e - 1];
+          }
+          gfirst[0] = j * ND + group_first_3d(k);
+          glast[0] = i;
         }
       }
     }
