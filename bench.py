@@ -43,6 +43,7 @@ def parse():
     ap.add_argument("--batch-count", type=int, default=256)
     ap.add_argument("--no-3d", action="store_true")
     ap.add_argument("--no-onlattice", action="store_true")
+    ap.add_argument("--no-forcing", action="store_true")
     ap.add_argument("--size-3d", type=int, default=256)
     return ap.parse_args()
 
@@ -291,6 +292,26 @@ def onlattice_leg(warmup, steps):
     return out
 
 
+def forcing_leg(L, warmup, steps):
+    """The headline workload with the external force of Sec. 5.4 (scheme B, g = 1e-6 along y) and no-slip
+    equilibrium walls on the x faces: the force/wall build of the step kernel."""
+    import torch
+    import workloads as W
+    from paper_1909_04502_amd import rlbm as R
+    n, T, u = W.taylor_green_2d(L, L, 0.1, density_sigma=1e-3, seed=2)
+    lat = R.Lattice(d=2, zeta=1.0, order=3, extent=(L, L), bc=("wall", "periodic"), tau=0.8, force=(0.0, 1e-6))
+    fa = lat.init(torch.tensor(n), torch.tensor(T), torch.tensor(u))
+    fb = lat.new_state()
+    t = time_steps(lat, fa, fb, warmup, steps)
+    b = 2 * lat.Q * 8 * L * L
+    out = {"workload": f"{L}x{L} zeta=1 N=3 f64, walls on x, g = 1e-6 along y", "MLUPS": round(L * L / t / 1e6, 2),
+           "ms_per_step": round(t * 1e3, 5), "achieved_GBs": round(b / t / 1e9, 1),
+           "frac": round(b / t / 1e9 / HBM_PEAK_GBS, 4)}
+    del lat, fa, fb
+    torch.cuda.empty_cache()
+    return out
+
+
 def cpu_baseline(seconds):
     """The FP64 oracle (as it stands) on a 128 x 128 lattice of the same workload, on this host's cores."""
     import torch
@@ -375,6 +396,8 @@ def main():
                                         "f32dev")
     if not args.no_onlattice:
         out["onlattice_ur"] = onlattice_leg(args.warmup, args.steps)
+    if not args.no_forcing:
+        out["forcing_walls"] = forcing_leg(L, args.warmup, args.steps)
     if not args.no_copy:
         cb = copy_bandwidth(Q * 8 * sites)
         out["roofline"]["copy_GBs"] = round(cb, 1)

@@ -80,7 +80,11 @@ typedef enum {
 } rlbm_status;
 
 typedef enum { RLBM_F64 = 0, RLBM_F32_DEV = 1 } rlbm_storage;
-typedef enum { RLBM_PERIODIC = 0, RLBM_OPEN = 1 } rlbm_bc;
+/* RLBM_WALL: reads clamp as RLBM_OPEN, and the first and last plane of the
+ * axis are no-slip walls whose collision is replaced by the local equilibrium
+ * at zero flow speed (the site's own n and T; the walls of the forcing
+ * validation, Sec. 7.2).  Product rules only. */
+typedef enum { RLBM_PERIODIC = 0, RLBM_OPEN = 1, RLBM_WALL = 2 } rlbm_bc;
 typedef enum {
   RLBM_QUAD_UR_ONLATTICE = 0, /* printed massless (2+1)-d order-2 rule, integer streaming (zeta = 0) */
   RLBM_QUAD_PRODUCT = 1       /* off-lattice product rule: shells x directions, interpolated streaming */
@@ -104,6 +108,11 @@ typedef struct {
   double tau;          /* relaxation time, used where tau_field is NULL; > 0.5 recommended */
   const void *tau_field; /* device [sites] per-site tau, double (F64) or float (F32_DEV), or NULL */
   double n_ref;        /* reference density of the F32_DEV deviations (T_ref = 1, U = 0) */
+  double force[3];     /* constant acceleration g (lattice units, first d used) of the external
+                        * force of Sec. 5.4, scheme B: Minkowski force K = p^0 g, K^0 = g.p;
+                        * the update subtracts F^ext_i = -(m/T) (K^a U_a / p_i^0) f^eq_i, the
+                        * sign of the kinetic equation (the fluid accelerates along g).  Zero =
+                        * no force; no effect for zeta = 0 (the term carries the mass). */
 } rlbm_config;
 
 typedef struct {

@@ -7,12 +7,19 @@ Layout: populations f have shape (Q, ny, nx) in 2D and (Q, nz, ny, nx) in
 leading (d+1) axis.  The quadrature order of populations is the one documented
 in ``oracle.quadrature``.
 
-One time step (Sec. 6.2, the eight numbered operations; forcing omitted):
+One time step (Sec. 6.2, the eight numbered operations):
  1. N^a = sum_i f_i p_i^a,  T^ab = sum_i f_i p_i^a p_i^b
  2. eps U^a = T^ab U_b with eps the largest eigenvalue (Landau frame, Sec. 4)
  3. n = U_a N^a
  4. T from the equation of state eps/n = T (G_d(m/T) - 1)
  5. f^eq_i = w_i sum_k a^(k) J^(k)(p_i)
+ 6. optional external force (Sec. 5.4, scheme B): a constant acceleration g
+    acting through the Minkowski force K = p^0 g, K^0 = g . p (so K.p = 0);
+    with df^eq/dp^a = -(U_a/T) f^eq the force term of the kinetic equation is
+    F^ext_i = -(m/T) (K^a U_a / p_i^0) f^eq_i, and the update subtracts it
+    (the kinetic equation carries -F^ext; Sec. 6.2 prints "+ F^ext", read here
+    as the same term with the equation's sign, which accelerates the fluid
+    along g).
  7. tau: a constant or a per-site field
  8. f_i(x + v_i dt, t + dt) = (1 - Omega_i) f_i + Omega_i f^eq_i with
     Omega_i = dt p_i^mu U_mu / (p_i^0 tau), dt = 1.
@@ -22,7 +29,10 @@ shifted value is read back on the grid by linear interpolation of the
 post-collision field at x - delta_i (bilinear in 2D, trilinear in 3D); the
 paper leaves interpolation schemes aside (Sec. 5.3), so this is a reading.
 Boundaries: periodic, or "open" = zero-gradient: a read outside the grid
-takes the value of the nearest boundary plane.
+takes the value of the nearest boundary plane, or "wall": the open read plus
+no-slip walls on the first and last plane of the axis, where the collision is
+replaced by the local equilibrium at zero flow speed (n and T of the site,
+U = (1, 0, ...)), as in the forcing validation of Sec. 7.2.
 """
 from __future__ import annotations
 
@@ -57,7 +67,7 @@ class Lattice:
     "open" in the same order; ``tau`` a float or a tensor of grid shape.
     """
 
-    def __init__(self, quad: Quadrature, tau, extent, bc=None):
+    def __init__(self, quad: Quadrature, tau, extent, bc=None, force=None):
         self.quad = quad
         self.d = quad.d
         self.m = float(quad.m)
@@ -70,6 +80,7 @@ class Lattice:
         self.bc = tuple(bc) if bc is not None else ("periodic",) * self.d
         self.tau = tau
         self.eta = eta_matrix(self.d)
+        self.force = None if force is None else torch.as_tensor(force, dtype=torch.float64)[: self.d]
 
     # -- step 1 -------------------------------------------------------------
     def moments(self, f):
@@ -135,14 +146,46 @@ class Lattice:
         shape = (-1,) + (1,) * (pU.dim() - 1)
         return pU / (self.p[:, 0].reshape(shape) * tau)
 
+    def forcing(self, T, U, feq):
+        """F^ext_i = -(m/T) (K^a U_a / p_i^0) f^eq_i with K = (g . p_i, p_i^0 g) (Sec. 5.4, scheme B)."""
+        g = self.force
+        Kdot = torch.einsum("ia,a->i", self.p[:, 1:], g)                  # K^0 = g . p
+        KU = Kdot.reshape((-1,) + (1,) * (U.dim() - 1)) * U[0] - \
+            self.p[:, 0].reshape((-1,) + (1,) * (U.dim() - 1)) * torch.einsum("a,a...->...", g, U[1:])[None]
+        return -(self.m / T)[None] * KU / self.p[:, 0].reshape((-1,) + (1,) * (U.dim() - 1)) * feq
+
+    def wall_mask(self, grid_shape):
+        """Sites on the first and last plane of every "wall" axis."""
+        mask = torch.zeros(grid_shape, dtype=torch.bool)
+        for ax in range(self.d):
+            if self.bc[ax] == "wall":
+                dim = len(grid_shape) - 1 - ax
+                idx = [slice(None)] * len(grid_shape)
+                idx[dim] = 0
+                mask[tuple(idx)] = True
+                idx[dim] = grid_shape[dim] - 1
+                mask[tuple(idx)] = True
+        return mask
+
     def collide(self, f, tau=None):
-        """f*_i = f_i + Omega_i (f^eq_i - f_i) at every site of ``f`` (shape (Q, ...))."""
+        """f*_i = f_i + Omega_i (f^eq_i - f_i) - F^ext_i at every site of ``f`` (shape (Q, ...));
+        wall sites take the local equilibrium at rest."""
         mac = self.macro(f)
         feq = self.equilibrium(mac["n"], mac["T"], mac["U"])
         if tau is None:
             tau = self.tau_at(mac["n"])
         Om = self.omega(mac["U"], tau)
-        return f + Om * (feq - f)
+        out = f + Om * (feq - f)
+        if self.force is not None and self.m > 0.0:
+            out = out - self.forcing(mac["T"], mac["U"], feq)
+        if "wall" in self.bc:
+            mask = self.wall_mask(f.shape[1:])
+            if mask.any():
+                rest = torch.zeros_like(mac["U"])
+                rest[0] = 1.0
+                feq0 = self.equilibrium(mac["n"], mac["T"], rest)
+                out = torch.where(mask[None], feq0, out)
+        return out
 
     # -- streaming ----------------------------------------------------------
     def _gather(self, a, offset):
@@ -156,7 +199,7 @@ class Lattice:
             nax = a.shape[dim]
             if self.bc[ax] == "periodic":
                 out = torch.roll(out, shifts=-o, dims=dim)
-            else:
+            else:                                   # "open" and "wall" read the nearest plane
                 idx = torch.clamp(torch.arange(nax) + o, 0, nax - 1)
                 out = torch.index_select(out, dim, idx)
         return out

@@ -80,6 +80,16 @@ rlbm::FieldPtrs field_ptrs(const rlbm_fields *f) {
   return p;
 }
 
+// the lattice needs the force / wall build of the step kernel
+int lattice_ext(const rlbm_lattice *h) {
+  if (h->cfg.model.kind != RLBM_QUAD_PRODUCT) return 0;
+  for (int a = 0; a < h->cfg.model.d; ++a) {
+    if (h->cfg.bc[a] == RLBM_WALL) return 1;
+    if (h->cfg.force[a] != 0.0 && h->cfg.model.zeta > 0.0) return 1;
+  }
+  return 0;
+}
+
 rlbm::LaunchArgs base_args(const rlbm_lattice *h, hipStream_t stream) {
   rlbm::LaunchArgs a;
   a.stencil = h->stencil;
@@ -93,6 +103,7 @@ rlbm::LaunchArgs base_args(const rlbm_lattice *h, hipStream_t stream) {
   a.err = h->d_err;
   a.stream = stream;
   a.variant = h->variant;
+  a.ext = lattice_ext(h);
   return a;
 }
 
@@ -139,7 +150,11 @@ rlbm_status rlbm_create(const rlbm_config *cfg, rlbm_lattice **out) {
   if (m.d != 2 && m.d != 3) return fail(RLBM_ERR_UNSUPPORTED, "d must be 2 or 3");
   for (int a = 0; a < m.d; ++a) {
     if (cfg->extent[a] < 1 || cfg->extent[a] > (1 << 20)) return fail(RLBM_ERR_INVALID_ARG, "extent out of range");
-    if (cfg->bc[a] != RLBM_PERIODIC && cfg->bc[a] != RLBM_OPEN) return fail(RLBM_ERR_INVALID_ARG, "bad bc");
+    if (cfg->bc[a] != RLBM_PERIODIC && cfg->bc[a] != RLBM_OPEN && cfg->bc[a] != RLBM_WALL)
+      return fail(RLBM_ERR_INVALID_ARG, "bad bc");
+    if (cfg->bc[a] == RLBM_WALL && m.kind != RLBM_QUAD_PRODUCT)
+      return fail(RLBM_ERR_UNSUPPORTED, "walls are built for product rules");
+    if (!std::isfinite(cfg->force[a])) return fail(RLBM_ERR_INVALID_ARG, "force must be finite");
   }
   if (m.d == 3 && m.kind == RLBM_QUAD_UR_ONLATTICE) return fail(RLBM_ERR_UNSUPPORTED, "on-lattice rule is 2D");
   if (cfg->storage != RLBM_F64 && cfg->storage != RLBM_F32_DEV) return fail(RLBM_ERR_INVALID_ARG, "bad storage");
@@ -172,6 +187,15 @@ rlbm_status rlbm_create(const rlbm_config *cfg, rlbm_lattice **out) {
   rc = rlbm::build_tables(h->quad, cfg->tau, cfg->storage == RLBM_F32_DEV ? cfg->n_ref : 1.0, cfg->storage,
                           cfg->extent, bc, *t, err);
   if (!rc && m.d == 3) rc = rlbm::build_eos_fit(m.zeta, *t, err);
+  if (!rc) {
+    for (int a = 0; a < 3; ++a) {
+      t->g[a] = a < m.d ? cfg->force[a] : 0.0;
+      t->gf[a] = (float)t->g[a];
+    }
+    // the force term carries the mass: nothing to add for zeta = 0
+    t->has_force = (m.zeta > 0.0 && m.kind == RLBM_QUAD_PRODUCT &&
+                    (t->g[0] != 0.0 || t->g[1] != 0.0 || t->g[2] != 0.0)) ? 1 : 0;
+  }
   if (rc) {
     delete t;
     delete h;
@@ -321,6 +345,9 @@ static rlbm_status adjoint_supported(const rlbm_lattice *h) {
     return fail(RLBM_ERR_UNSUPPORTED, "reverse mode is implemented for the 2D product rules");
   for (int a = 0; a < 2; ++a)
     if (h->cfg.bc[a] != RLBM_PERIODIC) return fail(RLBM_ERR_UNSUPPORTED, "reverse mode needs periodic boundaries");
+  for (int a = 0; a < h->cfg.model.d; ++a)
+    if (h->cfg.force[a] != 0.0 && h->cfg.model.zeta > 0.0)
+      return fail(RLBM_ERR_UNSUPPORTED, "reverse mode has no force term");
   return RLBM_OK;
 }
 
@@ -533,6 +560,8 @@ static hipError_t batch_enqueue(rlbm_batch *b, void *f_a, void *f_b, int32_t nst
   a.ntiles = b->ntiles;
   a.err = b->d_err;
   a.stream = stream;
+  a.ext = 0;
+  for (auto *h : b->lats) a.ext |= lattice_ext(h);
   for (int32_t s = 0; s < nsteps; ++s) {
     a.fin = (s & 1) ? f_b : f_a;
     a.fout = (s & 1) ? f_a : f_b;

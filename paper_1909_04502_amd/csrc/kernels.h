@@ -39,6 +39,7 @@ struct LaunchArgs {
   const double *n0 = nullptr, *T0 = nullptr, *u0 = nullptr, *noise = nullptr;
   double amp = 0.0;
   int *err = nullptr;               // device error flag
+  int ext = 0;                      // the lattice has an external force or no-slip walls
   hipStream_t stream = 0;
 };
 
@@ -81,6 +82,7 @@ struct BatchArgs {
   void *fout = nullptr;
   int *err = nullptr;
   hipStream_t stream = 0;
+  int ext = 0;                   // some member has an external force or no-slip walls
 };
 hipError_t launch_batch(const BatchArgs &a);
 

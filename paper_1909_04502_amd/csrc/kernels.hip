@@ -286,12 +286,19 @@ __device__ __forceinline__ void gather(const Tables *__restrict__ tb, const S *_
   }
 }
 
-template <class ST, int N, typename S, bool DEV, bool RELAX>
-__device__ __forceinline__ Macro<ST::D> collide_site(const Tables *__restrict__ tb, S (&f)[ST::Q], double tau) {
+template <class ST, int N, typename S, bool DEV, bool RELAX, bool EXT = false>
+__device__ __forceinline__ Macro<ST::D> collide_site(const Tables *__restrict__ tb, S (&f)[ST::Q], double tau,
+                                                     bool wall = false) {
   if constexpr (ST::ONLAT)
     return collide<ST, N, S, DEV, RELAX>(tb, f, tau);
   else
-    return collide_prod<ST, N, S, DEV, RELAX>(tb, f, tau);
+    return collide_prod<ST, N, S, DEV, RELAX, EXT>(tb, f, tau, wall);
+}
+
+// the site lies on a no-slip wall plane (first or last plane of a wall axis)
+__device__ __forceinline__ bool on_wall(const Tables *__restrict__ tb, int x, int y, int z) {
+  return (tb->wall[0] && (x == 0 || x == tb->nx - 1)) || (tb->wall[1] && (y == 0 || y == tb->ny - 1)) ||
+         (tb->wall[2] && (z == 0 || z == tb->nz - 1));
 }
 
 // post-collision store: plane base (uniform) + 32-bit byte offset of the site
@@ -346,7 +353,7 @@ __device__ __forceinline__ bool site_coords(const Tables *__restrict__ tb, int x
   return x < tb->nx && y < tb->ny && z < tb->nz;
 }
 
-template <class ST, int N, typename S, bool DEV, int OCC>
+template <class ST, int N, typename S, bool DEV, int OCC, bool EXT = false>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(OCC > 0 ? OCC : 1, 8))) k_step(const Tables *__restrict__ tb, const S *__restrict__ fin,
                                               S *__restrict__ fout, const void *__restrict__ tau_field,
                                               FieldPtrs last, int *err, int xcd) {
@@ -357,7 +364,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(OCC > 
   S f[ST::Q];
   gather<ST, S>(tb, fin, sites, x, y, z, f);
   const double tau = site_tau<S>(tb, tau_field, site);
-  const Macro<ST::D> mac = collide_site<ST, N, S, DEV, true>(tb, f, tau);
+  const Macro<ST::D> mac = collide_site<ST, N, S, DEV, true, EXT>(tb, f, tau, EXT && on_wall(tb, x, y, z));
   if (!mac.ok) flag_error(err);
   // a fresh copy of the plane size for the store addresses: otherwise the compiler keeps the
   // load phase's plane offsets alive (in spilled scalar registers) for reuse here
@@ -435,7 +442,7 @@ __global__ void __launch_bounds__(256) k_init(const Tables *__restrict__ tb, con
 #pragma unroll
   for (int i = 0; i < Q; ++i) f[i] = DEV ? (S)(fd[i] - tb->fref[i]) : (S)fd[i];
   const double tau = site_tau<S>(tb, tau_field, site);
-  const Macro<D> mac = collide_site<ST, N, S, DEV, true>(tb, f, tau);
+  const Macro<D> mac = collide_site<ST, N, S, DEV, true, true>(tb, f, tau, on_wall(tb, x, y, z));
   if (!mac.ok) flag_error(err);
   store_site<ST, S>(fout, sites, (uint32_t)site * (uint32_t)sizeof(S), f);
   if (fields0.any) write_fields<D>(fields0, site, sites, mac);
@@ -460,7 +467,10 @@ static hipError_t launch_t(const LaunchArgs &a) {
   dim3 grid((unsigned)nb, 1, 1);
   switch (a.op) {
     case OP_STEP:
-      if (vr.occ == 2)
+      if (a.ext)
+        hipLaunchKernelGGL((k_step<ST, N, S, DEV, 0, true>), grid, block, 0, a.stream, a.tb, (const S *)a.fin,
+                           (S *)a.fout, a.tau_field, a.fields, a.err, order);
+      else if (vr.occ == 2)
         hipLaunchKernelGGL((k_step<ST, N, S, DEV, 2>), grid, block, 0, a.stream, a.tb, (const S *)a.fin,
                            (S *)a.fout, a.tau_field, a.fields, a.err, order);
       else if (vr.occ == 3)

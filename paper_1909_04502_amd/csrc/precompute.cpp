@@ -415,7 +415,10 @@ int build_tables(const QuadHost &q, double tau, double n_ref, int storage, const
   t.nx = (int32_t)extent[0];
   t.ny = (int32_t)extent[1];
   t.nz = (int32_t)(d == 3 ? extent[2] : 1);
-  for (int a = 0; a < 3; ++a) t.open[a] = (a < d) ? (bc[a] == RLBM_OPEN) : 0;
+  for (int a = 0; a < 3; ++a) {
+    t.open[a] = (a < d) ? (bc[a] == RLBM_OPEN || bc[a] == RLBM_WALL) : 0;
+    t.wall[a] = (a < d) ? (bc[a] == RLBM_WALL) : 0;
+  }
   t.storage = storage;
   t.sites = (int64_t)t.nx * t.ny * t.nz;
   t.m = q.m;
@@ -640,6 +643,7 @@ int build_tables(const QuadHost &q, double tau, double n_ref, int storage, const
       ld f = 0.0L;
       for (int k = 0; k < NM; ++k) f += R[i * NM + k] * M[k];
       t.fref[i] = (double)f;
+      t.freff[i] = (float)f;
       for (int a = 0; a < D1; ++a) {
         Nr[a] += f * (ld)q.p[i * D1 + a];
         for (int b = 0; b < D1; ++b) Tr[a][b] += f * (ld)q.p[i * D1 + a] * (ld)q.p[i * D1 + b];

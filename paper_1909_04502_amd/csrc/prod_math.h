@@ -172,8 +172,12 @@ __device__ __forceinline__ void pull_prod(const Tables *__restrict__ tb, const S
   }
 }
 
-template <class ST, int N, typename S, bool DEV, bool RELAX>
-__device__ __forceinline__ Macro<ST::D> collide_prod(const Tables *__restrict__ tb, S (&f)[ST::Q], double tau) {
+// EXT: build the external-force term and the no-slip wall sites in (a separate
+// instantiation, so that lattices without them keep the leaner kernel).
+template <class ST, int N, typename S, bool DEV, bool RELAX, bool EXT = false>
+__device__ __forceinline__ Macro<ST::D> collide_prod(const Tables *__restrict__ tb, S (&f)[ST::Q], double tau,
+                                                     bool wall_site = false) {
+  const bool wall = EXT && wall_site;
   constexpr int D = ST::D, ND = ST::NDIR, NPD = ND / 2, KR = ST::NSHELL;
   using B = BasisDef<D, N>;
   constexpr AngTable<D, N> AT{};
@@ -275,6 +279,10 @@ __device__ __forceinline__ Macro<ST::D> collide_prod(const Tables *__restrict__ 
   }
   mac.ok = mac.ok && mac.n > 0.0 && mac.eps > 0.0;
   if constexpr (!RELAX) return mac;
+  // a no-slip wall site relaxes fully (Omega = 1) to the equilibrium at rest of its own n, T
+  double Ue[D + 1];
+#pragma unroll
+  for (int a = 0; a <= D; ++a) Ue[a] = wall ? (a == 0 ? 1.0 : 0.0) : mac.U[a];
   // ---- step 5: a' = G^{-1} M over parity blocks ----
   A ap[B::NM];
   if constexpr (D == 3) {
@@ -294,7 +302,7 @@ __device__ __forceinline__ Macro<ST::D> collide_prod(const Tables *__restrict__ 
 #pragma unroll
       for (int t = 0; t < CL.cnt[c]; ++t) {
         const int k = CL.idx[c][t];
-        mc[t] = basis_moment<D, N>(k, mac.n, mac.T, mac.U, rr);
+        mc[t] = basis_moment<D, N>(k, mac.n, mac.T, Ue, rr);
         if constexpr (DEV) mc[t] -= tb->Mref[k];
       }
       // moments of the shifted monomials (p^0 - m) p^e = p^0 p^e - m p^e
@@ -323,7 +331,7 @@ __device__ __forceinline__ Macro<ST::D> collide_prod(const Tables *__restrict__ 
     }
   } else {
     double Md[B::NM];
-    basis_moments<D, N>(mac.n, mac.T, mac.U, rr, Md);
+    basis_moments<D, N>(mac.n, mac.T, Ue, rr, Md);
     if constexpr (DEV) {
 #pragma unroll
       for (int k = 0; k < B::NM; ++k) Md[k] -= tb->Mref[k];
@@ -354,8 +362,8 @@ __device__ __forceinline__ Macro<ST::D> collide_prod(const Tables *__restrict__ 
     }
   }
   // ---- step 8 ingredients: Omega_jk = a0 - v_j (n_k . U)/tau ----
-  const double itau = 1.0 / tau;
-  const A a0 = (A)(mac.U[0] * itau);
+  const double itau = wall ? 0.0 : 1.0 / tau;
+  const A a0 = wall ? (A)1 : (A)(mac.U[0] * itau);
   A nU[NPD];
 #pragma unroll
   for (int q = 0; q < NPD; ++q) {
@@ -367,6 +375,27 @@ __device__ __forceinline__ Macro<ST::D> collide_prod(const Tables *__restrict__ 
     }
     nU[q] = (A)(acc * itau);
   }
+  // ---- step 6, external force (Sec. 5.4, scheme B): the update adds
+  //      (m/T) (K^a U_a / p_i^0) f^eq_i = (m/T) ((g . v_i) U^0 - g . U) f^eq_i ----
+  const bool force = EXT && tb->has_force && !wall;
+  A cF = 0, cU0 = 0, gU = 0;
+  if (force) {
+    cF = (A)(tb->m / mac.T);
+    cU0 = (A)mac.U[0];
+    double acc = 0.0;
+#pragma unroll
+    for (int a = 0; a < D; ++a) acc += tb->g[a] * mac.U[a + 1];
+    gU = (A)acc;
+  }
+  auto gdotn = [&](int q) {   // g . n_k of the pair's first member
+    A acc = 0;
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+      const double c = nhat<ST>(2 * q, a);
+      if (c != 0.0) acc += (A)c * tab<A>(tb->g[a], tb->gf[a]);
+    }
+    return acc;
+  };
   if constexpr (D == 3) {
     // Direction-major: f^eq_jk = sum_l (s0_jl P0_kl + s1_jl P1_kl) with the
     // shell-independent angular sums P_kl = sum_{|e| = l} a'_{m(e)} w_k n_k^e,
@@ -393,12 +422,20 @@ __device__ __forceinline__ Macro<ST::D> collide_prod(const Tables *__restrict__ 
           if (l & 1) O += t;
           else E += t;
         }
-        const A b = tab<A>(tb->sv[j], tb->svf[j]) * nU[qp];
+        const A vj = tab<A>(tb->sv[j], tb->svf[j]);
+        const A b = vj * nU[qp];
         const A om0 = a0 - b, om1 = a0 + b;
         const int i = j * ND + k;
         const A f0 = f[i], f1 = f[i + 1];
         f[i] = f0 + om0 * ((E + O) - f0);
         f[i + 1] = f1 + om1 * ((E - O) - f1);
+        if (force) {
+          const A gv = vj * gdotn(qp) * cU0;
+          const A fe0 = (E + O) + (DEV ? tab<A>(tb->fref[i], tb->freff[i]) : (A)0);
+          const A fe1 = (E - O) + (DEV ? tab<A>(tb->fref[i + 1], tb->freff[i + 1]) : (A)0);
+          f[i] += cF * (gv - gU) * fe0;
+          f[i + 1] += cF * (-gv - gU) * fe1;
+        }
       }
     }
     return mac;
@@ -433,6 +470,13 @@ __device__ __forceinline__ Macro<ST::D> collide_prod(const Tables *__restrict__ 
       const A f0 = f[i], f1 = f[i + 1];
       f[i] = f0 + om0 * ((E + O) - f0);
       f[i + 1] = f1 + om1 * ((E - O) - f1);
+      if (force) {
+        const A gv = v * gdotn(qp) * cU0;
+        const A fe0 = (E + O) + (DEV ? tab<A>(tb->fref[i], tb->freff[i]) : (A)0);
+        const A fe1 = (E - O) + (DEV ? tab<A>(tb->fref[i + 1], tb->freff[i + 1]) : (A)0);
+        f[i] += cF * (gv - gU) * fe0;
+        f[i + 1] += cF * (-gv - gU) * fe1;
+      }
     }
   }
   return mac;

@@ -142,7 +142,10 @@ constexpr int kMaxPacked = 96;   // packed class blocks of Linv (91 entries for 
 struct Tables {
   // geometry and physics
   int32_t nx, ny, nz, pad0;
-  int32_t open[3], storage;     // open[a]: zero-gradient boundary on axis a
+  int32_t open[3], storage;     // open[a]: reads clamp at the edges of axis a (open or wall)
+  int32_t wall[3], has_force;   // wall[a]: no-slip equilibrium walls on the end planes of axis a
+  double g[3];                  // external acceleration (Sec. 5.4, scheme B)
+  float gf[3], pad2;
   int64_t sites;                // nx * ny * nz
   double m;                     // reduced mass zeta = m/T0
   double tau;                   // relaxation time (when no field)
@@ -172,6 +175,7 @@ struct Tables {
   double tapw[kMaxQ][8];        // interpolation weights in the stencil's tap order
   float tapwf[kMaxQ][8];
   double fref[kMaxQ];           // reference populations f^ref (F32_DEV)
+  float freff[kMaxQ];
   // reference moments (F32_DEV): N^a, T^ab upper triangle, basis moments
   double Nref[4];
   double Tref[10];

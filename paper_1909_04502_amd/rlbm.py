@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(HERE, "librlbm.so")
 OK, ERR_INVALID_ARG, ERR_UNSUPPORTED, ERR_QUADRATURE, ERR_DEVICE, ERR_NONPHYSICAL = range(6)
 KIND = {"ur_onlattice": 0, "product": 1}
 STORAGE = {"f64": 0, "f32dev": 1}
-BC = {"periodic": 0, "open": 1}
+BC = {"periodic": 0, "open": 1, "wall": 2}
 
 
 class Model(Structure):
@@ -28,7 +28,7 @@ class Model(Structure):
 
 class Config(Structure):
     _fields_ = [("model", Model), ("extent", c_int64 * 3), ("bc", c_int32 * 3), ("storage", c_int32),
-                ("tau", c_double), ("tau_field", c_void_p), ("n_ref", c_double)]
+                ("tau", c_double), ("tau_field", c_void_p), ("n_ref", c_double), ("force", c_double * 3)]
 
 
 class Info(Structure):
@@ -172,7 +172,7 @@ class Lattice:
     """One lattice: handle of the C ABI plus the torch-side shapes."""
 
     def __init__(self, d=2, zeta=1.0, order=3, kind="product", extent=(64, 64), bc=None, storage="f64",
-                 tau=0.8, tau_field=None, n_ref=1.0, _handle=None):
+                 tau=0.8, tau_field=None, n_ref=1.0, force=None, _handle=None):
         L = lib()
         self._owned = _handle is None
         self.d = d
@@ -196,6 +196,9 @@ class Lattice:
         cfg.tau = float(tau)
         cfg.tau_field = tau_field.data_ptr() if tau_field is not None else None
         cfg.n_ref = float(n_ref)
+        self.force = tuple(float(g) for g in force) if force is not None else (0.0,) * d
+        for a in range(3):
+            cfg.force[a] = self.force[a] if a < len(self.force) else 0.0
         self.cfg = cfg
         if _handle is None:
             h = c_void_p()
@@ -358,6 +361,8 @@ class Batch:
             c.tau = float(sp["tau"])
             c.tau_field = None
             c.n_ref = 1.0
+            for a, g in enumerate(sp.get("force", ())):
+                c.force[a] = float(g)
         h = c_void_p()
         _check(L.rlbm_batch_create(cfgs, n, ctypes.byref(h)))
         self.h = h
@@ -373,7 +378,8 @@ class Batch:
             mh = c_void_p()
             _check(L.rlbm_batch_lattice(h, i, ctypes.byref(mh)))
             self.members.append(Lattice(d=2, zeta=sp["zeta"], order=order, extent=sp["extent"],
-                                        bc=sp.get("bc"), storage=storage, tau=sp["tau"], _handle=mh))
+                                        bc=sp.get("bc"), storage=storage, tau=sp["tau"], force=sp.get("force"),
+                                        _handle=mh))
         self.Q = self.members[0].Q
 
     def __del__(self):

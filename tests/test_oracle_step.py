@@ -227,3 +227,59 @@ def test_taylor_green_viscosity_slope_off_lattice():
     slope = (r2 - r1) / 0.6
     pred = 2 * k * k * mj.ce_shear_ratio(1.0, 2) / float(mj.G_d(1.0, 2))
     assert abs(slope - pred) / pred < 0.04, (slope, pred)
+
+
+# ---------------------------------------------------------------------------
+# External force (Sec. 5.4, scheme B) and no-slip walls (Sec. 7.2)
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("rule", ["p2m1", "p2m5", "p3m1"])
+def test_force_term_moments(rule):
+    """The force term conserves particle number for any state (sum p^0 F = 0: first moments of f^eq
+    are exact), and on a fluid at rest it adds momentum m n g and no energy per step
+    (sum p^0 p^a F^ext = -(m/T) g_b T^ab_eq = -m n g^a, sum p^0 p^0 F^ext = 0)."""
+    q = RULES[rule]()
+    d = q.d
+    g = torch.tensor([2e-3, -1e-3, 5e-4][:d], dtype=torch.float64)
+    lat = L.Lattice(q, 1.0, (3,) * d, force=g)
+    shape = (3,) * d
+    _, (n, T, u) = random_state(lat, shape, seed=11)
+    U = L.four_velocity(u)
+    feq = lat.equilibrium(n, T, U)
+    F = lat.forcing(T, U, feq)
+    p = lat.p
+    num = torch.einsum("i,i...->...", p[:, 0], F)
+    assert num.abs().max() < 1e-15 * feq.abs().max() * p[:, 0].max()
+    # at rest
+    n0 = torch.full(shape, 1.3, dtype=torch.float64)
+    T0 = torch.full(shape, 0.9, dtype=torch.float64)
+    U0 = torch.zeros((d + 1,) + shape, dtype=torch.float64)
+    U0[0] = 1.0
+    feq0 = lat.equilibrium(n0, T0, U0)
+    F0 = lat.forcing(T0, U0, feq0)
+    mom = torch.einsum("i,ia,i...->a...", p[:, 0], p[:, 1:], F0)
+    for a in range(d):
+        want = -lat.m * 1.3 * g[a].item()
+        assert abs(mom[a].flatten()[0].item() - want) < 1e-13 * abs(want)
+    energy = torch.einsum("i,i,i...->...", p[:, 0], p[:, 0], F0)
+    assert energy.abs().max() < 1e-15
+
+
+def test_force_accelerates_along_g_and_walls_hold_rest():
+    """One step of a uniform fluid at rest under g gains momentum +m n g (the update subtracts
+    F^ext); wall sites come out as the equilibrium at rest of their own n and T."""
+    q = RULES["p2m1"]()
+    g = torch.tensor([0.0, 1e-4], dtype=torch.float64)
+    nx, ny = 6, 4
+    lat = L.Lattice(q, 0.8, (nx, ny), bc=("wall", "periodic"), force=g)
+    n = torch.full((ny, nx), 1.0, dtype=torch.float64)
+    T = torch.full((ny, nx), 1.0, dtype=torch.float64)
+    u = torch.zeros((2, ny, nx), dtype=torch.float64)
+    f = lat.init(n, T, u)
+    fs = lat.collide(f)
+    p = lat.p
+    dmom = torch.einsum("i,i...->...", p[:, 0] * p[:, 2], fs - f)
+    interior = dmom[:, 1:-1]
+    assert torch.allclose(interior, torch.full_like(interior, lat.m * 1e-4), rtol=1e-12, atol=0)
+    # walls: the rest equilibrium of the wall sites' own n and T, i.e. unchanged here
+    assert (fs[:, :, 0] - f[:, :, 0]).abs().max() < 1e-15
+    assert (fs[:, :, -1] - f[:, :, -1]).abs().max() < 1e-15
