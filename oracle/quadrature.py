@@ -34,6 +34,18 @@ Rules:
   (+-1,+-1,+-1)_FS with group weights fixed by exactness at degrees 0, 4, 6.
   Displacements: delta_i = v_i n_i / |n_i| with v_i = |p_i| / p_i^0 and
   c dt = dx (one lattice site per step at the speed of light).
+* ``massive_onlattice_2d``: on-lattice rules for massive particles (Sec. 5.3,
+  Eqs. discrete-momentum-vectors, discrete-p0 and quadrature-problem):
+  p_i = p_i^0 (1, v0 n_i), p_i^0 = m / sqrt(1 - v0^2 |n_i|^2), n_i integer, one
+  weight per full-symmetric group of the stencil.  The weights solve the
+  square system of the orthonormality conditions written as exact moments
+  sum_i w_i (p^0)^a p^e = int omega (p^0)^a p^e for the invariants of degree
+  <= 2N (a in {0, 1}; e even, up to exchange of components); a line search
+  in v0 finds the window where all weights are non-negative.  Stencils: the
+  second-order example of Sec. 5.3 (29 vectors) and the third-order 45-vector
+  stencil of the GPU table of Sec. 6.3.  Population order: the groups as
+  listed, each group's vectors with first non-zero component positive in
+  decreasing (x, y) order, each followed by its opposite; the rest vector last.
 """
 from __future__ import annotations
 
@@ -60,6 +72,13 @@ DIRS_3D = [(1, 0, 0), (-1, 0, 0), (0, 1, 0), (0, -1, 0), (0, 0, 1), (0, 0, -1),
            (0, 1, 1), (0, -1, -1), (0, 1, -1), (0, -1, 1),
            (1, 1, 1), (-1, -1, -1), (1, 1, -1), (-1, -1, 1),
            (1, -1, 1), (-1, 1, -1), (-1, 1, 1), (1, -1, -1)]
+
+
+# Massive on-lattice stencils: full-symmetric groups, the rest vector first (as listed in Sec. 5.3)
+MASSIVE2D_GROUPS = {
+    2: [(0, 0), (1, 0), (1, 1), (2, 1), (2, 2), (3, 1)],
+    3: [(0, 0), (1, 0), (1, 1), (2, 0), (2, 1), (2, 2), (3, 0), (3, 2), (3, 3), (4, 0)],
+}
 
 
 @dataclass
@@ -209,3 +228,116 @@ def rest_frame_moment(idx, m: float, d: int) -> float:
     z = torch.tensor(float(m), dtype=torch.float64)
     n = 1.0 / mj.a_ratio(0, z, d) if d == 2 else 1.0 / float(mj.a_ratio(0, float(m), d))
     return float(mj.mj_tensor_moment(tuple(idx), n, T, U, float(m), d))
+
+
+# ---------------------------------------------------------------------------
+# Massive on-lattice rules (Sec. 5.3)
+# ---------------------------------------------------------------------------
+def fs_group(gen):
+    """The full-symmetric group of an integer vector, in the population order of the module header."""
+    members = set()
+    for perm in itertools.permutations(gen):
+        for signs in itertools.product((1, -1), repeat=len(gen)):
+            members.add(tuple(a * b for a, b in zip(perm, signs)))
+    if members == {(0,) * len(gen)}:
+        return [(0,) * len(gen)]
+    pos = sorted((n for n in members if next(c for c in n if c != 0) > 0), key=lambda n: tuple(-c for c in n))
+    out = []
+    for n in pos:
+        out.append(n)
+        out.append(tuple(-c for c in n))
+    return out
+
+
+def _invariants(order: int):
+    """(a, ex, ey): the monomials (p^0)^a px^ex py^ey, e even with ex >= ey, of degree <= 2N (2D)."""
+    rows = []
+    for a in (0, 1):
+        for deg in range(0, 2 * order + 1 - a, 2):
+            for ex in range(deg, -1, -1):
+                ey = deg - ex
+                if ex % 2 == 0 and ey % 2 == 0 and ex >= ey:
+                    rows.append((a, ex, ey))
+    return rows
+
+
+def massive_group_weights(m: float, order: int, v0: float, dps: int = 40):
+    """Weights per group (the rest vector first) solving A(v0) w = b (Sec. 5.3), in mpmath at dps digits."""
+    mpmath.mp.dps = dps
+    groups = [fs_group(g) for g in MASSIVE2D_GROUPS[order]]
+    rows = _invariants(order)
+    if len(rows) != len(groups):
+        raise ValueError("the stencil must have as many groups as invariants")
+    v = mpmath.mpf(v0)
+    M = mpmath.mpf(m)
+    A = mpmath.matrix(len(rows), len(groups))
+    for g, members in enumerate(groups):
+        for n in members:
+            p0 = M / mpmath.sqrt(1 - v * v * (n[0] ** 2 + n[1] ** 2))
+            px, py = p0 * v * n[0], p0 * v * n[1]
+            for r, (a, ex, ey) in enumerate(rows):
+                A[r, g] += p0 ** a * px ** ex * py ** ey
+    b = mpmath.matrix([rest_frame_moment((0,) * a + (1,) * ex + (2,) * ey, m, 2) for (a, ex, ey) in rows])
+    return [float(x) for x in mpmath.lu_solve(A, b)]
+
+
+def massive_feasible_window(m: float, order: int, scan: int = 600):
+    """The v0 interval where every group weight is >= 0 (line search of Sec. 5.3): a scan of
+    min_g w_g(v0) over (0, 1/max|n|), then bisection on both sides of the best point."""
+    nmax = max(math.hypot(*g) for g in MASSIVE2D_GROUPS[order])
+    grid = np.linspace(1e-3, 1.0 / nmax - 1e-4, scan)
+
+    def minw(v):
+        return min(massive_group_weights(m, order, v, dps=30))
+    vals = [minw(v) for v in grid]
+    k = int(np.argmax(vals))
+    lo, hi = grid[max(k - 1, 0)], grid[min(k + 1, scan - 1)]
+    # golden-section search for the maximum of min_g w_g on [lo, hi]
+    gr = (math.sqrt(5) - 1) / 2
+    a, b = lo, hi
+    c, d = b - gr * (b - a), a + gr * (b - a)
+    fc, fd = minw(c), minw(d)
+    for _ in range(60):
+        if fc > fd:
+            b, d, fd = d, c, fc
+            c = b - gr * (b - a)
+            fc = minw(c)
+        else:
+            a, c, fc = c, d, fd
+            d = a + gr * (b - a)
+            fd = minw(d)
+    vbest = (a + b) / 2
+    if minw(vbest) < 0:
+        raise ValueError("no v0 gives non-negative weights for this stencil and mass")
+
+    def edge(inside, outside):
+        for _ in range(80):
+            mid = (inside + outside) / 2
+            if minw(mid) >= 0:
+                inside = mid
+            else:
+                outside = mid
+        return inside
+    return edge(vbest, lo), edge(vbest, hi)
+
+
+def massive_onlattice_2d(m: float, order: int, v0: float = None) -> Quadrature:
+    """On-lattice massive (2+1)-d rule (Sec. 5.3); v0 defaults to the middle of the feasible window."""
+    if v0 is None:
+        lo, hi = massive_feasible_window(m, order)
+        v0 = 0.5 * (lo + hi)
+    wg = massive_group_weights(m, order, v0)
+    p, w, disp = [], [], []
+    rest = None
+    for gen, wgt in zip(MASSIVE2D_GROUPS[order], wg):
+        for n in fs_group(gen):
+            p0 = m / math.sqrt(1.0 - v0 * v0 * (n[0] ** 2 + n[1] ** 2))
+            row = ((p0, p0 * v0 * n[0], p0 * v0 * n[1]), wgt, (float(n[0]), float(n[1])))
+            if n == (0, 0):
+                rest = row
+            else:
+                p.append(row[0]), w.append(row[1]), disp.append(row[2])
+    p.append(rest[0]), w.append(rest[1]), disp.append(rest[2])
+    q = Quadrature(2, float(m), order, np.array(p), np.array(w), np.array(disp), True)
+    q.v0 = float(v0)
+    return q

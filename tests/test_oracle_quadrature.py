@@ -215,3 +215,33 @@ def test_first_order_ur_limit_sec52():
     assert np.abs(feq - ref).max() < 1e-14
     printed = q.w * n * (d / T + U[0] * p0 - (d - 1) * U[0] + pv @ U[1:]) / (d - 1)
     assert np.allclose(printed - ref, q.w * n * p0 / ((d - 1) * T), atol=1e-14)
+
+
+def test_massive_solver_reproduces_printed_weights_and_window():
+    """The line-search solver of Sec. 5.3 against the printed example: the group weights at
+    v0 = 0.2726 and the two v0 where a weight reaches zero (pruning to 25 vectors)."""
+    g = json.load(open(os.path.join(GOLDEN, "massive_2d_m5_order2.json")))
+    w = qd.massive_group_weights(g["m"], g["order"], g["v0"])
+    for got, want in zip(w, g["weights"]):
+        assert abs(got - want) < 1e-10 * want, (got, want)
+    lo, hi = qd.massive_feasible_window(g["m"], g["order"])
+    assert abs(lo - g["pruning_v0"]["w2_zero"]) < 1e-10
+    assert abs(hi - g["pruning_v0"]["w3_zero"]) < 1e-10
+    wl = qd.massive_group_weights(g["m"], g["order"], lo)
+    assert abs(wl[1]) < 1e-8 and min(wl) > -1e-8
+
+
+def test_massive_third_order_rule():
+    """The 45-vector stencil of the GPU table (Sec. 6.3) at m~ = 5: a non-empty window of
+    non-negative weights; at its middle the rule is exact to degree 2N = 6 (every monomial, odd
+    ones by symmetry) and not to degree 7; integer displacements; antipodal pairs adjacent with
+    the rest vector last."""
+    q = qd.massive_onlattice_2d(5.0, 3)
+    assert q.Q == 45 and q.w.min() > 0 and q.w.sum() == pytest.approx(1.0, abs=1e-13)
+    assert 0.2210 < q.v0 < 0.2212
+    for deg in range(7):
+        assert max_moment_error(q.p, q.w, 5.0, 2, deg) < 1e-11, deg
+    assert max_moment_error(q.p, q.w, 5.0, 2, 7) > 1e-6
+    assert np.all(q.disp == np.round(q.disp)) and np.abs(q.disp).max() == 4
+    assert np.allclose(q.p[0:44:2, 1:], -q.p[1:44:2, 1:]) and np.all(q.disp[44] == 0)
+    assert np.allclose(q.p[:, 0] ** 2 - q.p[:, 1] ** 2 - q.p[:, 2] ** 2, 25.0, rtol=1e-13)
