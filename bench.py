@@ -292,6 +292,32 @@ def onlattice_leg(warmup, steps):
     return out
 
 
+def massive_leg(warmup, steps):
+    """Massive on-lattice rules (Sec. 5.3) at zeta = 5, Taylor-Green start (u0 = 0.1, density noise 1e-3,
+    seed 2), periodic, tau = 0.8, v0 the middle of the admissible window: the 45-vector order-3 stencil on
+    the 512 x 512 lattice of the paper's GPU benchmark (FP64 and float deviations) and on 2048 x 2048
+    (beyond the 256 MB last-level cache), and the 29-vector order-2 stencil on 512 x 512.  Algorithmic
+    bytes per site: 2 Q x element size."""
+    import torch
+    import workloads as W
+    from paper_1909_04502_amd import rlbm as R
+    out = {}
+    for name, order, L, storage in (("n3_512", 3, 512, "f64"), ("n3_512_f32dev", 3, 512, "f32dev"),
+                                    ("n3_2048", 3, 2048, "f64"), ("n2_512", 2, 512, "f64")):
+        n, T, u = W.taylor_green_2d(L, L, 0.1, density_sigma=1e-3, seed=2)
+        lat = R.Lattice(d=2, zeta=5.0, order=order, kind="massive_onlattice", extent=(L, L), tau=0.8,
+                        storage=storage)
+        fa = lat.init(torch.tensor(n), torch.tensor(T), torch.tensor(u))
+        fb = lat.new_state()
+        t = time_steps(lat, fa, fb, warmup, steps)
+        b = 2 * lat.Q * (8 if storage == "f64" else 4) * L * L
+        out[name] = {"Q": lat.Q, "v0": lat.v0, "MLUPS": round(L * L / t / 1e6, 2), "ms_per_step": round(t * 1e3, 5),
+                     "achieved_GBs": round(b / t / 1e9, 1), "frac": round(b / t / 1e9 / HBM_PEAK_GBS, 4)}
+        del lat, fa, fb
+    torch.cuda.empty_cache()
+    return out
+
+
 def forcing_leg(L, warmup, steps):
     """The headline workload with the external force of Sec. 5.4 (scheme B, g = 1e-6 along y) and no-slip
     equilibrium walls on the x faces: the force/wall build of the step kernel."""
@@ -396,6 +422,7 @@ def main():
                                         "f32dev")
     if not args.no_onlattice:
         out["onlattice_ur"] = onlattice_leg(args.warmup, args.steps)
+        out["massive_onlattice"] = massive_leg(args.warmup, args.steps)
     if not args.no_forcing:
         out["forcing_walls"] = forcing_leg(L, args.warmup, args.steps)
     if not args.no_copy:

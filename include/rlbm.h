@@ -37,7 +37,13 @@
  *     (1,1,1) (-1,-1,-1) (1,1,-1) (-1,-1,1) (1,-1,1) (-1,1,-1) (-1,1,1) (1,-1,-1);
  *   for the printed on-lattice massless rule (Sec. 5.3 / App. H.2, order 2)
  *     (3,4) (-3,-4) (-3,4) (3,-4) (4,3) (-4,-3) (-4,3) (4,-3) (5,0) (-5,0) (0,5) (0,-5)
- *   on three shells, zero-weight populations dropped (28 populations).
+ *   on three shells, zero-weight populations dropped (28 populations);
+ *   for the massive on-lattice rules the generating vectors of the groups
+ *     order 2: (1,0) (1,1) (2,1) (2,2) (3,1)
+ *     order 3: (1,0) (1,1) (2,0) (2,1) (2,2) (3,0) (3,2) (3,3) (4,0)
+ *   in this order, each group's members with first non-zero component > 0 in
+ *   decreasing (x, y) order, each followed by its opposite, and the rest
+ *   vector (0,0) last (29 / 45 populations).
  *   Antipodal populations are always adjacent (i, i+1 for even i).
  *
  * State convention
@@ -87,7 +93,13 @@ typedef enum { RLBM_F64 = 0, RLBM_F32_DEV = 1 } rlbm_storage;
 typedef enum { RLBM_PERIODIC = 0, RLBM_OPEN = 1, RLBM_WALL = 2 } rlbm_bc;
 typedef enum {
   RLBM_QUAD_UR_ONLATTICE = 0, /* printed massless (2+1)-d order-2 rule, integer streaming (zeta = 0) */
-  RLBM_QUAD_PRODUCT = 1       /* off-lattice product rule: shells x directions, interpolated streaming */
+  RLBM_QUAD_PRODUCT = 1,      /* off-lattice product rule: shells x directions, interpolated streaming */
+  RLBM_QUAD_MASSIVE_ONLATTICE = 2 /* massive (2+1)-d on-lattice rule (Sec. 5.3): integer vectors n_i in
+                                   * full-symmetric groups, p_i = p^0_i (1, v0 n_i) with p^0_i =
+                                   * zeta / sqrt(1 - v0^2 |n_i|^2), one weight per group solving the
+                                   * moment conditions up to degree 2N; order 2: the 29-vector
+                                   * stencil of the worked example, order 3: the 45-vector stencil of
+                                   * the GPU benchmark (Sec. 6.3); zeta > 0, integer streaming */
 } rlbm_quad_kind;
 
 /* The paper's statement of the problem (Sec. 5.2-5.3): dimension d, reduced
@@ -98,6 +110,9 @@ typedef struct {
   int32_t kind;     /* rlbm_quad_kind */
   int32_t pad_;
   double zeta;      /* reduced mass m c^2/(k_B T0), >= 0 */
+  double v0;        /* RLBM_QUAD_MASSIVE_ONLATTICE: the lattice-speed parameter v0 of the stencil,
+                     * inside the window where every group weight is >= 0; 0 = the middle of that
+                     * window (found by the line search of Sec. 5.3).  Ignored by other kinds. */
 } rlbm_model;
 
 typedef struct {
@@ -122,6 +137,7 @@ typedef struct {
   int64_t state_bytes; /* bytes of one population buffer */
   int32_t elem_bytes;  /* 8 (F64) or 4 (F32_DEV) */
   int32_t on_lattice;  /* 1 if displacements are integers */
+  double v0;           /* RLBM_QUAD_MASSIVE_ONLATTICE: the v0 in use; 0 otherwise */
 } rlbm_info;
 
 typedef struct rlbm_lattice rlbm_lattice;   /* opaque */
@@ -143,6 +159,14 @@ typedef struct {
  * memory of the caller.  No GPU is touched. */
 rlbm_status rlbm_quadrature_build(const rlbm_model *model, int32_t *Q,
                                   double *p, double *w, double *disp);
+
+/* The v0 window of a massive on-lattice model (model->kind ==
+ * RLBM_QUAD_MASSIVE_ONLATTICE, d = 2, order 2 or 3, zeta > 0): the interval
+ * [*lo, *hi] where every group weight is >= 0 (Sec. 5.3 line search: a scan
+ * of min_g w_g(v0) over (0, 1/max|n|), golden-section refinement, bisection
+ * to both ends).  model->v0 is ignored.  RLBM_ERR_QUADRATURE if no v0
+ * qualifies.  Host only; takes tens of milliseconds. */
+rlbm_status rlbm_massive_window(const rlbm_model *model, double *lo, double *hi);
 
 const char *rlbm_status_string(rlbm_status s);
 

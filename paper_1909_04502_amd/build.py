@@ -11,7 +11,8 @@ import subprocess
 import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-SOURCES = ["csrc/api.hip", "csrc/kernels.hip", "csrc/adjoint.hip", "csrc/batch.hip", "csrc/precompute.cpp"]
+SOURCES = ["csrc/api.hip", "csrc/kernels.hip", "csrc/adjoint.hip", "csrc/batch.hip", "csrc/precompute.cpp",
+           "csrc/massive.cpp"]
 LIB = os.path.join(HERE, "librlbm.so")
 
 FLAGS = [

@@ -65,6 +65,7 @@ rlbm_status fail(rlbm_status s, const std::string &msg) {
 
 int stencil_of(const rlbm_model &m) {
   if (m.kind == RLBM_QUAD_UR_ONLATTICE) return rlbm::ST_UR2D;
+  if (m.kind == RLBM_QUAD_MASSIVE_ONLATTICE) return rlbm::ST_MASSIVE2D;
   return m.d == 2 ? rlbm::ST_PROD2D : rlbm::ST_PROD3D;
 }
 
@@ -134,13 +135,24 @@ rlbm_status rlbm_quadrature_build(const rlbm_model *model, int32_t *Q, double *p
   if (!model || !Q) return fail(RLBM_ERR_INVALID_ARG, "null argument");
   rlbm::QuadHost q;
   std::string err;
-  int rc = rlbm::build_quadrature(model->d, model->zeta, model->order, model->kind, q, err);
+  int rc = rlbm::build_quadrature(model->d, model->zeta, model->order, model->kind, model->v0, q, err);
   if (rc) return fail((rlbm_status)rc, err);
   *Q = q.Q;
   if (p) std::memcpy(p, q.p.data(), q.p.size() * sizeof(double));
   if (w) std::memcpy(w, q.w.data(), q.w.size() * sizeof(double));
   if (disp) std::memcpy(disp, q.disp.data(), q.disp.size() * sizeof(double));
   return RLBM_OK;
+}
+
+rlbm_status rlbm_massive_window(const rlbm_model *model, double *lo, double *hi) {
+  if (!model || !lo || !hi) return fail(RLBM_ERR_INVALID_ARG, "null argument");
+  if (model->kind != RLBM_QUAD_MASSIVE_ONLATTICE || model->d != 2)
+    return fail(RLBM_ERR_INVALID_ARG, "the window applies to 2D massive on-lattice rules");
+  if (model->order != 2 && model->order != 3) return fail(RLBM_ERR_UNSUPPORTED, "orders N = 2 and 3");
+  if (!(model->zeta > 0.0) || !std::isfinite(model->zeta)) return fail(RLBM_ERR_INVALID_ARG, "zeta must be > 0");
+  std::string err;
+  int rc = rlbm::massive_window(model->zeta, model->order, *lo, *hi, err);
+  return rc ? fail((rlbm_status)rc, err) : RLBM_OK;
 }
 
 rlbm_status rlbm_create(const rlbm_config *cfg, rlbm_lattice **out) {
@@ -156,7 +168,9 @@ rlbm_status rlbm_create(const rlbm_config *cfg, rlbm_lattice **out) {
       return fail(RLBM_ERR_UNSUPPORTED, "walls are built for product rules");
     if (!std::isfinite(cfg->force[a])) return fail(RLBM_ERR_INVALID_ARG, "force must be finite");
   }
-  if (m.d == 3 && m.kind == RLBM_QUAD_UR_ONLATTICE) return fail(RLBM_ERR_UNSUPPORTED, "on-lattice rule is 2D");
+  if (m.d == 3 && m.kind != RLBM_QUAD_PRODUCT) return fail(RLBM_ERR_UNSUPPORTED, "on-lattice rules are 2D");
+  if (m.kind == RLBM_QUAD_MASSIVE_ONLATTICE && (cfg->force[0] != 0.0 || cfg->force[1] != 0.0))
+    return fail(RLBM_ERR_UNSUPPORTED, "the external force is built for product rules");
   if (cfg->storage != RLBM_F64 && cfg->storage != RLBM_F32_DEV) return fail(RLBM_ERR_INVALID_ARG, "bad storage");
   if (!(cfg->tau > 0.0) || !std::isfinite(cfg->tau)) return fail(RLBM_ERR_INVALID_ARG, "tau must be > 0");
   if (cfg->storage == RLBM_F32_DEV && !(cfg->n_ref > 0.0)) return fail(RLBM_ERR_INVALID_ARG, "n_ref must be > 0");
@@ -177,11 +191,19 @@ rlbm_status rlbm_create(const rlbm_config *cfg, rlbm_lattice **out) {
   else if (m.kind == RLBM_QUAD_PRODUCT && cfg->storage == RLBM_F64) h->variant = 5;
   h->sites = sites;
   std::string err;
-  int rc = rlbm::build_quadrature(m.d, m.zeta, m.order, m.kind, h->quad, err);
+  int rc = rlbm::build_quadrature(m.d, m.zeta, m.order, m.kind, m.v0, h->quad, err);
   if (rc) {
     delete h;
     return fail((rlbm_status)rc, err);
   }
+  // integer streaming reads x - n_i with one periodic wrap: a periodic axis must be at least as
+  // long as the longest displacement along it
+  for (int i = 0; i < h->quad.Q; ++i)
+    for (int a = 0; a < m.d; ++a)
+      if (cfg->bc[a] == RLBM_PERIODIC && std::fabs(h->quad.disp[i * m.d + a]) > (double)cfg->extent[a]) {
+        delete h;
+        return fail(RLBM_ERR_INVALID_ARG, "a periodic extent is shorter than the stencil's longest displacement");
+      }
   rlbm::Tables *t = new rlbm::Tables;
   int bc[3] = {cfg->bc[0], cfg->bc[1], cfg->bc[2]};
   rc = rlbm::build_tables(h->quad, cfg->tau, cfg->storage == RLBM_F32_DEV ? cfg->n_ref : 1.0, cfg->storage,
@@ -233,7 +255,8 @@ rlbm_status rlbm_get_info(const rlbm_lattice *h, rlbm_info *info) {
   info->sites = h->sites;
   info->elem_bytes = h->cfg.storage == RLBM_F64 ? 8 : 4;
   info->state_bytes = (int64_t)info->elem_bytes * h->quad.Q * h->sites;
-  info->on_lattice = h->cfg.model.kind == RLBM_QUAD_UR_ONLATTICE;
+  info->on_lattice = h->cfg.model.kind != RLBM_QUAD_PRODUCT;
+  info->v0 = h->quad.v0;
   return RLBM_OK;
 }
 

@@ -69,8 +69,9 @@ __device__ __forceinline__ S pull(const Tables *__restrict__ tb, const S *__rest
   const S *plane = f + (int64_t)I * sites;
   const int nx = tb->nx, ny = tb->ny;
   if constexpr (ST::ONLAT) {
-    const int sx = wrap_or_clamp(x - ST::dir(I, 0), nx, tb->open[0]);
-    const int sy = wrap_or_clamp(y - ST::dir(I, 1), ny, tb->open[1]);
+    constexpr int dx = ST::dir(I, 0), dy = ST::dir(I, 1);
+    const int sx = dx == 0 ? x : wrap_or_clamp(x - dx, nx, tb->open[0]);
+    const int sy = dy == 0 ? y : wrap_or_clamp(y - dy, ny, tb->open[1]);
     return plane[(int64_t)sy * nx + sx];
   } else {
     constexpr int dx = ST::dir(I, 0), dy = ST::dir(I, 1);
@@ -122,9 +123,23 @@ __device__ __forceinline__ void pull_all(const Tables *__restrict__ tb, const S 
 // the F32_DEV mode) is replaced by f* in place.  Returns the macro state of
 // the pre-collision populations.
 // ---------------------------------------------------------------------------
+// Moments of the shifted monomials (p^0 - m) p^e = p^0 p^e - m p^e, in place
+// (stencils whose projection rows act on the shifted basis).
+template <int D, int N>
+__device__ __forceinline__ void shift_basis_moments(double m, double (&M)[BasisDef<D, N>::NM]) {
+  constexpr ClassTable<D, N> CL{};
+#pragma unroll
+  for (int k = 0; k < BasisDef<D, N>::NM; ++k)
+    if (CL.partner[k] >= 0) M[k] -= m * M[CL.partner[k]];
+}
+
+// Stencils with an odd population count carry a rest population (p = (m, 0))
+// as their last one; it has no partner, feeds only N^0 and T^00, and relaxes
+// with Omega = U^0 / tau towards the even part of the equilibrium.
 template <class ST, int N, typename S, bool DEV, bool RELAX>
 __device__ __forceinline__ Macro<ST::D> collide(const Tables *__restrict__ tb, S (&f)[ST::Q], double tau) {
   constexpr int D = ST::D, Q = ST::Q, NP = Q / 2;
+  constexpr bool REST = (Q & 1) != 0;
   using B = BasisDef<D, N>;
   constexpr int NE = B::NE, NO = B::NO;
   typedef typename Acc<S>::T A;
@@ -149,6 +164,11 @@ __device__ __forceinline__ Macro<ST::D> collide(const Tables *__restrict__ tb, S
       if constexpr (sizeof(A) == 8) mo[k] += (A)tb->mom_o[pr][k] * d;
       else mo[k] += tb->mom_of[pr][k] * d;
     }
+  }
+  if constexpr (REST) {
+    const A mr = (A)tb->m, s = (A)f[Q - 1];
+    me[0] += mr * s;
+    me[1] += mr * mr * s;
   }
   double Nv[D + 1], T[D + 1][D + 1];
   Nv[0] = (double)me[0];
@@ -200,9 +220,14 @@ __device__ __forceinline__ Macro<ST::D> collide(const Tables *__restrict__ tb, S
   // ---- step 5: equilibrium moments (deviation from the reference in F32_DEV) ----
   double Md[B::NM];
   basis_moments<D, N>(mac.n, mac.T, mac.U, rr, Md);
+  if constexpr (DEV) {
+#pragma unroll
+    for (int k = 0; k < B::NM; ++k) Md[k] -= tb->Mref[k];
+  }
+  if constexpr (ST::SHIFT) shift_basis_moments<D, N>(m, Md);
   A M[B::NM];
 #pragma unroll
-  for (int k = 0; k < B::NM; ++k) M[k] = DEV ? (A)(Md[k] - tb->Mref[k]) : (A)Md[k];
+  for (int k = 0; k < B::NM; ++k) M[k] = (A)Md[k];
   // ---- step 8: Omega_i = (U^0 - c_i . U)/tau; f* = f + Omega (f^eq - f) ----
   const double itau = 1.0 / tau;
   const A a0 = (A)(mac.U[0] * itau);
@@ -231,6 +256,16 @@ __device__ __forceinline__ Macro<ST::D> collide(const Tables *__restrict__ tb, S
     const A f0 = (A)f[2 * pr], f1 = (A)f[2 * pr + 1];
     f[2 * pr] = (S)(f0 + om0 * ((E + O) - f0));
     f[2 * pr + 1] = (S)(f1 + om1 * ((E - O) - f1));
+  }
+  if constexpr (REST) {
+    A E = 0;
+#pragma unroll
+    for (int k = 0; k < NE; ++k) {
+      if constexpr (sizeof(A) == 8) E += (A)tb->Rrest[k] * M[k];
+      else E += tb->Rrestf[k] * M[k];
+    }
+    const A fr = (A)f[Q - 1];
+    f[Q - 1] = (S)(fr + a0 * (E - fr));
   }
   return mac;
 }
@@ -423,6 +458,7 @@ __global__ void __launch_bounds__(256) k_init(const Tables *__restrict__ tb, con
   if (!(uu < 1.0) || !(n > 0.0) || !(T > 0.0)) flag_error(err);
   double M[B::NM];
   basis_moments<D, N>(n, T, U, rr, M);
+  if constexpr (ST::SHIFT) shift_basis_moments<D, N>(tb->m, M);
   double fd[Q];
 #pragma unroll
   for (int pr = 0; pr < NP; ++pr) {
@@ -433,6 +469,12 @@ __global__ void __launch_bounds__(256) k_init(const Tables *__restrict__ tb, con
     for (int k = 0; k < B::NO; ++k) O += tb->Ro[pr][k] * M[B::NE + k];
     fd[2 * pr] = E + O;
     fd[2 * pr + 1] = E - O;
+  }
+  if constexpr ((Q & 1) != 0) {
+    double E = 0.0;
+#pragma unroll
+    for (int k = 0; k < B::NE; ++k) E += tb->Rrest[k] * M[k];
+    fd[Q - 1] = E;
   }
   if (noise != nullptr) {
 #pragma unroll
@@ -502,6 +544,10 @@ static hipError_t launch_storage(const LaunchArgs &a) {
 
 hipError_t launch(const LaunchArgs &a) {
   if (a.stencil == ST_UR2D) return launch_storage<Stencil<ST_UR2D, 3>, 2>(a);
+  if (a.stencil == ST_MASSIVE2D) {
+    if (a.order == 2) return launch_storage<Stencil<ST_MASSIVE2D, 2>, 2>(a);
+    return launch_storage<Stencil<ST_MASSIVE2D, 3>, 3>(a);
+  }
   if (a.stencil == ST_PROD2D) {
     if (a.order == 2) return launch_storage<Stencil<ST_PROD2D, 3>, 2>(a);
     return launch_storage<Stencil<ST_PROD2D, 4>, 3>(a);

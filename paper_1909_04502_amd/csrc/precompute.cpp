@@ -4,6 +4,8 @@
 //  * RLBM_QUAD_UR_ONLATTICE: the printed (2+1)-d order-2 rule.  Shells and
 //    weights are the paper's numbers; its stencil vectors have length 5, so a
 //    massless particle crosses 5 sites per step (v0 = 1/5, Sec. 6.1).
+//  * RLBM_QUAD_MASSIVE_ONLATTICE: massive on-lattice rules built in
+//    massive.cpp (weights from the moment conditions, v0 by line search).
 //  * RLBM_QUAD_PRODUCT: off-lattice product rule.  In d = 2 the measure
 //    d^2p/p^0 = dp^0 dphi makes the radial weight e^{-(p^0 - m)}: Gauss-Laguerre
 //    shells times 8 equally weighted directions.  In d = 3, d^3p/p^0 =
@@ -138,7 +140,14 @@ static const double kURShells[3] = {0.4157745567834790, 2.2942803602790417, 6.28
 static const double kURW34[3] = {0.0888866262411466, 0.0348147166961551, 0.0004218743543938};
 static const double kURW50[3] = {0.0, 0.0, 0.0017535654166088};
 
-int build_quadrature(int d, double m, int order, int kind, QuadHost &q, std::string &err) {
+int build_quadrature(int d, double m, int order, int kind, double v0, QuadHost &q, std::string &err) {
+  if (kind == RLBM_QUAD_MASSIVE_ONLATTICE) {
+    if (d != 2) {
+      err = "massive on-lattice rules are provided for d = 2";
+      return RLBM_ERR_UNSUPPORTED;
+    }
+    return build_massive_2d(m, order, v0, q, err);
+  }
   q = QuadHost();
   q.d = d;
   q.m = m;
@@ -302,6 +311,27 @@ static int basis_ne(int d, int order) {
   return order == 2 ? BasisDef<3, 2>::NE : BasisDef<3, 3>::NE;
 }
 
+// Moments of the shifted monomials: M[(p^0 - m) p^e] = M[p^0 p^e] - m M[p^e].
+static void shift_moments(int d, int order, ld m, ld *M) {
+  const int NM = basis_size(d, order);
+  for (int k = 0; k < NM; ++k) {
+    const signed char *idx = basis_idx(d, order, k);
+    int e[3] = {0, 0, 0}, a = 0;
+    for (int s = 0; s < 3; ++s)
+      if (idx[s] == 0) ++a;
+      else if (idx[s] > 0) ++e[idx[s] - 1];
+    if (!a) continue;
+    for (int l = 0; l < NM; ++l) {
+      const signed char *jdx = basis_idx(d, order, l);
+      int f[3] = {0, 0, 0}, b = 0;
+      for (int s = 0; s < 3; ++s)
+        if (jdx[s] == 0) ++b;
+        else if (jdx[s] > 0) ++f[jdx[s] - 1];
+      if (b == 0 && f[0] == e[0] && f[1] == e[1] && f[2] == e[2]) M[k] -= m * M[l];
+    }
+  }
+}
+
 template <int D, int N>
 static void pack_linv(Tables &t) {
   constexpr ClassTable<D, N> CL{};
@@ -408,10 +438,15 @@ int build_tables(const QuadHost &q, double tau, double n_ref, int storage, const
   std::memset(&t, 0, sizeof(Tables));
   const int d = q.d, Q = q.Q, D1 = d + 1;
   const int NM = basis_size(d, q.order), NE = basis_ne(d, q.order), NO = NM - NE;
-  if (Q > kMaxQ || (Q & 1)) {
+  // an odd population count means a rest population (p = (m, 0)) stored last
+  const bool rest = (Q & 1) != 0;
+  if (Q > kMaxQ || (rest && q.kind != RLBM_QUAD_MASSIVE_ONLATTICE)) {
     err = "internal: population count";
     return RLBM_ERR_UNSUPPORTED;
   }
+  // on-lattice massive rules project over the shifted monomials (p^0 - m)^a p^e
+  const bool shifted = q.kind == RLBM_QUAD_MASSIVE_ONLATTICE;
+  const ld mshift = shifted ? (ld)q.m : 0.0L;
   t.nx = (int32_t)extent[0];
   t.ny = (int32_t)extent[1];
   t.nz = (int32_t)(d == 3 ? extent[2] : 1);
@@ -433,7 +468,8 @@ int build_tables(const QuadHost &q, double tau, double n_ref, int storage, const
       const signed char *idx = basis_idx(d, q.order, k);
       ld v = 1.0L;
       for (int s = 0; s < 3; ++s)
-        if (idx[s] >= 0) v *= (ld)q.p[i * D1 + idx[s]];
+        if (idx[s] == 0) v *= (ld)q.p[i * D1] - mshift;
+        else if (idx[s] > 0) v *= (ld)q.p[i * D1 + idx[s]];
       Phi[i * NM + k] = v;
     }
   std::vector<ld> G(NM * NM, 0.0L);
@@ -456,7 +492,8 @@ int build_tables(const QuadHost &q, double tau, double n_ref, int storage, const
       L[i * NM + j] = r / L[j * NM + j];
     }
   }
-  // R[i][k] = w_i (G^{-1} phi(p_i))_k : f^eq_i = sum_k R[i][k] M_k reproduces every basis moment.
+  // R[i][k] = w_i (G^{-1} phi(p_i))_k : f^eq_i = sum_k R[i][k] M_k reproduces every basis moment
+  // (M over the shifted monomials when `shifted`).
   std::vector<ld> R(Q * NM);
   for (int i = 0; i < Q; ++i) {
     std::vector<ld> y(NM);
@@ -483,6 +520,18 @@ int build_tables(const QuadHost &q, double tau, double n_ref, int storage, const
   if (worst > 1e-9L) {
     err = "projection does not reproduce the basis moments";
     return RLBM_ERR_QUADRATURE;
+  }
+  if (rest) {   // the rest population: zero momentum, so its odd row vanishes
+    const int i = Q - 1;
+    for (int a = 1; a < D1; ++a)
+      if (q.p[i * D1 + a] != 0.0) {
+        err = "internal: the last population of an odd stencil must be at rest";
+        return RLBM_ERR_QUADRATURE;
+      }
+    for (int k = 0; k < NE; ++k) {
+      t.Rrest[k] = (double)R[i * NM + k];
+      t.Rrestf[k] = (float)t.Rrest[k];
+    }
   }
   // antipodal structure: R[2pr+1] = +-R[2pr] (even / odd basis part)
   for (int pr = 0; pr < Q / 2; ++pr) {
@@ -637,7 +686,8 @@ int build_tables(const QuadHost &q, double tau, double n_ref, int storage, const
   {
     ld U[4] = {1.0L, 0.0L, 0.0L, 0.0L}, M[kMaxNM];
     basis_moments_ld(d, q.order, (ld)q.m, (ld)n_ref, 1.0L, U, M);
-    for (int k = 0; k < NM; ++k) t.Mref[k] = (double)M[k];
+    for (int k = 0; k < NM; ++k) t.Mref[k] = (double)M[k];   // plain monomials (kernels shift)
+    if (shifted) shift_moments(d, q.order, mshift, M);
     ld Nr[4] = {0, 0, 0, 0}, Tr[4][4] = {{0}};
     for (int i = 0; i < Q; ++i) {
       ld f = 0.0L;

@@ -15,7 +15,7 @@
 
 namespace rlbm {
 
-enum StencilId : int { ST_UR2D = 0, ST_PROD2D = 1, ST_PROD3D = 2 };
+enum StencilId : int { ST_UR2D = 0, ST_PROD2D = 1, ST_PROD3D = 2, ST_MASSIVE2D = 3 };
 
 // ---------------------------------------------------------------------------
 // Direction sets.  Antipodal directions are adjacent (k, k+1 for even k).
@@ -44,29 +44,84 @@ constexpr int kURShell[kUR2DQ] = {0, 0, 0, 0, 0, 0, 0, 0, 1, 1, 1, 1, 1, 1, 1, 1
 constexpr int kURDir[kUR2DQ] = {0, 1, 2, 3, 4, 5, 6, 7, 0, 1, 2, 3, 4, 5, 6, 7,
                                 0, 1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 11};
 
+// Massive on-lattice rules (Sec. 5.3): generating vectors of the full-symmetric
+// groups besides the rest vector.  Order 2: the 29-vector stencil of the
+// worked example; order 3: the 45-vector stencil of the GPU benchmark.
+constexpr int kMassiveGroups2 = 5, kMassiveGroups3 = 9;
+constexpr int kMassiveGen2[kMassiveGroups2][2] = {{1, 0}, {1, 1}, {2, 1}, {2, 2}, {3, 1}};
+constexpr int kMassiveGen3[kMassiveGroups3][2] = {{1, 0}, {1, 1}, {2, 0}, {2, 1}, {2, 2},
+                                                  {3, 0}, {3, 2}, {3, 3}, {4, 0}};
+
+// Non-rest vectors of a massive stencil in population order: per group, the
+// members with first non-zero component > 0 in decreasing (x, y) order, each
+// followed by its opposite.  The rest vector is population Q - 1.
+template <int N>
+struct MassiveDirs {
+  int n = 0;
+  int v[48][2] = {};
+  constexpr MassiveDirs() {
+    const int ng = N == 2 ? kMassiveGroups2 : kMassiveGroups3;
+    for (int g = 0; g < ng; ++g) {
+      const int a = N == 2 ? kMassiveGen2[g][0] : kMassiveGen3[g][0];
+      const int b = N == 2 ? kMassiveGen2[g][1] : kMassiveGen3[g][1];
+      int pos[4][2] = {}, np = 0;
+      if (b == 0) {
+        pos[np][0] = a, pos[np++][1] = 0;
+        pos[np][0] = 0, pos[np++][1] = a;
+      } else if (a == b) {
+        pos[np][0] = a, pos[np++][1] = a;
+        pos[np][0] = a, pos[np++][1] = -a;
+      } else {
+        pos[np][0] = a, pos[np++][1] = b;
+        pos[np][0] = a, pos[np++][1] = -b;
+        pos[np][0] = b, pos[np++][1] = a;
+        pos[np][0] = b, pos[np++][1] = -a;
+      }
+      for (int k = 0; k < np; ++k) {
+        v[n][0] = pos[k][0], v[n][1] = pos[k][1], ++n;
+        v[n][0] = -pos[k][0], v[n][1] = -pos[k][1], ++n;
+      }
+    }
+  }
+};
+constexpr MassiveDirs<2> kMassiveDirs2{};
+constexpr MassiveDirs<3> kMassiveDirs3{};
+
 template <int SID, int KR>
 struct Stencil;
 
 template <int KR>
 struct Stencil<ST_PROD2D, KR> {
   static constexpr int D = 2, NDIR = 8, Q = KR * 8, NSHELL = KR;
-  static constexpr bool ONLAT = false;
+  static constexpr bool ONLAT = false, SHIFT = false;
   RLBM_HD static constexpr int dir(int i, int a) { return kDir2D[i % 8][a]; }
 };
 
 template <int KR>
 struct Stencil<ST_PROD3D, KR> {
   static constexpr int D = 3, NDIR = 26, Q = KR * 26, NSHELL = KR;
-  static constexpr bool ONLAT = false;
+  static constexpr bool ONLAT = false, SHIFT = false;
   RLBM_HD static constexpr int dir(int i, int a) { return kDir3D[i % 26][a]; }
 };
 
 template <>
 struct Stencil<ST_UR2D, 3> {
   static constexpr int D = 2, NDIR = 12, Q = kUR2DQ, NSHELL = 3;
-  static constexpr bool ONLAT = true;
+  static constexpr bool ONLAT = true, SHIFT = false;
   // integer displacement of population i (sites per step)
   RLBM_HD static constexpr int dir(int i, int a) { return kDirUR[kURDir[i]][a]; }
+};
+
+// Massive on-lattice rule of order N: Q = 29 (N = 2) or 45 (N = 3), the rest
+// population last.  SHIFT: its projection rows act on the moments of the
+// shifted monomials (p^0 - m)^a p^e (better conditioned for large m).
+template <int N>
+struct Stencil<ST_MASSIVE2D, N> {
+  static constexpr int D = 2, Q = (N == 2 ? kMassiveDirs2.n : kMassiveDirs3.n) + 1, NDIR = Q, NSHELL = 0;
+  static constexpr bool ONLAT = true, SHIFT = true;
+  RLBM_HD static constexpr int dir(int i, int a) {
+    return i >= Q - 1 ? 0 : (N == 2 ? kMassiveDirs2.v[i][a] : kMassiveDirs3.v[i][a]);
+  }
 };
 
 // Number of interpolation taps of population i: 2^(number of non-zero direction components).
@@ -166,6 +221,8 @@ struct Tables {
   double mom_o[kMaxPairs][6];   // odd moment weights: p^a, p0 p^a
   double Re[kMaxPairs][kMaxNE]; // projection rows, even basis part
   double Ro[kMaxPairs][kMaxNO]; // projection rows, odd basis part
+  double Rrest[kMaxNE];         // projection row of a rest population (p = (m, 0)), even part
+  float Rrestf[kMaxNE];
   float Ref[kMaxPairs][kMaxNE]; // float copies for the F32_DEV path
   float Rof[kMaxPairs][kMaxNO];
   float cf[kMaxPairs][3];

@@ -17,13 +17,14 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "librlbm.so")
 
 OK, ERR_INVALID_ARG, ERR_UNSUPPORTED, ERR_QUADRATURE, ERR_DEVICE, ERR_NONPHYSICAL = range(6)
-KIND = {"ur_onlattice": 0, "product": 1}
+KIND = {"ur_onlattice": 0, "product": 1, "massive_onlattice": 2}
 STORAGE = {"f64": 0, "f32dev": 1}
 BC = {"periodic": 0, "open": 1, "wall": 2}
 
 
 class Model(Structure):
-    _fields_ = [("d", c_int32), ("order", c_int32), ("kind", c_int32), ("pad_", c_int32), ("zeta", c_double)]
+    _fields_ = [("d", c_int32), ("order", c_int32), ("kind", c_int32), ("pad_", c_int32), ("zeta", c_double),
+                ("v0", c_double)]
 
 
 class Config(Structure):
@@ -33,7 +34,7 @@ class Config(Structure):
 
 class Info(Structure):
     _fields_ = [("Q", c_int32), ("n_basis", c_int32), ("sites", c_int64), ("state_bytes", c_int64),
-                ("elem_bytes", c_int32), ("on_lattice", c_int32)]
+                ("elem_bytes", c_int32), ("on_lattice", c_int32), ("v0", c_double)]
 
 
 class Fields(Structure):
@@ -78,6 +79,8 @@ def lib():
     L.rlbm_last_error.argtypes = []
     L.rlbm_quadrature_build.restype = st
     L.rlbm_quadrature_build.argtypes = [POINTER(Model), POINTER(c_int32), c_void_p, c_void_p, c_void_p]
+    L.rlbm_massive_window.restype = st
+    L.rlbm_massive_window.argtypes = [POINTER(Model), POINTER(c_double), POINTER(c_double)]
     L.rlbm_create.restype = st
     L.rlbm_create.argtypes = [POINTER(Config), POINTER(c_void_p)]
     L.rlbm_destroy.restype = st
@@ -143,14 +146,16 @@ def _check(status):
         raise RLBMError(status, L.rlbm_last_error().decode() or L.rlbm_status_string(status).decode())
 
 
-def _model(d, zeta, order, kind):
-    return Model(d=d, order=order, kind=KIND[kind] if isinstance(kind, str) else int(kind), pad_=0, zeta=float(zeta))
+def _model(d, zeta, order, kind, v0=0.0):
+    return Model(d=d, order=order, kind=KIND[kind] if isinstance(kind, str) else int(kind), pad_=0, zeta=float(zeta),
+                 v0=float(v0))
 
 
-def quadrature_build(d: int, zeta: float, order: int, kind="product"):
-    """Host-side quadrature of the library: (p [Q, d+1], w [Q], disp [Q, d]) as float64 CPU tensors."""
+def quadrature_build(d: int, zeta: float, order: int, kind="product", v0=0.0):
+    """Host-side quadrature of the library: (p [Q, d+1], w [Q], disp [Q, d]) as float64 CPU tensors.
+    v0: massive on-lattice rules only (0 = the middle of the window of non-negative weights)."""
     L = lib()
-    m = _model(d, zeta, order, kind)
+    m = _model(d, zeta, order, kind, v0)
     Q = c_int32(0)
     _check(L.rlbm_quadrature_build(ctypes.byref(m), ctypes.byref(Q), None, None, None))
     p = torch.empty((Q.value, d + 1), dtype=torch.float64)
@@ -158,6 +163,15 @@ def quadrature_build(d: int, zeta: float, order: int, kind="product"):
     disp = torch.empty((Q.value, d), dtype=torch.float64)
     _check(L.rlbm_quadrature_build(ctypes.byref(m), ctypes.byref(Q), p.data_ptr(), w.data_ptr(), disp.data_ptr()))
     return p, w, disp
+
+
+def massive_window(zeta: float, order: int):
+    """(lo, hi): the v0 interval of non-negative weights of the 2D massive on-lattice rule (Sec. 5.3)."""
+    L = lib()
+    m = _model(2, zeta, order, "massive_onlattice")
+    lo, hi = c_double(0.0), c_double(0.0)
+    _check(L.rlbm_massive_window(ctypes.byref(m), ctypes.byref(lo), ctypes.byref(hi)))
+    return lo.value, hi.value
 
 
 def _stream():
@@ -172,7 +186,7 @@ class Lattice:
     """One lattice: handle of the C ABI plus the torch-side shapes."""
 
     def __init__(self, d=2, zeta=1.0, order=3, kind="product", extent=(64, 64), bc=None, storage="f64",
-                 tau=0.8, tau_field=None, n_ref=1.0, force=None, _handle=None):
+                 tau=0.8, tau_field=None, n_ref=1.0, force=None, v0=0.0, _handle=None):
         L = lib()
         self._owned = _handle is None
         self.d = d
@@ -187,7 +201,7 @@ class Lattice:
             assert tuple(tau_field.shape) == self.grid_shape
         self.tau_field = tau_field          # kept alive: the handle stores its pointer
         cfg = Config()
-        cfg.model = _model(d, zeta, order, kind)
+        cfg.model = _model(d, zeta, order, kind, v0)
         ext = list(self.extent) + [1] * (3 - d)
         for a in range(3):
             cfg.extent[a] = ext[a]
@@ -212,6 +226,7 @@ class Lattice:
         self.n_basis = info.n_basis
         self.sites = info.sites
         self.on_lattice = bool(info.on_lattice)
+        self.v0 = info.v0
 
     def __del__(self):
         h = getattr(self, "h", None)

@@ -110,3 +110,69 @@ def test_tables_build_over_the_zeta_range(rlbm_lib, d, order, zetas):
         h = ctypes.c_void_p()
         st = rlbm_lib.rlbm_create(ctypes.byref(c), ctypes.byref(h))
         assert st == R.ERR_DEVICE, (z, st, rlbm_lib.rlbm_last_error())
+
+
+@pytest.fixture(scope="module")
+def massive_rules():
+    return {order: qd.massive_onlattice_2d(5.0, order) for order in (2, 3)}
+
+
+@pytest.mark.parametrize("order", [2, 3])
+def test_library_massive_rule_matches_oracle(rlbm_lib, massive_rules, order):
+    """The binary128 solver of the library against the oracle's mpmath solver (Sec. 5.3): the v0
+    window, the rule at the oracle's v0 and the default (v0 = 0 -> middle of the window)."""
+    from paper_1909_04502_amd import rlbm as R
+    q = massive_rules[order]
+    lo, hi = R.massive_window(5.0, order)
+    qlo, qhi = qd.massive_feasible_window(5.0, order)
+    assert abs(lo - qlo) < 1e-15 and abs(hi - qhi) < 1e-15
+    for v0 in (q.v0, 0.0):
+        p, w, disp = R.quadrature_build(2, 5.0, order, "massive_onlattice", v0=v0)
+        assert p.shape[0] == q.Q == (29 if order == 2 else 45)
+        assert np.abs(p.numpy() - q.p).max() < 1e-14 * np.abs(q.p).max()
+        assert np.abs(w.numpy() - q.w).max() < 1e-12 * q.w.max()
+        assert np.all(disp.numpy() == q.disp)
+
+
+def test_library_massive_rule_printed_example(rlbm_lib):
+    """The worked example of Sec. 5.3 (m~ = 5, v0 = 0.2726): the printed group weights."""
+    import json
+    from paper_1909_04502_amd import rlbm as R
+    g = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "massive_2d_m5_order2.json")))
+    p, w, disp = R.quadrature_build(2, g["m"], g["order"], "massive_onlattice", v0=g["v0"])
+    w = w.numpy()
+    per_group = [w[-1]] + [w[k] for k in (0, 4, 8, 16, 20)]       # rest, then each group's first member
+    for got, want in zip(per_group, g["weights"]):
+        assert abs(got - want) < 1e-10 * want
+
+
+def test_library_massive_rule_rejections(rlbm_lib):
+    from paper_1909_04502_amd import rlbm as R
+    for args, kw in [((2, 0.0, 3, "massive_onlattice"), {}),            # massless
+                     ((2, 5.0, 4, "massive_onlattice"), {}),            # order
+                     ((3, 5.0, 3, "massive_onlattice"), {}),            # d
+                     ((2, 5.0, 2, "massive_onlattice"), {"v0": 0.26}),  # outside the window
+                     ((2, 5.0, 2, "massive_onlattice"), {"v0": 0.4})]:  # beyond 1/max|n|
+        with pytest.raises(R.RLBMError) as e:
+            R.quadrature_build(*args, **kw)
+        assert e.value.status in (R.ERR_INVALID_ARG, R.ERR_UNSUPPORTED, R.ERR_QUADRATURE)
+
+
+def test_create_validates_massive_lattices(rlbm_lib):
+    """Checks that run before any device call: a periodic extent shorter than the longest integer
+    displacement (the pull would wrap more than once) and a force on a massive on-lattice rule."""
+    from paper_1909_04502_amd import rlbm as R
+    cfg = R.Config()
+    cfg.model = R.Model(d=2, order=3, kind=R.KIND["massive_onlattice"], pad_=0, zeta=5.0, v0=0.0)
+    cfg.extent[0], cfg.extent[1], cfg.extent[2] = 3, 8, 1   # |n_x| reaches 4
+    cfg.tau = 0.8
+    h = ctypes.c_void_p()
+    assert rlbm_lib.rlbm_create(ctypes.byref(cfg), ctypes.byref(h)) == R.ERR_INVALID_ARG
+    cfg.extent[0] = 8
+    cfg.force[0] = 1e-5
+    assert rlbm_lib.rlbm_create(ctypes.byref(cfg), ctypes.byref(h)) == R.ERR_UNSUPPORTED
+    ur = R.Config()
+    ur.model = R.Model(d=2, order=2, kind=R.KIND["ur_onlattice"], pad_=0, zeta=0.0)
+    ur.extent[0], ur.extent[1], ur.extent[2] = 16, 4, 1     # |n_y| reaches 5
+    ur.tau = 0.8
+    assert rlbm_lib.rlbm_create(ctypes.byref(ur), ctypes.byref(h)) == R.ERR_INVALID_ARG
