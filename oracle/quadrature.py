@@ -34,7 +34,7 @@ Rules:
   (+-1,+-1,+-1)_FS with group weights fixed by exactness at degrees 0, 4, 6.
   Displacements: delta_i = v_i n_i / |n_i| with v_i = |p_i| / p_i^0 and
   c dt = dx (one lattice site per step at the speed of light).
-* ``massive_onlattice_2d``: on-lattice rules for massive particles (Sec. 5.3,
+* ``massive_onlattice`` (``massive_onlattice_2d``): on-lattice rules for massive particles (Sec. 5.3,
   Eqs. discrete-momentum-vectors, discrete-p0 and quadrature-problem):
   p_i = p_i^0 (1, v0 n_i), p_i^0 = m / sqrt(1 - v0^2 |n_i|^2), n_i integer, one
   weight per full-symmetric group of the stencil.  The weights solve the
@@ -43,12 +43,17 @@ Rules:
   <= 2N (a in {0, 1}; e even, up to exchange of components); a line search
   in v0 finds the window where all weights are non-negative.  Stencils: the
   second-order example of Sec. 5.3 (29 vectors) and the third-order 45-vector
-  stencil of the GPU table of Sec. 6.3.  Population order: the groups as
-  listed, each group's vectors with first non-zero component positive in
-  decreasing (x, y) order, each followed by its opposite; the rest vector last.
+  stencil and the (3+1)-d 143-vector stencil of the GPU table of Sec. 6.3.
+  The right-hand side b is evaluated in closed form at mpmath precision
+  (Bessel K in d = 3): the system's condition number (up to ~1e13) would
+  amplify a double-rounded b into the weights.  Population order: the groups
+  as listed, each group's vectors with first non-zero component positive in
+  decreasing lexicographic order, each followed by its opposite; the rest
+  vector last.
 """
 from __future__ import annotations
 
+import functools
 import itertools
 import math
 from dataclasses import dataclass
@@ -74,11 +79,15 @@ DIRS_3D = [(1, 0, 0), (-1, 0, 0), (0, 1, 0), (0, -1, 0), (0, 0, 1), (0, 0, -1),
            (1, -1, 1), (-1, 1, -1), (-1, 1, 1), (1, -1, -1)]
 
 
-# Massive on-lattice stencils: full-symmetric groups, the rest vector first (as listed in Sec. 5.3)
-MASSIVE2D_GROUPS = {
-    2: [(0, 0), (1, 0), (1, 1), (2, 1), (2, 2), (3, 1)],
-    3: [(0, 0), (1, 0), (1, 1), (2, 0), (2, 1), (2, 2), (3, 0), (3, 2), (3, 3), (4, 0)],
+# Massive on-lattice stencils: full-symmetric groups, the rest vector first (as listed in Sec. 5.3
+# and in the stencils of the GPU benchmark, Sec. 6.3), keyed by (d, order)
+MASSIVE_GROUPS = {
+    (2, 2): [(0, 0), (1, 0), (1, 1), (2, 1), (2, 2), (3, 1)],
+    (2, 3): [(0, 0), (1, 0), (1, 1), (2, 0), (2, 1), (2, 2), (3, 0), (3, 2), (3, 3), (4, 0)],
+    (3, 3): [(0, 0, 0), (1, 0, 0), (1, 1, 1), (2, 0, 0), (2, 1, 1), (2, 2, 0), (2, 2, 1), (2, 2, 2),
+             (3, 0, 0), (3, 1, 1), (3, 2, 0)],
 }
+MASSIVE2D_GROUPS = {order: MASSIVE_GROUPS[(2, order)] for order in (2, 3)}
 
 
 @dataclass
@@ -249,63 +258,122 @@ def fs_group(gen):
     return out
 
 
-def _invariants(order: int):
-    """(a, ex, ey): the monomials (p^0)^a px^ex py^ey, e even with ex >= ey, of degree <= 2N (2D)."""
+def _invariants(order: int, d: int = 2):
+    """(a, e_1, .., e_d): the monomials (p^0)^a p^e with every e_k even and e_1 >= e_2 >= ..,
+    of degree a + |e| <= 2N; for a rule symmetric under permutations and reflections of the axes
+    these are the independent moment conditions."""
     rows = []
     for a in (0, 1):
         for deg in range(0, 2 * order + 1 - a, 2):
-            for ex in range(deg, -1, -1):
-                ey = deg - ex
-                if ex % 2 == 0 and ey % 2 == 0 and ex >= ey:
-                    rows.append((a, ex, ey))
+            parts = {tuple(sorted(q, reverse=True)) for q in itertools.product(range(0, deg + 1, 2), repeat=d)
+                     if sum(q) == deg}
+            for e in sorted(parts, reverse=True):
+                rows.append((a,) + e)
     return rows
 
 
-def massive_group_weights(m: float, order: int, v0: float, dps: int = 40):
-    """Weights per group (the rest vector first) solving A(v0) w = b (Sec. 5.3), in mpmath at dps digits."""
+def _dfact(n: int) -> int:
+    r = 1
+    while n > 1:
+        r *= n
+        n -= 2
+    return r
+
+
+def rest_frame_moment_mp(a: int, e, m, d: int):
+    """The moment of (p^0)^a p^e (e even) of omega = C exp(-p^0) (T0 = 1, normalised to 1) in closed
+    form at mpmath precision.  The angular average of n^e over the unit sphere is
+    prod (e_k - 1)!! / (|e| + d - 2)!!.  Radial part, k = |e|/2:
+      d = 2 (d^2p/p^0 = dp^0 dphi, x = p^0 - m): int_0^inf e^{-x} (m + x)^a (x^2 + 2 m x)^k dx, a
+            polynomial in m after binomial expansion;
+      d = 3 (d^3p/p^0 = |p| dp^0 dOmega): I_k = int_m^inf e^{-p0} |p|^(2k+1) dp0
+            = (2k+1)!!/2^(k+1) (2m)^(k+1) K_{k+1}(m), the a = 1 integral is I_{k+1}/(2k+3)
+            (integration by parts), and the normalisation is I_0 = m K_1(m)."""
+    m = mpmath.mpf(m)
+    k = sum(e) // 2
+    ang = mpmath.mpf(1)
+    for c in e:
+        ang *= _dfact(c - 1)
+    ang /= _dfact(sum(e) + d - 2)
+    if d == 2:
+        rad = mpmath.mpf(0)
+        for j in range(k + 1):
+            c = mpmath.binomial(k, j) * (2 * m) ** (k - j)
+            rad += c * (mpmath.factorial(k + j) if a == 0 else m * mpmath.factorial(k + j) + mpmath.factorial(k + j + 1))
+        return ang * rad
+    if d != 3:
+        raise ValueError("d = 2 or 3")
+
+    def I(kk):
+        return mpmath.mpf(_dfact(2 * kk + 1)) / 2 ** (kk + 1) * (2 * m) ** (kk + 1) * mpmath.besselk(kk + 1, m)
+    rad = I(k) if a == 0 else I(k + 1) / (2 * k + 3)
+    return ang * rad / I(0)
+
+
+def massive_group_weights(m: float, order: int, v0: float, dps: int = 40, d: int = 2):
+    """Weights per group (the rest vector first) solving A(v0) w = b (Sec. 5.3), in mpmath at dps
+    digits; b holds the exact rest-frame moments (the system is ill conditioned, so b is not rounded
+    to double first)."""
     mpmath.mp.dps = dps
-    groups = [fs_group(g) for g in MASSIVE2D_GROUPS[order]]
-    rows = _invariants(order)
-    if len(rows) != len(groups):
-        raise ValueError("the stencil must have as many groups as invariants")
+    rows, norms, sums = _group_sums(d, order)
     v = mpmath.mpf(v0)
     M = mpmath.mpf(m)
-    A = mpmath.matrix(len(rows), len(groups))
-    for g, members in enumerate(groups):
-        for n in members:
-            p0 = M / mpmath.sqrt(1 - v * v * (n[0] ** 2 + n[1] ** 2))
-            px, py = p0 * v * n[0], p0 * v * n[1]
-            for r, (a, ex, ey) in enumerate(rows):
-                A[r, g] += p0 ** a * px ** ex * py ** ey
-    b = mpmath.matrix([rest_frame_moment((0,) * a + (1,) * ex + (2,) * ey, m, 2) for (a, ex, ey) in rows])
+    A = mpmath.matrix(len(rows), len(norms))
+    # every member n of group g has p^0_g = m / sqrt(1 - v0^2 |n|^2) and p = p^0_g v0 n, so
+    # sum_{n in g} (p^0)^a p^e = (p^0_g)^a (p^0_g v0)^|e| sum_{n in g} n^e
+    for g, nn in enumerate(norms):
+        p0 = M / mpmath.sqrt(1 - v * v * nn)
+        for r, row in enumerate(rows):
+            A[r, g] = p0 ** row[0] * (p0 * v) ** sum(row[1:]) * sums[r][g]
+    b = mpmath.matrix(_rest_moments(float(m), d, order, dps))
     return [float(x) for x in mpmath.lu_solve(A, b)]
 
 
-def massive_feasible_window(m: float, order: int, scan: int = 600):
+@functools.lru_cache(maxsize=None)
+def _rest_moments(m: float, d: int, order: int, dps: int):
+    """The right-hand side b of the weight system (independent of v0), at dps digits."""
+    mpmath.mp.dps = dps
+    return [rest_frame_moment_mp(row[0], row[1:], m, d) for row in _invariants(order, d)]
+
+
+@functools.lru_cache(maxsize=None)
+def _group_sums(d: int, order: int):
+    """Invariant rows, |n|^2 per group, and the integer sums sum_{n in g} n^e per (row, group)."""
+    groups = [fs_group(g) for g in MASSIVE_GROUPS[(d, order)]]
+    rows = _invariants(order, d)
+    if len(rows) != len(groups):
+        raise ValueError("the stencil must have as many groups as invariants")
+    norms = [sum(c * c for c in mem[0]) for mem in groups]
+    sums = [[sum(math.prod(c ** ex for c, ex in zip(n, row[1:])) for n in mem) for mem in groups] for row in rows]
+    return rows, norms, sums
+
+
+def massive_feasible_window(m: float, order: int, scan: int = 600, d: int = 2):
     """The v0 interval where every group weight is >= 0 (line search of Sec. 5.3): a scan of
-    min_g w_g(v0) over (0, 1/max|n|), then bisection on both sides of the best point."""
-    nmax = max(math.hypot(*g) for g in MASSIVE2D_GROUPS[order])
+    min_g w_g(v0) over (0, 1/max|n|), golden-section refinement of its maximum, then bisection on
+    both sides of the best point."""
+    nmax = max(math.sqrt(sum(c * c for c in g)) for g in MASSIVE_GROUPS[(d, order)])
     grid = np.linspace(1e-3, 1.0 / nmax - 1e-4, scan)
 
     def minw(v):
-        return min(massive_group_weights(m, order, v, dps=30))
+        return min(massive_group_weights(m, order, v, dps=30, d=d))
     vals = [minw(v) for v in grid]
     k = int(np.argmax(vals))
     lo, hi = grid[max(k - 1, 0)], grid[min(k + 1, scan - 1)]
     # golden-section search for the maximum of min_g w_g on [lo, hi]
     gr = (math.sqrt(5) - 1) / 2
     a, b = lo, hi
-    c, d = b - gr * (b - a), a + gr * (b - a)
-    fc, fd = minw(c), minw(d)
+    c1, c2 = b - gr * (b - a), a + gr * (b - a)
+    f1, f2 = minw(c1), minw(c2)
     for _ in range(60):
-        if fc > fd:
-            b, d, fd = d, c, fc
-            c = b - gr * (b - a)
-            fc = minw(c)
+        if f1 > f2:
+            b, c2, f2 = c2, c1, f1
+            c1 = b - gr * (b - a)
+            f1 = minw(c1)
         else:
-            a, c, fc = c, d, fd
-            d = a + gr * (b - a)
-            fd = minw(d)
+            a, c1, f1 = c1, c2, f2
+            c2 = a + gr * (b - a)
+            f2 = minw(c2)
     vbest = (a + b) / 2
     if minw(vbest) < 0:
         raise ValueError("no v0 gives non-negative weights for this stencil and mass")
@@ -321,23 +389,30 @@ def massive_feasible_window(m: float, order: int, scan: int = 600):
     return edge(vbest, lo), edge(vbest, hi)
 
 
-def massive_onlattice_2d(m: float, order: int, v0: float = None) -> Quadrature:
-    """On-lattice massive (2+1)-d rule (Sec. 5.3); v0 defaults to the middle of the feasible window."""
+def massive_onlattice(d: int, m: float, order: int, v0: float = None) -> Quadrature:
+    """On-lattice massive (d+1)-dimensional rule (Sec. 5.3); v0 defaults to the middle of the
+    feasible window."""
+    window = None
     if v0 is None:
-        lo, hi = massive_feasible_window(m, order)
-        v0 = 0.5 * (lo + hi)
-    wg = massive_group_weights(m, order, v0)
+        window = massive_feasible_window(m, order, d=d)
+        v0 = 0.5 * (window[0] + window[1])
+    wg = massive_group_weights(m, order, v0, d=d)
     p, w, disp = [], [], []
     rest = None
-    for gen, wgt in zip(MASSIVE2D_GROUPS[order], wg):
+    for gen, wgt in zip(MASSIVE_GROUPS[(d, order)], wg):
         for n in fs_group(gen):
-            p0 = m / math.sqrt(1.0 - v0 * v0 * (n[0] ** 2 + n[1] ** 2))
-            row = ((p0, p0 * v0 * n[0], p0 * v0 * n[1]), wgt, (float(n[0]), float(n[1])))
-            if n == (0, 0):
+            p0 = m / math.sqrt(1.0 - v0 * v0 * sum(c * c for c in n))
+            row = ((p0,) + tuple(p0 * v0 * c for c in n), wgt, tuple(float(c) for c in n))
+            if not any(n):
                 rest = row
             else:
                 p.append(row[0]), w.append(row[1]), disp.append(row[2])
     p.append(rest[0]), w.append(rest[1]), disp.append(rest[2])
-    q = Quadrature(2, float(m), order, np.array(p), np.array(w), np.array(disp), True)
+    q = Quadrature(d, float(m), order, np.array(p), np.array(w), np.array(disp), True)
     q.v0 = float(v0)
+    q.window = window
     return q
+
+
+def massive_onlattice_2d(m: float, order: int, v0: float = None) -> Quadrature:
+    return massive_onlattice(2, m, order, v0)

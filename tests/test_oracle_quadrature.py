@@ -245,3 +245,68 @@ def test_massive_third_order_rule():
     assert np.all(q.disp == np.round(q.disp)) and np.abs(q.disp).max() == 4
     assert np.allclose(q.p[0:44:2, 1:], -q.p[1:44:2, 1:]) and np.all(q.disp[44] == 0)
     assert np.allclose(q.p[:, 0] ** 2 - q.p[:, 1] ** 2 - q.p[:, 2] ** 2, 25.0, rtol=1e-13)
+
+
+@pytest.mark.parametrize("d", [2, 3])
+def test_rest_frame_moment_closed_form(d):
+    """The closed forms behind the massive weight systems against two other routes: the App. B
+    moments (float64, through the A_n ratios), and, split into its factors, brute force: the angular
+    average of n^e from the product rule's direction set (exact for angular degree <= 7) or, in 2D,
+    an equispaced angle sum; the radial integral by numerical quadrature."""
+    import mpmath
+    m = 5.0
+    mpmath.mp.dps = 30
+    for a, e in [(0, (0,) * d), (1, (0,) * d), (0, (2,) + (0,) * (d - 1)), (1, (2, 2) + (0,) * (d - 2)),
+                 (0, (4, 2) + (0,) * (d - 2)), (0, (2,) * d), (0, (6,) + (0,) * (d - 1))]:
+        idx = (0,) * a + sum(((k + 1,) * c for k, c in enumerate(e)), ())
+        got = qd.rest_frame_moment_mp(a, e, m, d)
+        assert abs(float(got) / qd.rest_frame_moment(idx, m, d) - 1) < 1e-13, (a, e)
+    # factors of the closed form, d = 3
+    if d == 3:
+        q = qd.product_3d(1.0, 3)
+        dirs = q.p[:26, 1:] / np.linalg.norm(q.p[:26, 1:], axis=1)[:, None]
+        wdir = q.w[:26] / q.w[:26].sum()
+        for e in [(2, 0, 0), (4, 0, 0), (2, 2, 0), (6, 0, 0), (4, 2, 0), (2, 2, 2)]:
+            ang = np.sum(wdir * np.prod(dirs ** np.array(e), axis=1))
+            want = qd._dfact(e[0] - 1) * qd._dfact(e[1] - 1) * qd._dfact(e[2] - 1) / qd._dfact(sum(e) + 1)
+            assert abs(ang - want) < 1e-14
+        M = mpmath.mpf(m)
+        norm = mpmath.quad(lambda p0: mpmath.e ** (-p0) * mpmath.sqrt(p0 * p0 - M * M), [M, M + 10, mpmath.inf])
+        for a, k in [(0, 1), (1, 0), (1, 2), (0, 3)]:
+            num = mpmath.quad(lambda p0: mpmath.e ** (-p0) * p0 ** a * (p0 * p0 - M * M) ** (k + mpmath.mpf(1) / 2),
+                              [M, M + 10, mpmath.inf]) / norm
+            e = (2 * k, 0, 0)
+            ang = mpmath.mpf(qd._dfact(2 * k - 1)) / qd._dfact(2 * k + 1)
+            assert abs(qd.rest_frame_moment_mp(a, e, m, 3) / ang / num - 1) < 1e-25
+    else:
+        M = mpmath.mpf(m)
+        for a, ex, ey in [(0, 2, 2), (1, 4, 0), (0, 4, 2)]:
+            ang = mpmath.fsum(mpmath.cos(2 * mpmath.pi * j / 64) ** ex * mpmath.sin(2 * mpmath.pi * j / 64) ** ey
+                              for j in range(64)) / 64
+            k = (ex + ey) // 2
+            rad = mpmath.quad(lambda p0: mpmath.e ** (M - p0) * p0 ** a * (p0 * p0 - M * M) ** k, [M, M + 10, mpmath.inf])
+            assert abs(qd.rest_frame_moment_mp(a, (ex, ey), m, 2) / (ang * rad) - 1) < 1e-25
+
+
+@pytest.fixture(scope="module")
+def massive3d():
+    return qd.massive_onlattice(3, 5.0, 3)
+
+
+def test_massive_3d_rule(massive3d):
+    """The 143-vector (3+1)-d stencil of the GPU table (Sec. 6.3) at m~ = 5: a window of non-negative
+    weights exists; at its middle the rule is exact to degree 2N = 6 for every monomial and not at
+    degree 7; integer displacements up to 3; antipodal pairs adjacent, the rest vector last."""
+    q = massive3d
+    assert q.Q == 143 and q.w.min() > 0 and q.w.sum() == pytest.approx(1.0, abs=1e-13)
+    lo, hi = q.window
+    assert lo < q.v0 < hi and 0.2715 < q.v0 < 0.2720
+    for deg in range(7):
+        assert max_moment_error(q.p, q.w, 5.0, 3, deg) < 1e-11, deg
+    assert max_moment_error(q.p, q.w, 5.0, 3, 7) > 1e-6
+    assert np.all(q.disp == np.round(q.disp)) and np.abs(q.disp).max() == 3
+    assert np.allclose(q.p[0:142:2, 1:], -q.p[1:142:2, 1:]) and np.all(q.disp[142] == 0)
+    assert np.allclose(q.p[:, 0] ** 2 - (q.p[:, 1:] ** 2).sum(1), 25.0, rtol=1e-13)
+    # at the window's ends one weight vanishes
+    for v in (lo, hi):
+        assert abs(min(qd.massive_group_weights(5.0, 3, v, d=3))) < 1e-9
