@@ -296,24 +296,33 @@ def massive_leg(warmup, steps):
     """Massive on-lattice rules (Sec. 5.3) at zeta = 5, Taylor-Green start (u0 = 0.1, density noise 1e-3,
     seed 2), periodic, tau = 0.8, v0 the middle of the admissible window: the 45-vector order-3 stencil on
     the 512 x 512 lattice of the paper's GPU benchmark (FP64 and float deviations) and on 2048 x 2048
-    (beyond the 256 MB last-level cache), and the 29-vector order-2 stencil on 512 x 512.  Algorithmic
-    bytes per site: 2 Q x element size."""
+    (beyond the 256 MB last-level cache), the 29-vector order-2 stencil on 512 x 512, and the (3+1)-d
+    143-vector stencil on the 192^3 lattice of the paper's 3D benchmark (3D Taylor-Green start; a tenth
+    of the steps).  Algorithmic bytes per site: 2 Q x element size."""
     import torch
     import workloads as W
     from paper_1909_04502_amd import rlbm as R
     out = {}
-    for name, order, L, storage in (("n3_512", 3, 512, "f64"), ("n3_512_f32dev", 3, 512, "f32dev"),
-                                    ("n3_2048", 3, 2048, "f64"), ("n2_512", 2, 512, "f64")):
-        n, T, u = W.taylor_green_2d(L, L, 0.1, density_sigma=1e-3, seed=2)
-        lat = R.Lattice(d=2, zeta=5.0, order=order, kind="massive_onlattice", extent=(L, L), tau=0.8,
+    for name, d, order, L, storage in (("n3_512", 2, 3, 512, "f64"), ("n3_512_f32dev", 2, 3, 512, "f32dev"),
+                                       ("n3_2048", 2, 3, 2048, "f64"), ("n2_512", 2, 2, 512, "f64"),
+                                       ("d3_192", 3, 3, 192, "f64"), ("d3_192_f32dev", 3, 3, 192, "f32dev")):
+        if d == 2:
+            n, T, u = W.taylor_green_2d(L, L, 0.1, density_sigma=1e-3, seed=2)
+        else:
+            n, T, u = W.taylor_green_3d(L, L, L, 0.1, density_sigma=1e-3, seed=2)
+        ext = (L,) * d
+        lat = R.Lattice(d=d, zeta=5.0, order=order, kind="massive_onlattice", extent=ext, tau=0.8,
                         storage=storage)
         fa = lat.init(torch.tensor(n), torch.tensor(T), torch.tensor(u))
         fb = lat.new_state()
-        t = time_steps(lat, fa, fb, warmup, steps)
-        b = 2 * lat.Q * (8 if storage == "f64" else 4) * L * L
-        out[name] = {"Q": lat.Q, "v0": lat.v0, "MLUPS": round(L * L / t / 1e6, 2), "ms_per_step": round(t * 1e3, 5),
+        k = steps if d == 2 else max(2, steps // 10)
+        t = time_steps(lat, fa, fb, warmup if d == 2 else 2, k)
+        sites = L ** d
+        b = 2 * lat.Q * (8 if storage == "f64" else 4) * sites
+        out[name] = {"Q": lat.Q, "v0": lat.v0, "MLUPS": round(sites / t / 1e6, 2), "ms_per_step": round(t * 1e3, 5),
                      "achieved_GBs": round(b / t / 1e9, 1), "frac": round(b / t / 1e9 / HBM_PEAK_GBS, 4)}
         del lat, fa, fb
+        torch.cuda.empty_cache()
     torch.cuda.empty_cache()
     return out
 

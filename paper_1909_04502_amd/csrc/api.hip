@@ -65,7 +65,7 @@ rlbm_status fail(rlbm_status s, const std::string &msg) {
 
 int stencil_of(const rlbm_model &m) {
   if (m.kind == RLBM_QUAD_UR_ONLATTICE) return rlbm::ST_UR2D;
-  if (m.kind == RLBM_QUAD_MASSIVE_ONLATTICE) return rlbm::ST_MASSIVE2D;
+  if (m.kind == RLBM_QUAD_MASSIVE_ONLATTICE) return m.d == 2 ? rlbm::ST_MASSIVE2D : rlbm::ST_MASSIVE3D;
   return m.d == 2 ? rlbm::ST_PROD2D : rlbm::ST_PROD3D;
 }
 
@@ -146,12 +146,13 @@ rlbm_status rlbm_quadrature_build(const rlbm_model *model, int32_t *Q, double *p
 
 rlbm_status rlbm_massive_window(const rlbm_model *model, double *lo, double *hi) {
   if (!model || !lo || !hi) return fail(RLBM_ERR_INVALID_ARG, "null argument");
-  if (model->kind != RLBM_QUAD_MASSIVE_ONLATTICE || model->d != 2)
-    return fail(RLBM_ERR_INVALID_ARG, "the window applies to 2D massive on-lattice rules");
-  if (model->order != 2 && model->order != 3) return fail(RLBM_ERR_UNSUPPORTED, "orders N = 2 and 3");
+  if (model->kind != RLBM_QUAD_MASSIVE_ONLATTICE)
+    return fail(RLBM_ERR_INVALID_ARG, "the window applies to massive on-lattice rules");
+  if (!((model->d == 2 && (model->order == 2 || model->order == 3)) || (model->d == 3 && model->order == 3)))
+    return fail(RLBM_ERR_UNSUPPORTED, "massive rules: d = 2 with N = 2, 3; d = 3 with N = 3");
   if (!(model->zeta > 0.0) || !std::isfinite(model->zeta)) return fail(RLBM_ERR_INVALID_ARG, "zeta must be > 0");
   std::string err;
-  int rc = rlbm::massive_window(model->zeta, model->order, *lo, *hi, err);
+  int rc = rlbm::massive_window(model->d, model->zeta, model->order, *lo, *hi, err);
   return rc ? fail((rlbm_status)rc, err) : RLBM_OK;
 }
 
@@ -168,8 +169,8 @@ rlbm_status rlbm_create(const rlbm_config *cfg, rlbm_lattice **out) {
       return fail(RLBM_ERR_UNSUPPORTED, "walls are built for product rules");
     if (!std::isfinite(cfg->force[a])) return fail(RLBM_ERR_INVALID_ARG, "force must be finite");
   }
-  if (m.d == 3 && m.kind != RLBM_QUAD_PRODUCT) return fail(RLBM_ERR_UNSUPPORTED, "on-lattice rules are 2D");
-  if (m.kind == RLBM_QUAD_MASSIVE_ONLATTICE && (cfg->force[0] != 0.0 || cfg->force[1] != 0.0))
+  if (m.d == 3 && m.kind == RLBM_QUAD_UR_ONLATTICE) return fail(RLBM_ERR_UNSUPPORTED, "the printed massless rule is 2D");
+  if (m.kind == RLBM_QUAD_MASSIVE_ONLATTICE && (cfg->force[0] != 0.0 || cfg->force[1] != 0.0 || cfg->force[2] != 0.0))
     return fail(RLBM_ERR_UNSUPPORTED, "the external force is built for product rules");
   if (cfg->storage != RLBM_F64 && cfg->storage != RLBM_F32_DEV) return fail(RLBM_ERR_INVALID_ARG, "bad storage");
   if (!(cfg->tau > 0.0) || !std::isfinite(cfg->tau)) return fail(RLBM_ERR_INVALID_ARG, "tau must be > 0");

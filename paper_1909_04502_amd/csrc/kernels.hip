@@ -24,6 +24,7 @@
 
 #include "device_math.h"
 #include "kernels.h"
+#include "massive_math.h"
 #include "prod_math.h"
 
 namespace rlbm {
@@ -308,13 +309,45 @@ __device__ __forceinline__ Offs make_offs(const Tables *__restrict__ tb, int x, 
   return o;
 }
 
+// Integer streaming: population I at the site comes from x - n_I.  The byte
+// offsets of the upstream rows are computed once per axis and distance (up to
+// ST::RMAX sites), so each population costs one add and one load.
+template <class ST>
+RLBM_HD constexpr int dir_z(int i) {
+  if constexpr (ST::D == 3) return ST::dir(i, 2);
+  else return 0;
+}
+
+template <class ST, typename S, int R, int... I>
+__device__ __forceinline__ void gather_onlat_impl(const S *__restrict__ fin, int64_t sites, const uint32_t (&ox)[2 * R + 1],
+                                                  const uint32_t (&oy)[2 * R + 1], const uint32_t (&oz)[2 * R + 1],
+                                                  S (&f)[ST::Q], std::integer_sequence<int, I...>) {
+  ((f[I] = *(const S *)((const char *)(fin + (int64_t)I * sites) + ox[R - ST::dir(I, 0)] + oy[R - ST::dir(I, 1)] +
+                        oz[R - dir_z<ST>(I)])),
+   ...);
+}
+
+template <class ST, typename S>
+__device__ __forceinline__ void gather_onlat(const Tables *__restrict__ tb, const S *__restrict__ fin, int64_t sites,
+                                             int x, int y, int z, S (&f)[ST::Q]) {
+  constexpr int R = ST::RMAX;
+  uint32_t ox[2 * R + 1], oy[2 * R + 1], oz[2 * R + 1];
+  const uint32_t nx = tb->nx, nxy = (uint32_t)tb->nx * tb->ny;
+#pragma unroll
+  for (int k = 0; k <= 2 * R; ++k) {
+    ox[k] = (uint32_t)wrap_or_clamp(x + k - R, tb->nx, tb->open[0]) * (uint32_t)sizeof(S);
+    oy[k] = (uint32_t)wrap_or_clamp(y + k - R, tb->ny, tb->open[1]) * nx * (uint32_t)sizeof(S);
+    oz[k] = ST::D == 3 ? (uint32_t)wrap_or_clamp(z + k - R, tb->nz, tb->open[2]) * nxy * (uint32_t)sizeof(S) : 0u;
+  }
+  gather_onlat_impl<ST, S, R>(fin, sites, ox, oy, oz, f, std::make_integer_sequence<int, ST::Q>{});
+}
+
 // pre-collision populations at the site
 template <class ST, typename S>
 __device__ __forceinline__ void gather(const Tables *__restrict__ tb, const S *__restrict__ fin, int64_t sites, int x,
                                        int y, int z, S (&f)[ST::Q]) {
   if constexpr (ST::ONLAT) {
-    const Nbr nb = make_nbr<ST>(tb, x, y, z);
-    pull_all<ST, S>(tb, fin, sites, nb, x, y, z, f);
+    gather_onlat<ST, S>(tb, fin, sites, x, y, z, f);
   } else {
     const Offs o = make_offs<ST, S>(tb, x, y, z);
     pull_prod<ST, S>(tb, fin, sites, o, f);
@@ -324,7 +357,9 @@ __device__ __forceinline__ void gather(const Tables *__restrict__ tb, const S *_
 template <class ST, int N, typename S, bool DEV, bool RELAX, bool EXT = false>
 __device__ __forceinline__ Macro<ST::D> collide_site(const Tables *__restrict__ tb, S (&f)[ST::Q], double tau,
                                                      bool wall = false) {
-  if constexpr (ST::ONLAT)
+  if constexpr (ST::ONLAT && ST::SHIFT)
+    return collide_massive<ST, N, S, DEV, RELAX>(tb, f, tau);
+  else if constexpr (ST::ONLAT)
     return collide<ST, N, S, DEV, RELAX>(tb, f, tau);
   else
     return collide_prod<ST, N, S, DEV, RELAX, EXT>(tb, f, tau, wall);
@@ -548,6 +583,7 @@ hipError_t launch(const LaunchArgs &a) {
     if (a.order == 2) return launch_storage<Stencil<ST_MASSIVE2D, 2>, 2>(a);
     return launch_storage<Stencil<ST_MASSIVE2D, 3>, 3>(a);
   }
+  if (a.stencil == ST_MASSIVE3D) return launch_storage<Stencil<ST_MASSIVE3D, 3>, 3>(a);
   if (a.stencil == ST_PROD2D) {
     if (a.order == 2) return launch_storage<Stencil<ST_PROD2D, 3>, 2>(a);
     return launch_storage<Stencil<ST_PROD2D, 4>, 3>(a);

@@ -1,4 +1,4 @@
-// massive.cpp -- massive on-lattice (2+1)-d quadratures (Sec. 5.3).
+// massive.cpp -- massive on-lattice (2+1)-d and (3+1)-d quadratures (Sec. 5.3).
 //
 // The stencil is a union of full-symmetric groups of integer vectors n; every
 // member of a group carries the same weight, and the momenta lie on the mass
@@ -17,10 +17,19 @@
 // 45-vector stencil), so it is assembled and solved in binary128
 // (__float128, ~34 digits); the weights then carry full double precision.
 //
-// Rest-frame moments in d = 2: with d^2p/p^0 = dp^0 dphi and C = e^m / (2 pi),
-//   b(a, ex, ey) = [(ex-1)!! (ey-1)!! / (ex+ey)!!] * int_0^inf e^{-x} (m+x)^a (x^2 + 2 m x)^k dx,
-// k = (ex+ey)/2 (x = p^0 - m); expanding (x^2 + 2 m x)^k binomially leaves
-// integrals int_0^inf x^q e^{-x} dx = q!, so b is a polynomial in m.
+// Rest-frame moments, k = |e|/2, with the angular average of n^e over the unit
+// sphere prod (e_a - 1)!! / (|e| + d - 2)!!:
+//  d = 2 (d^2p/p^0 = dp^0 dphi, C = e^m / (2 pi)): the radial integral
+//    int_0^inf e^{-x} (m+x)^a (x^2 + 2 m x)^k dx (x = p^0 - m); expanding
+//    (x^2 + 2 m x)^k binomially leaves int_0^inf x^q e^{-x} dx = q!, so b is a
+//    polynomial in m;
+//  d = 3 (d^3p/p^0 = |p| dp^0 dOmega): I_k = int_m^inf e^{-p0} |p|^(2k+1) dp0
+//    = (2k+1)!!/2^(k+1) (2m)^(k+1) K_{k+1}(m); the a = 1 integral is
+//    I_{k+1}/(2k+3) (by parts) and the normalisation I_0 = m K_1(m).  K_0 and
+//    K_1 come from K_nu(z) = int_0^inf exp(-z cosh t) cosh(nu t) dt by the
+//    trapezoidal rule (spectrally accurate for this analytic, even integrand),
+//    higher orders from K_{nu+1} = K_{nu-1} + (2 nu / z) K_nu.
+#include <algorithm>
 #include <cmath>
 #include <string>
 #include <vector>
@@ -53,85 +62,148 @@ static qf qdfact(int n) {   // n!! with (-1)!! = 1
 
 static qf qbinom(int n, int k) { return qfact(n) / (qfact(k) * qfact(n - k)); }
 
-// Rest-frame moment of p0^a px^ex py^ey (ex, ey even) for omega = C exp(-p0), normalised to 1.
-static qf rest_moment_2d(qf m, int a, int ex, int ey) {
-  const int k = (ex + ey) / 2;
-  qf rad = 0;
-  for (int j = 0; j <= k; ++j) {
-    qf c = qbinom(k, j);
-    for (int t = 0; t < k - j; ++t) c *= 2 * m;
-    // x^(k+j) (m + x)^a
-    rad += c * (a == 0 ? qfact(k + j) : m * qfact(k + j) + qfact(k + j + 1));
+// e^x in binary128: x = k ln2 + r, |r| <= ln2/2, Taylor series for e^r.
+static qf qexp(qf x) {
+  const qf ln2 = 0.6931471805599453094172321214581765680755Q;
+  const double kd = std::nearbyint((double)(x / ln2));
+  const qf r = x - (qf)kd * ln2;
+  qf term = 1, sum = 1;
+  for (int j = 1; j < 40; ++j) {
+    term *= r / j;
+    sum += term;
   }
-  return qdfact(ex - 1) * qdfact(ey - 1) / qdfact(ex + ey) * rad;
+  qf scale = 1, base = kd >= 0 ? (qf)2 : (qf)0.5Q;
+  for (long k = (long)std::fabs(kd); k > 0; k >>= 1) {
+    if (k & 1) scale *= base;
+    base *= base;
+  }
+  return sum * scale;
 }
 
-// Members of the group generated by (g0, g1), g0 >= g1 >= 0, in the library's
-// population order: those with first non-zero component > 0 in decreasing
-// (x, y) order, each followed by its opposite.
-static void group_members(int g0, int g1, std::vector<int> &out) {
-  int pos[4][2], np = 0;
-  if (g0 == 0 && g1 == 0) {
-    out.insert(out.end(), {0, 0});
-    return;
+// K_0(z) and K_1(z) for z > 0 (trapezoidal rule with step 1/32 until the terms vanish).
+static void qbessel_k01(qf z, qf &k0, qf &k1) {
+  const qf h = 0.03125Q;
+  k0 = 0.5Q * qexp(-z);
+  k1 = k0;
+  for (int j = 1; j < 100000; ++j) {
+    const qf t = h * j, et = qexp(t), ch = 0.5Q * (et + 1 / et);
+    const qf f = qexp(-z * ch);
+    k0 += f;
+    k1 += f * ch;
+    if (f < 1e-45Q * k0) break;
   }
-  if (g1 == 0) {
-    pos[np][0] = g0, pos[np++][1] = 0;
-    pos[np][0] = 0, pos[np++][1] = g0;
-  } else if (g0 == g1) {
-    pos[np][0] = g0, pos[np++][1] = g0;
-    pos[np][0] = g0, pos[np++][1] = -g0;
+  k0 *= h;
+  k1 *= h;
+}
+
+// Rest-frame moment of p0^a p^e (e even) for omega = C exp(-p0), normalised to 1.
+static qf rest_moment(int d, qf m, int a, const int *e) {
+  int k = 0;
+  qf ang = 1;
+  for (int c = 0; c < d; ++c) {
+    k += e[c];
+    ang *= qdfact(e[c] - 1);
+  }
+  ang /= qdfact(k + d - 2);
+  k /= 2;
+  if (d == 2) {
+    qf rad = 0;
+    for (int j = 0; j <= k; ++j) {
+      qf c = qbinom(k, j);
+      for (int t = 0; t < k - j; ++t) c *= 2 * m;
+      // x^(k+j) (m + x)^a
+      rad += c * (a == 0 ? qfact(k + j) : m * qfact(k + j) + qfact(k + j + 1));
+    }
+    return ang * rad;
+  }
+  qf K[8];
+  qbessel_k01(m, K[0], K[1]);
+  for (int nu = 1; nu < 7; ++nu) K[nu + 1] = K[nu - 1] + (2 * nu) / m * K[nu];
+  auto I = [&](int kk) {
+    qf r = qdfact(2 * kk + 1) * K[kk + 1];
+    for (int t = 0; t <= kk; ++t) r *= m;   // (2m)^(k+1) / 2^(k+1)
+    return r;
+  };
+  const qf rad = a == 0 ? I(k) : I(k + 1) / (2 * k + 3);
+  return ang * rad / I(0);
+}
+
+// The stencil of (d, order): members of each non-rest group in population order
+// (shared with the kernels), their |n|^2, and the largest |n|.
+struct MassiveSpec {
+  int d = 0, ng = 0, n = 0;
+  const int (*v)[3] = nullptr;
+  const int *first = nullptr, *count = nullptr;
+};
+
+static bool massive_spec(int d, int order, MassiveSpec &sp) {
+  sp.d = d;
+  if (d == 2 && order == 2) {
+    sp.ng = kMassiveDirs22.NG, sp.n = kMassiveDirs22.n, sp.v = kMassiveDirs22.v;
+    sp.first = kMassiveDirs22.first, sp.count = kMassiveDirs22.count;
+  } else if (d == 2 && order == 3) {
+    sp.ng = kMassiveDirs23.NG, sp.n = kMassiveDirs23.n, sp.v = kMassiveDirs23.v;
+    sp.first = kMassiveDirs23.first, sp.count = kMassiveDirs23.count;
+  } else if (d == 3 && order == 3) {
+    sp.ng = kMassiveDirs33.NG, sp.n = kMassiveDirs33.n, sp.v = kMassiveDirs33.v;
+    sp.first = kMassiveDirs33.first, sp.count = kMassiveDirs33.count;
   } else {
-    pos[np][0] = g0, pos[np++][1] = g1;
-    pos[np][0] = g0, pos[np++][1] = -g1;
-    pos[np][0] = g1, pos[np++][1] = g0;
-    pos[np][0] = g1, pos[np++][1] = -g0;
+    return false;
   }
-  for (int k = 0; k < np; ++k) out.insert(out.end(), {pos[k][0], pos[k][1], -pos[k][0], -pos[k][1]});
+  return true;
 }
 
-static int massive_groups(int order, const int (*&gen)[2]) {
-  if (order == 2) {
-    gen = kMassiveGen2;
-    return kMassiveGroups2;
-  }
-  gen = kMassiveGen3;
-  return kMassiveGroups3;
+static int norm2(const MassiveSpec &sp, int i) {
+  int r = 0;
+  for (int a = 0; a < sp.d; ++a) r += sp.v[i][a] * sp.v[i][a];
+  return r;
 }
 
-// Group weights (the rest group first, then the generators in order) at v0.
+// Group weights (the rest group first, then the stencil's groups in order) at
+// v0.  Every member n of group g has p^0_g = m / sqrt(1 - v0^2 |n|^2) and
+// p = p^0_g v0 n, so its row entries are (p^0_g)^a (p^0_g v0)^|e| sum_n n^e.
 // Returns false if the system is singular.
-static bool massive_weights(qf m, int order, qf v0, std::vector<qf> &w) {
-  const int(*gen)[2];
-  const int ng = massive_groups(order, gen) + 1;
-  // invariant monomials (a, ex, ey): even ex >= ey, degree a + ex + ey <= 2N
+static bool massive_weights(int d, qf m, int order, qf v0, std::vector<qf> &w) {
+  MassiveSpec sp;
+  if (!massive_spec(d, order, sp)) return false;
+  const int ng = sp.ng + 1;
+  // invariant monomials (a, e): every e_c even, e_1 >= e_2 >= ..., degree a + |e| <= 2N
   std::vector<int> inv;
   for (int a = 0; a <= 1; ++a)
     for (int deg = 0; deg <= 2 * order - a; deg += 2)
-      for (int ex = deg; ex >= 0; --ex) {
-        const int ey = deg - ex;
-        if (ex % 2 == 0 && ey % 2 == 0 && ex >= ey) inv.insert(inv.end(), {a, ex, ey});
-      }
-  const int nr = (int)inv.size() / 3;
+      for (int e0 = deg; e0 >= 0; e0 -= 2)
+        for (int e1 = std::min(e0, deg - e0); e1 >= 0; e1 -= 2) {
+          const int e2 = deg - e0 - e1;
+          if (d == 2 && e2 != 0) continue;
+          if (e2 > e1) continue;
+          inv.insert(inv.end(), {a, e0, e1, e2});
+        }
+  const int nr = (int)inv.size() / 4;
   if (nr != ng) return false;
   std::vector<qf> A(nr * (ng + 1), 0);   // augmented [A | b]
   for (int g = 0; g < ng; ++g) {
-    std::vector<int> mem;
-    if (g == 0) group_members(0, 0, mem);
-    else group_members(gen[g - 1][0], gen[g - 1][1], mem);
-    for (size_t k = 0; k < mem.size(); k += 2) {
-      const qf nx = mem[k], ny = mem[k + 1];
-      const qf p0 = m / qsqrt(1 - v0 * v0 * (nx * nx + ny * ny));
-      const qf px = p0 * v0 * nx, py = p0 * v0 * ny;
-      for (int r = 0; r < nr; ++r) {
-        qf v = inv[3 * r] ? p0 : (qf)1;
-        for (int e = 0; e < inv[3 * r + 1]; ++e) v *= px;
-        for (int e = 0; e < inv[3 * r + 2]; ++e) v *= py;
-        A[r * (ng + 1) + g] += v;
+    qf p0 = m, sc = 0;
+    int first = 0, cnt = 1;
+    if (g > 0) {
+      first = sp.first[g - 1], cnt = sp.count[g - 1];
+      p0 = m / qsqrt(1 - v0 * v0 * (qf)norm2(sp, first));
+      sc = p0 * v0;
+    }
+    for (int r = 0; r < nr; ++r) {
+      const int *e = &inv[4 * r + 1];
+      long s = 0;   // sum over the group of n^e (integers)
+      for (int i = first; i < first + cnt; ++i) {
+        long t = 1;
+        for (int a = 0; a < d; ++a)
+          for (int c = 0; c < e[a]; ++c) t *= (g > 0 ? sp.v[i][a] : 0);
+        s += t;
       }
+      qf v = inv[4 * r] ? p0 : (qf)1;
+      for (int c = 0; c < e[0] + e[1] + e[2]; ++c) v *= sc;
+      A[r * (ng + 1) + g] = v * (qf)s;
     }
   }
-  for (int r = 0; r < nr; ++r) A[r * (ng + 1) + ng] = rest_moment_2d(m, inv[3 * r], inv[3 * r + 1], inv[3 * r + 2]);
+  for (int r = 0; r < nr; ++r) A[r * (ng + 1) + ng] = rest_moment(d, m, inv[4 * r], &inv[4 * r + 1]);
   // Gaussian elimination with partial pivoting
   const int W = ng + 1;
   for (int c = 0; c < ng; ++c) {
@@ -157,60 +229,60 @@ static bool massive_weights(qf m, int order, qf v0, std::vector<qf> &w) {
   return true;
 }
 
-static double min_weight(double m, int order, double v0) {
+static double min_weight(int d, double m, int order, double v0) {
   std::vector<qf> w;
-  if (!massive_weights((qf)m, order, (qf)v0, w)) return -1.0;
+  if (!massive_weights(d, (qf)m, order, (qf)v0, w)) return -1.0;
   qf lo = w[0];
   for (qf x : w) lo = x < lo ? x : lo;
   return (double)lo;
 }
 
-static double max_norm(int order) {
-  const int(*gen)[2];
-  const int ng = massive_groups(order, gen);
-  double r = 0.0;
-  for (int g = 0; g < ng; ++g) r = std::fmax(r, std::hypot((double)gen[g][0], (double)gen[g][1]));
-  return r;
+static double max_norm(int d, int order) {
+  MassiveSpec sp;
+  if (!massive_spec(d, order, sp)) return 1.0;
+  int r = 0;
+  for (int i = 0; i < sp.n; ++i) r = std::max(r, norm2(sp, i));
+  return std::sqrt((double)r);
 }
 
 // The v0 window of non-negative weights: the largest min_g w_g over a scan of
 // (0, 1/max|n|), refined by golden-section search, then bisection towards
 // both ends.
-int massive_window(double m, int order, double &lo, double &hi, std::string &err) {
+int massive_window(int d, double m, int order, double &lo, double &hi, std::string &err) {
   const int scan = 600;
-  const double a0 = 1e-3, a1 = 1.0 / max_norm(order) - 1e-4;
+  const double a0 = 1e-3, a1 = 1.0 / max_norm(d, order) - 1e-4;
   int best = 0;
   double bestv = -1e300;
   for (int k = 0; k < scan; ++k) {
     const double v = a0 + (a1 - a0) * k / (scan - 1);
-    const double mw = min_weight(m, order, v);
+    const double mw = min_weight(d, m, order, v);
     if (mw > bestv) bestv = mw, best = k;
   }
   const double glo = a0 + (a1 - a0) * (best > 0 ? best - 1 : 0) / (scan - 1);
   const double ghi = a0 + (a1 - a0) * (best < scan - 1 ? best + 1 : scan - 1) / (scan - 1);
   const double gr = (std::sqrt(5.0) - 1.0) / 2.0;
-  double a = glo, b = ghi, c = b - gr * (b - a), d = a + gr * (b - a);
-  double fc = min_weight(m, order, c), fd = min_weight(m, order, d);
+  double a = glo, b = ghi, c1 = b - gr * (b - a), c2 = a + gr * (b - a);
+  double f1 = min_weight(d, m, order, c1), f2 = min_weight(d, m, order, c2);
   for (int it = 0; it < 60; ++it) {
-    if (fc > fd) {
-      b = d, d = c, fd = fc;
-      c = b - gr * (b - a);
-      fc = min_weight(m, order, c);
+    if (f1 > f2) {
+      b = c2, c2 = c1, f2 = f1;
+      c1 = b - gr * (b - a);
+      f1 = min_weight(d, m, order, c1);
     } else {
-      a = c, c = d, fc = fd;
-      d = a + gr * (b - a);
-      fd = min_weight(m, order, d);
+      a = c1, c1 = c2, f1 = f2;
+      c2 = a + gr * (b - a);
+      f2 = min_weight(d, m, order, c2);
     }
   }
   const double vbest = 0.5 * (a + b);
-  if (min_weight(m, order, vbest) < 0.0) {
+  if (min_weight(d, m, order, vbest) < 0.0) {
     err = "no v0 gives non-negative weights for this stencil and mass";
     return RLBM_ERR_QUADRATURE;
   }
   auto edge = [&](double inside, double outside) {
     for (int it = 0; it < 80; ++it) {
       const double mid = 0.5 * (inside + outside);
-      if (min_weight(m, order, mid) >= 0.0) inside = mid;
+      if (min_weight(d, m, order, mid) >= 0.0) inside = mid;
       else outside = mid;
     }
     return inside;
@@ -220,27 +292,28 @@ int massive_window(double m, int order, double &lo, double &hi, std::string &err
   return 0;
 }
 
-int build_massive_2d(double m, int order, double v0, QuadHost &q, std::string &err) {
+int build_massive(int d, double m, int order, double v0, QuadHost &q, std::string &err) {
   if (!(m > 0.0) || !std::isfinite(m)) {
     err = "massive on-lattice rules need zeta > 0";
     return RLBM_ERR_INVALID_ARG;
   }
-  if (order != 2 && order != 3) {
-    err = "massive on-lattice rules are provided for orders N = 2 and 3";
+  MassiveSpec sp;
+  if (!massive_spec(d, order, sp)) {
+    err = "massive on-lattice rules are provided for d = 2 (N = 2, 3) and d = 3 (N = 3)";
     return RLBM_ERR_UNSUPPORTED;
   }
   if (v0 == 0.0) {
     double lo, hi;
-    int rc = massive_window(m, order, lo, hi, err);
+    int rc = massive_window(d, m, order, lo, hi, err);
     if (rc) return rc;
     v0 = 0.5 * (lo + hi);
   }
-  if (!(v0 > 0.0) || !(v0 * max_norm(order) < 1.0)) {
+  if (!(v0 > 0.0) || !(v0 * max_norm(d, order) < 1.0)) {
     err = "v0 must lie in (0, 1/max|n|)";
     return RLBM_ERR_INVALID_ARG;
   }
   std::vector<qf> wg;
-  if (!massive_weights((qf)m, order, (qf)v0, wg)) {
+  if (!massive_weights(d, (qf)m, order, (qf)v0, wg)) {
     err = "singular moment system for the massive stencil";
     return RLBM_ERR_QUADRATURE;
   }
@@ -249,27 +322,27 @@ int build_massive_2d(double m, int order, double v0, QuadHost &q, std::string &e
       err = "v0 lies outside the window of non-negative weights";
       return RLBM_ERR_QUADRATURE;
     }
-  const int(*gen)[2];
-  const int ng = massive_groups(order, gen);
   q = QuadHost();
-  q.d = 2;
+  q.d = d;
   q.m = m;
   q.order = order;
   q.kind = RLBM_QUAD_MASSIVE_ONLATTICE;
   q.v0 = v0;
   q.nshell = 0;
-  auto push = [&](int nx, int ny, qf wgt) {
-    const qf p0 = (qf)m / qsqrt(1 - (qf)v0 * (qf)v0 * (qf)(nx * nx + ny * ny));
-    q.p.insert(q.p.end(), {(double)p0, (double)(p0 * (qf)v0 * nx), (double)(p0 * (qf)v0 * ny)});
+  auto push = [&](const int *n, qf wgt) {
+    const qf n2 = (qf)(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
+    const qf p0 = (qf)m / qsqrt(1 - (qf)v0 * (qf)v0 * n2);
+    q.p.push_back((double)p0);
+    for (int a = 0; a < d; ++a) q.p.push_back((double)(p0 * (qf)v0 * n[a]));
     q.w.push_back((double)wgt);
-    q.disp.insert(q.disp.end(), {(double)nx, (double)ny});
+    for (int a = 0; a < d; ++a) q.disp.push_back((double)n[a]);
   };
-  for (int g = 0; g < ng; ++g) {
-    std::vector<int> mem;
-    group_members(gen[g][0], gen[g][1], mem);
-    for (size_t k = 0; k < mem.size(); k += 2) push(mem[k], mem[k + 1], wg[g + 1]);
+  for (int g = 0; g < sp.ng; ++g) {
+    q.gfirst.push_back(sp.first[g]);
+    for (int i = sp.first[g]; i < sp.first[g] + sp.count[g]; ++i) push(sp.v[i], wg[g + 1]);
   }
-  push(0, 0, wg[0]);
+  const int zero[3] = {0, 0, 0};
+  push(zero, wg[0]);
   q.Q = (int)q.w.size();
   q.ndir = q.Q;
   return 0;

@@ -141,13 +141,7 @@ static const double kURW34[3] = {0.0888866262411466, 0.0348147166961551, 0.00042
 static const double kURW50[3] = {0.0, 0.0, 0.0017535654166088};
 
 int build_quadrature(int d, double m, int order, int kind, double v0, QuadHost &q, std::string &err) {
-  if (kind == RLBM_QUAD_MASSIVE_ONLATTICE) {
-    if (d != 2) {
-      err = "massive on-lattice rules are provided for d = 2";
-      return RLBM_ERR_UNSUPPORTED;
-    }
-    return build_massive_2d(m, order, v0, q, err);
-  }
+  if (kind == RLBM_QUAD_MASSIVE_ONLATTICE) return build_massive(d, m, order, v0, q, err);
   q = QuadHost();
   q.d = d;
   q.m = m;
@@ -603,12 +597,12 @@ int build_tables(const QuadHost &q, double tau, double n_ref, int storage, const
       }
     }
   }
-  // Product rules evaluate the equilibrium as f^eq_i = w_i psi(p_i)^T G'^{-1} M'
-  // over the shifted monomials psi = (p^0 - m)^a p^e (M' the matching
-  // moments).  With the kinetic energy p^0 - m instead of p^0 the Gram matrix
-  // stays well conditioned for large m (1 and p^0 are nearly collinear over
-  // the shells when m >> 1).
-  if (q.kind == RLBM_QUAD_PRODUCT) {
+  // Product and massive on-lattice rules evaluate the equilibrium as
+  // f^eq_i = w_i psi(p_i)^T G'^{-1} M' over the shifted monomials
+  // psi = (p^0 - m)^a p^e (M' the matching moments).  With the kinetic energy
+  // p^0 - m instead of p^0 the Gram matrix stays well conditioned for large m
+  // (1 and p^0 are nearly collinear over the shells when m >> 1).
+  if (q.kind != RLBM_QUAD_UR_ONLATTICE) {
     std::vector<ld> Ps(Q * NM);
     for (int i = 0; i < Q; ++i)
       for (int k = 0; k < NM; ++k) {
@@ -655,6 +649,32 @@ int build_tables(const QuadHost &q, double tau, double n_ref, int storage, const
       if (q.order == 2) pack_linv<3, 2>(t);
       else pack_linv<3, 3>(t);
     }
+  }
+  if (q.kind == RLBM_QUAD_MASSIVE_ONLATTICE) {
+    // group factors: p = (p0, v n) with v = v0 p0 for every member n of a group
+    if ((int)q.gfirst.size() > kMaxMassiveGroups) {
+      err = "internal: too many groups";
+      return RLBM_ERR_UNSUPPORTED;
+    }
+    for (size_t g = 0; g < q.gfirst.size(); ++g) {
+      const int i = q.gfirst[g];
+      const ld p0 = (ld)q.p[i * D1], v = (ld)q.v0 * p0, w = (ld)q.w[i], dl = p0 - (ld)q.m;
+      ld f[13] = {p0, p0 * p0, v, p0 * v, v * v};
+      ld vl = 1.0L;
+      for (int l = 0; l < 4; ++l) {
+        f[5 + l] = w * vl;
+        f[9 + l] = w * dl * vl;
+        vl *= v;
+      }
+      for (int k = 0; k < 13; ++k) {
+        t.mgrp[g][k] = (double)f[k];
+        t.mgrpf[g][k] = (float)f[k];
+      }
+    }
+    t.wrest = q.w[Q - 1];
+    t.wrestf = (float)t.wrest;
+    t.v0 = q.v0;
+    t.v0f = (float)q.v0;
   }
   if (q.kind == RLBM_QUAD_PRODUCT) {
     // shell factors: the radial weight W_j is w_i / (direction weight)

@@ -12,6 +12,7 @@ struct QuadHost {
   int d = 0, order = 0, kind = 0, Q = 0, nshell = 0, ndir = 0;
   double m = 0.0;
   double v0 = 0.0;            // massive on-lattice rules: the lattice-speed parameter
+  std::vector<int> gfirst;    // massive on-lattice rules: first population of each non-rest group
   std::vector<double> p;      // [Q][d+1]
   std::vector<double> w;      // [Q]
   std::vector<double> disp;   // [Q][d]
@@ -21,10 +22,10 @@ struct QuadHost {
 // v0: massive on-lattice rules only (0 = the middle of the admissible window).
 int build_quadrature(int d, double m, int order, int kind, double v0, QuadHost &q, std::string &err);
 
-// Massive on-lattice (2+1)-d rules (Sec. 5.3): the v0 window where every group
-// weight is >= 0, and the rule at v0 (v0 = 0: the middle of the window).
-int massive_window(double m, int order, double &lo, double &hi, std::string &err);
-int build_massive_2d(double m, int order, double v0, QuadHost &q, std::string &err);
+// Massive on-lattice (d+1)-dimensional rules (Sec. 5.3): the v0 window where
+// every group weight is >= 0, and the rule at v0 (v0 = 0: the middle of the window).
+int massive_window(int d, double m, int order, double &lo, double &hi, std::string &err);
+int build_massive(int d, double m, int order, double v0, QuadHost &q, std::string &err);
 
 // Fills the stencil-independent part of the tables (projection rows, moment
 // weights, interpolation weights, reference state) for quadrature q.

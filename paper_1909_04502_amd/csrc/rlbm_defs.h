@@ -15,7 +15,7 @@
 
 namespace rlbm {
 
-enum StencilId : int { ST_UR2D = 0, ST_PROD2D = 1, ST_PROD3D = 2, ST_MASSIVE2D = 3 };
+enum StencilId : int { ST_UR2D = 0, ST_PROD2D = 1, ST_PROD3D = 2, ST_MASSIVE2D = 3, ST_MASSIVE3D = 4 };
 
 // ---------------------------------------------------------------------------
 // Direction sets.  Antipodal directions are adjacent (k, k+1 for even k).
@@ -45,47 +45,93 @@ constexpr int kURDir[kUR2DQ] = {0, 1, 2, 3, 4, 5, 6, 7, 0, 1, 2, 3, 4, 5, 6, 7,
                                 0, 1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 11};
 
 // Massive on-lattice rules (Sec. 5.3): generating vectors of the full-symmetric
-// groups besides the rest vector.  Order 2: the 29-vector stencil of the
-// worked example; order 3: the 45-vector stencil of the GPU benchmark.
-constexpr int kMassiveGroups2 = 5, kMassiveGroups3 = 9;
-constexpr int kMassiveGen2[kMassiveGroups2][2] = {{1, 0}, {1, 1}, {2, 1}, {2, 2}, {3, 1}};
-constexpr int kMassiveGen3[kMassiveGroups3][2] = {{1, 0}, {1, 1}, {2, 0}, {2, 1}, {2, 2},
-                                                  {3, 0}, {3, 2}, {3, 3}, {4, 0}};
+// groups besides the rest vector.  2D order 2: the 29-vector stencil of the
+// worked example; 2D order 3 and 3D order 3: the 45- and 143-vector stencils
+// of the GPU benchmark (Sec. 6.3).
+constexpr int kMassiveGroups2 = 5, kMassiveGroups3 = 9, kMassiveGroups3D = 10;
+constexpr int kMassiveGen2[kMassiveGroups2][3] = {{1, 0, 0}, {1, 1, 0}, {2, 1, 0}, {2, 2, 0}, {3, 1, 0}};
+constexpr int kMassiveGen3[kMassiveGroups3][3] = {{1, 0, 0}, {1, 1, 0}, {2, 0, 0}, {2, 1, 0}, {2, 2, 0},
+                                                  {3, 0, 0}, {3, 2, 0}, {3, 3, 0}, {4, 0, 0}};
+constexpr int kMassiveGen3D[kMassiveGroups3D][3] = {{1, 0, 0}, {1, 1, 1}, {2, 0, 0}, {2, 1, 1}, {2, 2, 0},
+                                                    {2, 2, 1}, {2, 2, 2}, {3, 0, 0}, {3, 1, 1}, {3, 2, 0}};
+constexpr int kMaxMassiveGroups = 10;
 
 // Non-rest vectors of a massive stencil in population order: per group, the
-// members with first non-zero component > 0 in decreasing (x, y) order, each
-// followed by its opposite.  The rest vector is population Q - 1.
-template <int N>
+// members with first non-zero component > 0 in decreasing lexicographic order,
+// each followed by its opposite.  The rest vector is population Q - 1.
+template <int D, int N>
 struct MassiveDirs {
-  int n = 0;
-  int v[48][2] = {};
+  static constexpr int NG = D == 3 ? kMassiveGroups3D : (N == 2 ? kMassiveGroups2 : kMassiveGroups3);
+  int n = 0;                  // non-rest vectors
+  int v[144][3] = {};
+  int first[kMaxMassiveGroups] = {}, count[kMaxMassiveGroups] = {};
+  int rmax = 0;               // largest |component|
+  static constexpr int gen(int g, int a) {
+    return D == 3 ? kMassiveGen3D[g][a] : (N == 2 ? kMassiveGen2[g][a] : kMassiveGen3[g][a]);
+  }
   constexpr MassiveDirs() {
-    const int ng = N == 2 ? kMassiveGroups2 : kMassiveGroups3;
-    for (int g = 0; g < ng; ++g) {
-      const int a = N == 2 ? kMassiveGen2[g][0] : kMassiveGen3[g][0];
-      const int b = N == 2 ? kMassiveGen2[g][1] : kMassiveGen3[g][1];
-      int pos[4][2] = {}, np = 0;
-      if (b == 0) {
-        pos[np][0] = a, pos[np++][1] = 0;
-        pos[np][0] = 0, pos[np++][1] = a;
-      } else if (a == b) {
-        pos[np][0] = a, pos[np++][1] = a;
-        pos[np][0] = a, pos[np++][1] = -a;
-      } else {
-        pos[np][0] = a, pos[np++][1] = b;
-        pos[np][0] = a, pos[np++][1] = -b;
-        pos[np][0] = b, pos[np++][1] = a;
-        pos[np][0] = b, pos[np++][1] = -a;
-      }
+    constexpr int perm[6][3] = {{0, 1, 2}, {0, 2, 1}, {1, 0, 2}, {1, 2, 0}, {2, 0, 1}, {2, 1, 0}};
+    const int nperm = D == 3 ? 6 : 2;
+    for (int g = 0; g < NG; ++g) {
+      int pos[48][3] = {}, np = 0;
+      for (int pi = 0; pi < nperm; ++pi)
+        for (int sm = 0; sm < (1 << D); ++sm) {
+          int c[3] = {0, 0, 0};
+          for (int a = 0; a < D; ++a) {
+            const int src = D == 3 ? perm[pi][a] : (pi == 0 ? a : 1 - a);
+            c[a] = ((sm >> a) & 1) ? -gen(g, src) : gen(g, src);
+          }
+          int lead = 0;   // sign of the first non-zero component
+          for (int a = D - 1; a >= 0; --a)
+            if (c[a] != 0) lead = c[a];
+          if (lead <= 0) continue;
+          bool dup = false;
+          for (int k = 0; k < np; ++k)
+            if (pos[k][0] == c[0] && pos[k][1] == c[1] && pos[k][2] == c[2]) dup = true;
+          if (dup) continue;
+          pos[np][0] = c[0], pos[np][1] = c[1], pos[np][2] = c[2];
+          ++np;
+        }
+      // decreasing lexicographic order
+      for (int i = 0; i < np; ++i)
+        for (int j = i + 1; j < np; ++j) {
+          bool gt = false;
+          for (int a = 0; a < 3; ++a)
+            if (pos[j][a] != pos[i][a]) {
+              gt = pos[j][a] > pos[i][a];
+              break;
+            }
+          if (gt)
+            for (int a = 0; a < 3; ++a) {
+              const int t = pos[i][a];
+              pos[i][a] = pos[j][a];
+              pos[j][a] = t;
+            }
+        }
+      first[g] = n;
+      count[g] = 2 * np;
       for (int k = 0; k < np; ++k) {
-        v[n][0] = pos[k][0], v[n][1] = pos[k][1], ++n;
-        v[n][0] = -pos[k][0], v[n][1] = -pos[k][1], ++n;
+        for (int a = 0; a < 3; ++a) {
+          v[n][a] = pos[k][a];
+          v[n + 1][a] = -pos[k][a];
+          rmax = pos[k][a] > rmax ? pos[k][a] : (-pos[k][a] > rmax ? -pos[k][a] : rmax);
+        }
+        n += 2;
       }
     }
   }
 };
-constexpr MassiveDirs<2> kMassiveDirs2{};
-constexpr MassiveDirs<3> kMassiveDirs3{};
+constexpr MassiveDirs<2, 2> kMassiveDirs22{};
+constexpr MassiveDirs<2, 3> kMassiveDirs23{};
+constexpr MassiveDirs<3, 3> kMassiveDirs33{};
+static_assert(kMassiveDirs22.n == 28 && kMassiveDirs23.n == 44 && kMassiveDirs33.n == 142, "massive stencil sizes");
+
+template <int D, int N>
+RLBM_HD constexpr const MassiveDirs<D, N> &massive_dirs() {
+  if constexpr (D == 3) return kMassiveDirs33;
+  else if constexpr (N == 2) return kMassiveDirs22;
+  else return kMassiveDirs23;
+}
 
 template <int SID, int KR>
 struct Stencil;
@@ -106,23 +152,28 @@ struct Stencil<ST_PROD3D, KR> {
 
 template <>
 struct Stencil<ST_UR2D, 3> {
-  static constexpr int D = 2, NDIR = 12, Q = kUR2DQ, NSHELL = 3;
+  static constexpr int D = 2, NDIR = 12, Q = kUR2DQ, NSHELL = 3, RMAX = 5;
   static constexpr bool ONLAT = true, SHIFT = false;
   // integer displacement of population i (sites per step)
   RLBM_HD static constexpr int dir(int i, int a) { return kDirUR[kURDir[i]][a]; }
 };
 
-// Massive on-lattice rule of order N: Q = 29 (N = 2) or 45 (N = 3), the rest
-// population last.  SHIFT: its projection rows act on the moments of the
-// shifted monomials (p^0 - m)^a p^e (better conditioned for large m).
-template <int N>
-struct Stencil<ST_MASSIVE2D, N> {
-  static constexpr int D = 2, Q = (N == 2 ? kMassiveDirs2.n : kMassiveDirs3.n) + 1, NDIR = Q, NSHELL = 0;
+// Massive on-lattice rules (d = 2: Q = 29 for N = 2, 45 for N = 3; d = 3: Q =
+// 143 for N = 3), the rest population last.  NG groups of equal weight and
+// energy, group g holding populations [gfirst(g), gfirst(g) + gcount(g)).
+template <int D_, int N>
+struct MassiveStencil {
+  static constexpr int D = D_, Q = massive_dirs<D_, N>().n + 1, NDIR = Q, NSHELL = 0;
+  static constexpr int NG = MassiveDirs<D_, N>::NG, RMAX = massive_dirs<D_, N>().rmax;
   static constexpr bool ONLAT = true, SHIFT = true;
-  RLBM_HD static constexpr int dir(int i, int a) {
-    return i >= Q - 1 ? 0 : (N == 2 ? kMassiveDirs2.v[i][a] : kMassiveDirs3.v[i][a]);
-  }
+  RLBM_HD static constexpr int dir(int i, int a) { return i >= Q - 1 ? 0 : massive_dirs<D_, N>().v[i][a]; }
+  RLBM_HD static constexpr int gfirst(int g) { return massive_dirs<D_, N>().first[g]; }
+  RLBM_HD static constexpr int gcount(int g) { return massive_dirs<D_, N>().count[g]; }
 };
+template <int N>
+struct Stencil<ST_MASSIVE2D, N> : MassiveStencil<2, N> {};
+template <int N>
+struct Stencil<ST_MASSIVE3D, N> : MassiveStencil<3, N> {};
 
 // Number of interpolation taps of population i: 2^(number of non-zero direction components).
 template <class ST>
@@ -185,14 +236,14 @@ RLBM_HD constexpr int basis_size(int D, int N) {
 // Per-lattice constant tables (device memory).  Sized for the largest
 // stencil; kernels index only what their stencil uses.
 // ---------------------------------------------------------------------------
-constexpr int kMaxQ = 104;
+constexpr int kMaxQ = 144;
 constexpr int kMaxPairs = kMaxQ / 2;
 constexpr int kMaxNE = 14, kMaxNO = 16, kMaxNM = 30;
 constexpr int kMaxShell = 4;
 constexpr int kNMom3 = 14;   // 4 (N^a) + 10 (T^ab) in 3D; 2D uses 3 + 6
 
 constexpr int kEosTerms = 44;
-constexpr int kMaxPacked = 96;   // packed class blocks of Linv (91 entries for d = 3, N = 3)   // Chebyshev terms of the d = 3 equation-of-state fits
+constexpr int kMaxPacked = 96;   // packed class blocks of Linv (91 entries for d = 3, N = 3)
 
 struct Tables {
   // geometry and physics
@@ -223,6 +274,12 @@ struct Tables {
   double Ro[kMaxPairs][kMaxNO]; // projection rows, odd basis part
   double Rrest[kMaxNE];         // projection row of a rest population (p = (m, 0)), even part
   float Rrestf[kMaxNE];
+  // massive on-lattice rules, per group g (p = (p0, v n), v = v0 p0, weight w, D = p0 - m):
+  // p0, p0^2, v, p0 v, v^2, w v^l (l = 0..3), w D v^l (l = 0..3)
+  double mgrp[kMaxMassiveGroups][13];
+  float mgrpf[kMaxMassiveGroups][13];
+  double wrest, v0;             // rest weight, lattice-speed parameter
+  float wrestf, v0f;
   float Ref[kMaxPairs][kMaxNE]; // float copies for the F32_DEV path
   float Rof[kMaxPairs][kMaxNO];
   float cf[kMaxPairs][3];

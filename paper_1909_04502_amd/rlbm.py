@@ -165,10 +165,10 @@ def quadrature_build(d: int, zeta: float, order: int, kind="product", v0=0.0):
     return p, w, disp
 
 
-def massive_window(zeta: float, order: int):
-    """(lo, hi): the v0 interval of non-negative weights of the 2D massive on-lattice rule (Sec. 5.3)."""
+def massive_window(zeta: float, order: int, d: int = 2):
+    """(lo, hi): the v0 interval of non-negative weights of the massive on-lattice rule (Sec. 5.3)."""
     L = lib()
-    m = _model(2, zeta, order, "massive_onlattice")
+    m = _model(d, zeta, order, "massive_onlattice")
     lo, hi = c_double(0.0), c_double(0.0)
     _check(L.rlbm_massive_window(ctypes.byref(m), ctypes.byref(lo), ctypes.byref(hi)))
     return lo.value, hi.value

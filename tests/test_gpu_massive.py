@@ -172,3 +172,113 @@ def test_massive_launch_variants_agree():
             ref = out.clone()
         else:
             assert rel(out, ref) < 1e-14, v
+
+
+# ---------------------------------------------------------------- (3+1)-d, 143 vectors
+# name: (extent, bc, tau, storage)
+CASES3 = {
+    "d3_periodic": ((9, 7, 6), ("periodic",) * 3, 0.8, "f64"),
+    "d3_open": ((8, 5, 4), ("open", "periodic", "periodic"), 1.1, "f64"),
+    "d3_edge": ((3, 3, 3), ("periodic",) * 3, 0.7, "f64"),          # extent = max |n|
+    "d3_f32dev": ((9, 7, 6), ("periodic",) * 3, 0.9, "f32dev"),
+}
+
+
+@functools.lru_cache(maxsize=None)
+def oracle_rule_3d():
+    return qd.massive_onlattice(3, ZETA, 3)
+
+
+def fields_3d(shape, seed):
+    g = np.random.default_rng(seed)
+    n = 1.0 + 0.02 * g.standard_normal(shape)
+    T = 1.0 + 0.05 * g.uniform(-1, 1, shape)
+    u = 0.05 * g.uniform(-1, 1, (3,) + shape)
+    return n, T, u
+
+
+@pytest.mark.parametrize("name", list(CASES3))
+def test_massive_3d_parity(name):
+    from paper_1909_04502_amd import rlbm as R
+    print(f"[case] massive 3d {name}", flush=True)
+    ext, bc, tau, storage = CASES3[name]
+    q = oracle_rule_3d()
+    n, T, u = (torch.tensor(a) for a in fields_3d(tuple(reversed(ext)), seed=11))
+    gl = R.Lattice(d=3, zeta=ZETA, order=3, kind="massive_onlattice", extent=ext, bc=bc, storage=storage,
+                   tau=tau, v0=q.v0)
+    assert gl.Q == 143
+    ol = OL.Lattice(q, tau, ext, bc=bc)
+    nsteps = 4 if storage == "f64" else 10
+    res = gl.step(gl.init(n, T, u), gl.new_state(), nsteps)
+    mom = gl.moments(res)
+    gl.sync()
+    fs = ol.collide(ol.init(n, T, u))
+    for _ in range(nsteps):
+        fs = ol.collide(ol.stream(fs))
+    ref = ol.macro(ol.stream(fs))
+    tol = 1e-12 if storage == "f64" else 1e-5
+    if storage == "f64":
+        assert rel(res, fs) < tol
+    for k in ("n", "eps", "T"):
+        assert rel(mom[k], ref[k]) < tol, k
+    assert rel(mom["U"], ref["U"]) < tol
+
+
+def window_oracle(q, tau, fields, site, steps, R=3):
+    """f* after `steps` steps at one site of a periodic lattice, from the oracle run on the periodic
+    window of half-width steps * R around it (the update reaches R sites per step, so the window's
+    own wrap-around never reaches the centre)."""
+    h = steps * R
+    n, T, u = fields
+    idx = [np.arange(c - h, c + h + 1) % s for c, s in zip(site, n.shape)]
+    ix = np.ix_(*idx)
+    wn, wT = n[ix], T[ix]
+    wu = np.stack([c[ix] for c in u])
+    w = 2 * h + 1
+    ol = OL.Lattice(q, tau, (w, w, w))
+    fs = ol.collide(ol.init(torch.tensor(wn), torch.tensor(wT), torch.tensor(wu)))
+    for _ in range(steps):
+        fs = ol.collide(ol.stream(fs))
+    return fs[(slice(None), h, h, h)]
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32dev"])
+def test_massive_3d_full_size(storage):
+    """192^3, the benchmark's lattice and launch shape: two steps compared with the oracle at sampled
+    sites (windowed oracle, edges and interior), and over ten more steps the totals of N^0 and T^0a."""
+    from paper_1909_04502_amd import rlbm as R
+    print(f"[case] massive 3d 192^3 {storage}", flush=True)
+    q = oracle_rule_3d()
+    L = 192
+    fields = W.taylor_green_3d(L, L, L, 0.1, density_sigma=1e-3, seed=12)
+    gl = R.Lattice(d=3, zeta=ZETA, order=3, kind="massive_onlattice", extent=(L, L, L), tau=0.8, v0=q.v0,
+                   storage=storage)
+    fa = gl.init(*(torch.tensor(a) for a in fields))
+    fb = gl.new_state()
+    res = gl.step(fa, fb, 2)                 # even: the result is in fa
+    gl.sync()
+    g = np.random.default_rng(13)
+    sites = [(0, 0, 0), (L - 1, L - 1, L - 1), (0, L // 2, L - 2)] + [tuple(g.integers(0, L, 3)) for _ in range(9)]
+    fref = 0.0
+    if storage == "f32dev":        # the buffer holds f - f^ref, f^ref the rest equilibrium at n = T = 1
+        one = torch.ones((1, 1, 1), dtype=torch.float64)
+        rest = torch.zeros((4, 1, 1, 1), dtype=torch.float64)
+        rest[0] = 1.0
+        fref = OL.Lattice(q, 0.8, (1, 1, 1)).equilibrium(one, one, rest)[:, 0, 0, 0]
+    tol = 1e-12 if storage == "f64" else 1e-5
+    for s in sites:
+        ref = window_oracle(q, 0.8, fields, s, 2)
+        got = res[(slice(None),) + tuple(int(c) for c in s)].cpu().to(torch.float64) + fref
+        assert ((got - ref).abs().max() / ref.abs().max()).item() < tol, s
+    if storage == "f64":
+        p = torch.tensor(q.p, device="cuda")
+        w0 = p[:, :1] * p
+        w0[:, 0] = p[:, 0]
+
+        def totals(f):
+            return torch.einsum("i...,ia->a", f, w0).cpu()
+        t0 = totals(res)
+        res = gl.step(res, fb, 10)
+        gl.sync()
+        t1 = totals(res)
+        assert (t1 - t0).abs().max().item() < 1e-13 * t0.abs().max().item()

@@ -114,21 +114,21 @@ def test_tables_build_over_the_zeta_range(rlbm_lib, d, order, zetas):
 
 @pytest.fixture(scope="module")
 def massive_rules():
-    return {order: qd.massive_onlattice_2d(5.0, order) for order in (2, 3)}
+    return {(d, order): qd.massive_onlattice(d, 5.0, order) for d, order in ((2, 2), (2, 3), (3, 3))}
 
 
-@pytest.mark.parametrize("order", [2, 3])
-def test_library_massive_rule_matches_oracle(rlbm_lib, massive_rules, order):
+@pytest.mark.parametrize("d,order", [(2, 2), (2, 3), (3, 3)])
+def test_library_massive_rule_matches_oracle(rlbm_lib, massive_rules, d, order):
     """The binary128 solver of the library against the oracle's mpmath solver (Sec. 5.3): the v0
     window, the rule at the oracle's v0 and the default (v0 = 0 -> middle of the window)."""
     from paper_1909_04502_amd import rlbm as R
-    q = massive_rules[order]
-    lo, hi = R.massive_window(5.0, order)
-    qlo, qhi = qd.massive_feasible_window(5.0, order)
+    q = massive_rules[(d, order)]
+    lo, hi = R.massive_window(5.0, order, d=d)
+    qlo, qhi = q.window
     assert abs(lo - qlo) < 1e-15 and abs(hi - qhi) < 1e-15
     for v0 in (q.v0, 0.0):
-        p, w, disp = R.quadrature_build(2, 5.0, order, "massive_onlattice", v0=v0)
-        assert p.shape[0] == q.Q == (29 if order == 2 else 45)
+        p, w, disp = R.quadrature_build(d, 5.0, order, "massive_onlattice", v0=v0)
+        assert p.shape[0] == q.Q == {(2, 2): 29, (2, 3): 45, (3, 3): 143}[(d, order)]
         assert np.abs(p.numpy() - q.p).max() < 1e-14 * np.abs(q.p).max()
         assert np.abs(w.numpy() - q.w).max() < 1e-12 * q.w.max()
         assert np.all(disp.numpy() == q.disp)
@@ -150,7 +150,7 @@ def test_library_massive_rule_rejections(rlbm_lib):
     from paper_1909_04502_amd import rlbm as R
     for args, kw in [((2, 0.0, 3, "massive_onlattice"), {}),            # massless
                      ((2, 5.0, 4, "massive_onlattice"), {}),            # order
-                     ((3, 5.0, 3, "massive_onlattice"), {}),            # d
+                     ((3, 5.0, 2, "massive_onlattice"), {}),            # no 3D order-2 stencil
                      ((2, 5.0, 2, "massive_onlattice"), {"v0": 0.26}),  # outside the window
                      ((2, 5.0, 2, "massive_onlattice"), {"v0": 0.4})]:  # beyond 1/max|n|
         with pytest.raises(R.RLBMError) as e:

@@ -36,6 +36,23 @@ def taylor_green_2d(nx: int, ny: int, u0: float, n0: float = 1.0, T0: float = 1.
     return n, T, u
 
 
+def taylor_green_3d(nx: int, ny: int, nz: int, u0: float, n0: float = 1.0, T0: float = 1.0,
+                    density_sigma: float = 0.0, seed: int | None = None):
+    """Return n, T (nz, ny, nx) and u (3, nz, ny, nx) for the 3D Taylor-Green vortex
+    u = u0 (sin x cos y cos z, -cos x sin y cos z, 0), with optional Gaussian density noise."""
+    x = 2.0 * np.pi * np.arange(nx) / nx
+    y = 2.0 * np.pi * np.arange(ny) / ny
+    z = 2.0 * np.pi * np.arange(nz) / nz
+    Z, Y, X = np.meshgrid(z, y, x, indexing="ij")     # shape (nz, ny, nx)
+    u = np.stack([u0 * np.sin(X) * np.cos(Y) * np.cos(Z), -u0 * np.cos(X) * np.sin(Y) * np.cos(Z),
+                  np.zeros_like(X)])
+    n = np.full((nz, ny, nx), n0, dtype=np.float64)
+    if density_sigma > 0.0:
+        n = n + density_sigma * rng(seed).standard_normal((nz, ny, nx))
+    T = np.full((nz, ny, nx), T0, dtype=np.float64)
+    return n, T, u
+
+
 def riemann_3d(nx: int, ny: int, nz: int, x0: int, nL: float, TL: float, nR: float, TR: float):
     """Return n, T (nz, ny, nx) and u (3, nz, ny, nx) = 0 for a shock tube split at x = x0."""
     n = np.where(np.arange(nx)[None, None, :] < x0, nL, nR) * np.ones((nz, ny, 1))
