@@ -327,11 +327,12 @@ __device__ __forceinline__ void gather_onlat_impl(const S *__restrict__ fin, int
    ...);
 }
 
+// byte offsets of the rows x + k - R, y + k - R, z + k - R (k = 0 .. 2R)
 template <class ST, typename S>
-__device__ __forceinline__ void gather_onlat(const Tables *__restrict__ tb, const S *__restrict__ fin, int64_t sites,
-                                             int x, int y, int z, S (&f)[ST::Q]) {
+__device__ __forceinline__ void onlat_offsets(const Tables *__restrict__ tb, int x, int y, int z,
+                                              uint32_t (&ox)[2 * ST::RMAX + 1], uint32_t (&oy)[2 * ST::RMAX + 1],
+                                              uint32_t (&oz)[2 * ST::RMAX + 1]) {
   constexpr int R = ST::RMAX;
-  uint32_t ox[2 * R + 1], oy[2 * R + 1], oz[2 * R + 1];
   const uint32_t nx = tb->nx, nxy = (uint32_t)tb->nx * tb->ny;
 #pragma unroll
   for (int k = 0; k <= 2 * R; ++k) {
@@ -339,6 +340,14 @@ __device__ __forceinline__ void gather_onlat(const Tables *__restrict__ tb, cons
     oy[k] = (uint32_t)wrap_or_clamp(y + k - R, tb->ny, tb->open[1]) * nx * (uint32_t)sizeof(S);
     oz[k] = ST::D == 3 ? (uint32_t)wrap_or_clamp(z + k - R, tb->nz, tb->open[2]) * nxy * (uint32_t)sizeof(S) : 0u;
   }
+}
+
+template <class ST, typename S>
+__device__ __forceinline__ void gather_onlat(const Tables *__restrict__ tb, const S *__restrict__ fin, int64_t sites,
+                                             int x, int y, int z, S (&f)[ST::Q]) {
+  constexpr int R = ST::RMAX;
+  uint32_t ox[2 * R + 1], oy[2 * R + 1], oz[2 * R + 1];
+  onlat_offsets<ST, S>(tb, x, y, z, ox, oy, oz);
   gather_onlat_impl<ST, S, R>(fin, sites, ox, oy, oz, f, std::make_integer_sequence<int, ST::Q>{});
 }
 
@@ -444,6 +453,39 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(OCC > 
   if (last.any) write_fields<ST::D>(last, site, sites, mac);
 }
 
+// Massive rules whose populations do not fit in registers (the 143-vector 3D
+// stencil in double storage): every population is loaded once for the
+// moments, loaded again (normally from the caches) for the relaxation, and
+// stored at once, so that none stays live across the eigen-solve and the
+// projection.
+template <class ST, int N, typename S, bool DEV, int OCC>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(OCC > 0 ? OCC : 1, 8)))
+k_step_stream(const Tables *__restrict__ tb, const S *__restrict__ fin, S *__restrict__ fout,
+              const void *__restrict__ tau_field, FieldPtrs last, int *err, int xcd) {
+  int x, y, z;
+  if (!site_coords(tb, xcd, x, y, z)) return;
+  const int64_t sites = tb->sites;
+  const int64_t site = ((int64_t)z * tb->ny + y) * tb->nx + x;
+  constexpr int R = ST::RMAX;
+  uint32_t ox[2 * R + 1], oy[2 * R + 1], oz[2 * R + 1];
+  onlat_offsets<ST, S>(tb, x, y, z, ox, oy, oz);
+  // a second, opaque copy of the input pointer: the relaxation's loads are not merged with the
+  // moment loads (which would keep every population live)
+  const S *fin2 = fin;
+  asm volatile("" : "+s"(fin2));
+  const uint32_t site_off = (uint32_t)site * (uint32_t)sizeof(S);
+  auto load = [&](const S *base, int i) {
+    return *(const S *)((const char *)(base + (int64_t)i * sites) + ox[R - ST::dir(i, 0)] + oy[R - ST::dir(i, 1)] +
+                        oz[R - dir_z<ST>(i)]);
+  };
+  const double tau = site_tau<S>(tb, tau_field, site);
+  const Macro<ST::D> mac = massive_update<ST, N, S, DEV, true>(
+      tb, tau, [&](int i) { return load(fin, i); }, [&](int i) { return load(fin2, i); },
+      [&](int i, S v) { *(S *)((char *)(fout + (int64_t)i * sites) + site_off) = v; });
+  if (!mac.ok) flag_error(err);
+  if (last.any) write_fields<ST::D>(last, site, sites, mac);
+}
+
 template <class ST, int N, typename S, bool DEV>
 __global__ void __launch_bounds__(256) k_moments(const Tables *__restrict__ tb, const S *__restrict__ fin,
                                                  FieldPtrs out, int *err) {
@@ -542,8 +584,23 @@ static hipError_t launch_t(const LaunchArgs &a) {
     nb = 8 * ((npatch + 7) / 8) * gx * py * pz;
   }
   dim3 grid((unsigned)nb, 1, 1);
+  // the 143 doubles of the 3D massive rule overflow the registers (scratch spills): stream them;
+  // 143 floats fit, and there the single load is faster
+  constexpr bool kStream = ST::ONLAT && ST::SHIFT && ST::D == 3 && sizeof(S) == 8;
   switch (a.op) {
     case OP_STEP:
+      if constexpr (kStream) {
+        if (vr.occ == 2)
+          hipLaunchKernelGGL((k_step_stream<ST, N, S, DEV, 2>), grid, block, 0, a.stream, a.tb, (const S *)a.fin,
+                             (S *)a.fout, a.tau_field, a.fields, a.err, order);
+        else if (vr.occ == 3)
+          hipLaunchKernelGGL((k_step_stream<ST, N, S, DEV, 3>), grid, block, 0, a.stream, a.tb, (const S *)a.fin,
+                             (S *)a.fout, a.tau_field, a.fields, a.err, order);
+        else
+          hipLaunchKernelGGL((k_step_stream<ST, N, S, DEV, 0>), grid, block, 0, a.stream, a.tb, (const S *)a.fin,
+                             (S *)a.fout, a.tau_field, a.fields, a.err, order);
+        break;
+      }
       if (a.ext)
         hipLaunchKernelGGL((k_step<ST, N, S, DEV, 0, true>), grid, block, 0, a.stream, a.tb, (const S *)a.fin,
                            (S *)a.fout, a.tau_field, a.fields, a.err, order);

@@ -111,8 +111,15 @@ __device__ __forceinline__ void massive_coefficients(const Tables *__restrict__ 
   }
 }
 
-template <class ST, int N, typename S, bool DEV, bool RELAX>
-__device__ __forceinline__ Macro<ST::D> collide_massive(const Tables *__restrict__ tb, S (&f)[ST::Q], double tau) {
+// The update of one site with the populations reached through callbacks:
+// fetch(i) returns the pre-collision f_i for the moments, refetch(i) returns it
+// again for the relaxation, and put(i, v) takes the post-collision value.  The
+// register-resident collide passes its array; the streaming kernel loads from
+// memory twice and stores directly, so that no population stays live across
+// the eigen-solve and the projection.
+template <class ST, int N, typename S, bool DEV, bool RELAX, class Fetch, class Refetch, class Put>
+__device__ __forceinline__ Macro<ST::D> massive_update(const Tables *__restrict__ tb, double tau, Fetch &&fetch,
+                                                       Refetch &&refetch, Put &&put) {
   constexpr int D = ST::D, Q = ST::Q, NG = ST::NG, NT = D * (D + 1) / 2;
   using B = BasisDef<D, N>;
   constexpr AngTable<D, N> AT{};
@@ -132,8 +139,9 @@ __device__ __forceinline__ Macro<ST::D> collide_massive(const Tables *__restrict
     for (int a = 0; a < NT; ++a) Sab[a] = 0;
 #pragma unroll
     for (int i = ST::gfirst(g); i < ST::gfirst(g) + ST::gcount(g); i += 2) {
-      const A s = f[i] + f[i + 1];
-      const A d = f[i] - f[i + 1];
+      const A fi = fetch(i), fj = fetch(i + 1);
+      const A s = fi + fj;
+      const A d = fi - fj;
       S0 += s;
 #pragma unroll
       for (int a = 0; a < D; ++a) {
@@ -171,7 +179,7 @@ __device__ __forceinline__ Macro<ST::D> collide_massive(const Tables *__restrict
   }
   {
     const double m = tb->m;
-    const A fr = f[Q - 1];
+    const A fr = fetch(Q - 1);
     N0 += (A)m * fr;
     T00 += (A)(m * m) * fr;
   }
@@ -261,17 +269,23 @@ __device__ __forceinline__ Macro<ST::D> collide_massive(const Tables *__restrict
         else if (c != 0) b += (A)c * ub[a];
       }
       const A om0 = a0 - b, om1 = a0 + b;
-      const A f0 = f[i], f1 = f[i + 1];
-      f[i] = f0 + om0 * ((E + O) - f0);
-      f[i + 1] = f1 + om1 * ((E - O) - f1);
+      const A f0 = refetch(i), f1 = refetch(i + 1);
+      put(i, f0 + om0 * ((E + O) - f0));
+      put(i + 1, f1 + om1 * ((E - O) - f1));
     }
   }
   {
     const A E = ap[0] * tab<A>(tb->wrest, tb->wrestf);   // the constant monomial is basis entry 0
-    const A fr = f[Q - 1];
-    f[Q - 1] = fr + a0 * (E - fr);
+    const A fr = refetch(Q - 1);
+    put(Q - 1, fr + a0 * (E - fr));
   }
   return mac;
+}
+
+template <class ST, int N, typename S, bool DEV, bool RELAX>
+__device__ __forceinline__ Macro<ST::D> collide_massive(const Tables *__restrict__ tb, S (&f)[ST::Q], double tau) {
+  auto get = [&](int i) { return f[i]; };
+  return massive_update<ST, N, S, DEV, RELAX>(tb, tau, get, get, [&](int i, S v) { f[i] = v; });
 }
 
 }  // namespace rlbm
