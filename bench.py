@@ -327,6 +327,53 @@ def massive_leg(warmup, steps):
     return out
 
 
+def sod_leg(warmup, steps):
+    """The ultra-relativistic Sod tube of the paper's inviscid test with the printed order-3 massless
+    rule (Q = 44, integer shifts, FP64): 6400 x 5 sites (a mirror-periodic tube, uniform across the
+    five rows), tau = 1/2 + tau_T / T for eta/s = 0.002, 300 steps to t = 3.0 fm/c (its agreement
+    with App. D is checked by the tests); and the same rule on a 1024 x 1024 Taylor-Green lattice for
+    throughput (704 algorithmic bytes per site)."""
+    import numpy as np
+    import torch
+    import workloads as W
+    from paper_1909_04502_amd import rlbm as R
+    out = {}
+    nx, ny, split, nsteps = 6400, 5, 1600, 300
+    PL, PR, TR = 1.0, 1.0 / 5.43, 0.475
+    nR = PR / TR
+    k = np.arange(nx)
+    left = np.where(k < nx // 2, k, nx - 1 - k) < split
+    n = torch.tensor(np.where(left, 1.0, nR)[None, :] * np.ones((ny, 1)))
+    T = torch.tensor(np.where(left, 1.0, TR)[None, :] * np.ones((ny, 1)))
+    u = torch.zeros((2, ny, nx), dtype=torch.float64)
+    tau_T = 0.002 * 3 / 0.75 * (197.327 / 400.0) / 0.01
+    lat = R.Lattice(d=2, zeta=0.0, order=3, kind="ur_onlattice", extent=(nx, ny), tau=0.5, tau_T=tau_T)
+    fa = lat.init(n, T, u)
+    fb = lat.new_state()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    lat.step(fa, fb, nsteps)
+    e1.record()
+    torch.cuda.synchronize()
+    t = e0.elapsed_time(e1) * 1e-3
+    lat.sync()
+    out["sod_6400x5"] = {"steps": nsteps, "ms_total": round(t * 1e3, 3), "MLUPS": round(nx * ny * nsteps / t / 1e6, 1)}
+    del lat, fa, fb
+    L = 1024
+    n, T, u = W.taylor_green_2d(L, L, 0.01, seed=2)
+    lat = R.Lattice(d=2, zeta=0.0, order=3, kind="ur_onlattice", extent=(L, L), tau=0.9)
+    fa = lat.init(torch.tensor(n), torch.tensor(T), torch.tensor(u))
+    fb = lat.new_state()
+    t = time_steps(lat, fa, fb, warmup, steps)
+    b = 2 * lat.Q * 8 * L * L
+    out["ur3_1024x1024"] = {"MLUPS": round(L * L / t / 1e6, 2), "ms_per_step": round(t * 1e3, 5),
+                            "achieved_GBs": round(b / t / 1e9, 1), "frac": round(b / t / 1e9 / HBM_PEAK_GBS, 4)}
+    del lat, fa, fb
+    torch.cuda.empty_cache()
+    return out
+
+
 def forcing_leg(L, warmup, steps):
     """The headline workload with the external force of Sec. 5.4 (scheme B, g = 1e-6 along y) and no-slip
     equilibrium walls on the x faces: the force/wall build of the step kernel."""
@@ -432,6 +479,7 @@ def main():
     if not args.no_onlattice:
         out["onlattice_ur"] = onlattice_leg(args.warmup, args.steps)
         out["massive_onlattice"] = massive_leg(args.warmup, args.steps)
+        out["sod_ur"] = sod_leg(args.warmup, args.steps)
     if not args.no_forcing:
         out["forcing_walls"] = forcing_leg(L, args.warmup, args.steps)
     if not args.no_copy:

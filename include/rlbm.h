@@ -35,9 +35,10 @@
  *     (+-1,0,0) (0,+-1,0) (0,0,+-1), (1,1,0) (-1,-1,0) (1,-1,0) (-1,1,0),
  *     (1,0,1) (-1,0,-1) (1,0,-1) (-1,0,1), (0,1,1) (0,-1,-1) (0,1,-1) (0,-1,1),
  *     (1,1,1) (-1,-1,-1) (1,1,-1) (-1,-1,1) (1,-1,1) (-1,1,-1) (-1,1,1) (1,-1,-1);
- *   for the printed on-lattice massless rule (Sec. 5.3 / App. H.2, order 2)
+ *   for the printed on-lattice massless rules (Sec. 5.3 / App. H.2)
  *     (3,4) (-3,-4) (-3,4) (3,-4) (4,3) (-4,-3) (-4,3) (4,-3) (5,0) (-5,0) (0,5) (0,-5)
- *   on three shells, zero-weight populations dropped (28 populations);
+ *   on three (order 2) or four (order 3) shells, zero-weight populations
+ *   dropped (28 / 44 populations);
  *   for the massive on-lattice rules the generating vectors of the groups
  *     order 2: (1,0) (1,1) (2,1) (2,2) (3,1)
  *     order 3: (1,0) (1,1) (2,0) (2,1) (2,2) (3,0) (3,2) (3,3) (4,0)
@@ -92,7 +93,8 @@ typedef enum { RLBM_F64 = 0, RLBM_F32_DEV = 1 } rlbm_storage;
  * validation, Sec. 7.2).  Product rules only. */
 typedef enum { RLBM_PERIODIC = 0, RLBM_OPEN = 1, RLBM_WALL = 2 } rlbm_bc;
 typedef enum {
-  RLBM_QUAD_UR_ONLATTICE = 0, /* printed massless (2+1)-d order-2 rule, integer streaming (zeta = 0) */
+  RLBM_QUAD_UR_ONLATTICE = 0, /* printed massless (2+1)-d rules of order 2 and 3 (App. H.2), integer
+                               * streaming (zeta = 0) */
   RLBM_QUAD_PRODUCT = 1,      /* off-lattice product rule: shells x directions, interpolated streaming */
   RLBM_QUAD_MASSIVE_ONLATTICE = 2 /* massive (2+1)-d on-lattice rule (Sec. 5.3): integer vectors n_i in
                                    * full-symmetric groups, p_i = p^0_i (1, v0 n_i) with p^0_i =
@@ -106,7 +108,7 @@ typedef enum {
  * mass zeta = m/T0, expansion order N and the quadrature. */
 typedef struct {
   int32_t d;        /* spatial dimensions: 2 or 3 */
-  int32_t order;    /* expansion order N: 2 or 3 (RLBM_QUAD_UR_ONLATTICE: 2) */
+  int32_t order;    /* expansion order N: 2 or 3 */
   int32_t kind;     /* rlbm_quad_kind */
   int32_t pad_;
   double zeta;      /* reduced mass m c^2/(k_B T0), >= 0 */
@@ -128,6 +130,12 @@ typedef struct {
                         * the update subtracts F^ext_i = -(m/T) (K^a U_a / p_i^0) f^eq_i, the
                         * sign of the kinetic equation (the fluid accelerates along g).  Zero =
                         * no force; no effect for zeta = 0 (the term carries the mass). */
+  double tau_T;        /* on-lattice rules: the relaxation time becomes tau(x) + tau_T / T(x),
+                        * T the site's temperature of the step (Sec. 6.2 step 7, tau chosen so
+                        * that eta/s stays constant: for a massless gas with s = (d + 1) n and
+                        * the lattice shear viscosity eta = c_eta P (tau - 1/2), take tau = 1/2
+                        * and tau_T = (eta/s)(d + 1)/c_eta in lattice units).  0 = off;
+                        * RLBM_ERR_UNSUPPORTED for product rules. */
 } rlbm_config;
 
 typedef struct {

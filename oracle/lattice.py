@@ -20,7 +20,10 @@ One time step (Sec. 6.2, the eight numbered operations):
     (the kinetic equation carries -F^ext; Sec. 6.2 prints "+ F^ext", read here
     as the same term with the equation's sign, which accelerates the fluid
     along g).
- 7. tau: a constant or a per-site field
+ 7. tau: a constant or a per-site field, plus optionally tau_T / T(x), the law that
+    keeps eta/s constant for a massless gas with s = (d + 1) n and the lattice shear
+    viscosity eta = c_eta P (tau - 1/2) (Sec. 6.2 step 7 leaves the law open; reading:
+    tau = 1/2 + (eta/s)(d + 1)/(c_eta T) in lattice units)
  8. f_i(x + v_i dt, t + dt) = (1 - Omega_i) f_i + Omega_i f^eq_i with
     Omega_i = dt p_i^mu U_mu / (p_i^0 tau), dt = 1.
 Streaming moves f_i by its displacement delta_i.  For integer delta_i it is
@@ -67,7 +70,7 @@ class Lattice:
     "open" in the same order; ``tau`` a float or a tensor of grid shape.
     """
 
-    def __init__(self, quad: Quadrature, tau, extent, bc=None, force=None):
+    def __init__(self, quad: Quadrature, tau, extent, bc=None, force=None, tau_T: float = 0.0):
         self.quad = quad
         self.d = quad.d
         self.m = float(quad.m)
@@ -81,6 +84,7 @@ class Lattice:
         self.tau = tau
         self.eta = eta_matrix(self.d)
         self.force = None if force is None else torch.as_tensor(force, dtype=torch.float64)[: self.d]
+        self.tau_T = float(tau_T)
 
     # -- step 1 -------------------------------------------------------------
     def moments(self, f):
@@ -174,6 +178,8 @@ class Lattice:
         feq = self.equilibrium(mac["n"], mac["T"], mac["U"])
         if tau is None:
             tau = self.tau_at(mac["n"])
+            if self.tau_T != 0.0:                  # step 7: tau from the local temperature
+                tau = tau + self.tau_T / mac["T"]
         Om = self.omega(mac["U"], tau)
         out = f + Om * (feq - f)
         if self.force is not None and self.m > 0.0:

@@ -15,14 +15,16 @@ antipodal directions are adjacent (k, k+1 for even k).  Zero-weight
 populations of the printed ultra-relativistic rule are dropped.
 
 Rules:
-* ``ur_onlattice_2d``: the printed (2+1)-d massless rule of order 2
-  (Sec. 5.3, worked example, and App. H.2 "Order 2"), stencil
+* ``ur_onlattice_2d``: the printed (2+1)-d massless rules of order 2
+  (Sec. 5.3, worked example, and App. H.2 "Order 2") and order 3 (App. H.2
+  "Order 3", four shells, used for the Sod tests), stencil
   (+-3,+-4)_FS U (+-5,0)_FS, three energy shells.  Displacements are the
   integer stencil vectors: speed c = 1 means |n_i| = 5 sites per step
   (v0 = 1/5).  Reading of the printed weight list: the main-text values
   w_{1j} = (0, 0, 1.7536e-3) belong to the (+-5,0) group and
   w_{2j} = (8.889e-2, 3.481e-2, 4.219e-4) to the (+-3,+-4) group, the only
-  assignment with sum_i w_i = 1.
+  assignment with sum_i w_i = 1; the order-3 list is read the same way (again
+  the only normalised assignment).
 * ``product_2d`` / ``product_3d``: off-lattice product rules.  The paper names
   off-lattice schemes but does not build them (Sec. 5.3, last paragraphs;
   Sec. 7.3 closing remark); this is the reading used here.  In d = 2,
@@ -68,6 +70,12 @@ UR2D_SHELLS = (0.4157745567834790, 2.2942803602790417, 6.2899450829374791)
 UR2D_W_34 = (0.0888866262411466, 0.0348147166961551, 0.0004218743543938)   # (+-3,+-4)_FS group
 UR2D_W_50 = (0.0, 0.0, 0.0017535654166088)                                  # (+-5, 0)_FS group
 
+# Printed (2+1)-d ultra-relativistic order-3 rule (App. H.2), same stencil, four shells; the printed
+# weight list read shell-major with the (+-5,0) group first in each shell (as for order 2).
+UR2D3_SHELLS = (0.3225476896193923, 1.7457611011583465, 4.5366202969211279, 9.3950709123011331)
+UR2D3_W_50 = (0.0, 0.0410206173754781, 0.0044457884155769, 0.0000616926157132)
+UR2D3_W_34 = (0.0753942630427042, 0.0241670278669858, 0.0026380943565871, 0.0000365655303385)
+
 DIRS_UR2D = [(3, 4), (-3, -4), (-3, 4), (3, -4), (4, 3), (-4, -3), (-4, 3), (4, -3),
              (5, 0), (-5, 0), (0, 5), (0, -5)]
 DIRS_2D = [(1, 0), (-1, 0), (0, 1), (0, -1), (1, 1), (-1, -1), (-1, 1), (1, -1)]
@@ -105,19 +113,22 @@ class Quadrature:
         return self.w.shape[0]
 
 
-def ur_onlattice_2d() -> Quadrature:
-    """Printed massless (2+1)-d rule of order 2 (Sec. 5.3 and App. H.2), 28 non-zero populations."""
+def ur_onlattice_2d(order: int = 2) -> Quadrature:
+    """Printed massless (2+1)-d rules (Sec. 5.3 and App. H.2): order 2 (28 non-zero populations) and
+    order 3 (44 non-zero populations)."""
+    shells, w34, w50 = (UR2D_SHELLS, UR2D_W_34, UR2D_W_50) if order == 2 else \
+        (UR2D3_SHELLS, UR2D3_W_34, UR2D3_W_50)
     p, w, disp = [], [], []
-    for j, p0 in enumerate(UR2D_SHELLS):
+    for j, p0 in enumerate(shells):
         for (nx, ny) in DIRS_UR2D:
-            wj = UR2D_W_50[j] if nx * ny == 0 else UR2D_W_34[j]
+            wj = w50[j] if nx * ny == 0 else w34[j]
             if wj == 0.0:
                 continue
             norm = math.hypot(nx, ny)          # = 5 for every vector of the stencil
             p.append((p0, p0 * nx / norm, p0 * ny / norm))
             w.append(wj)
             disp.append((float(nx), float(ny)))
-    return Quadrature(2, 0.0, 2, np.array(p), np.array(w), np.array(disp), True)
+    return Quadrature(2, 0.0, order, np.array(p), np.array(w), np.array(disp), True)
 
 
 def product_2d(m: float, order: int) -> Quadrature:

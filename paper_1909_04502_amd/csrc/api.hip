@@ -170,6 +170,9 @@ rlbm_status rlbm_create(const rlbm_config *cfg, rlbm_lattice **out) {
     if (!std::isfinite(cfg->force[a])) return fail(RLBM_ERR_INVALID_ARG, "force must be finite");
   }
   if (m.d == 3 && m.kind == RLBM_QUAD_UR_ONLATTICE) return fail(RLBM_ERR_UNSUPPORTED, "the printed massless rule is 2D");
+  if (!std::isfinite(cfg->tau_T)) return fail(RLBM_ERR_INVALID_ARG, "tau_T must be finite");
+  if (cfg->tau_T != 0.0 && m.kind == RLBM_QUAD_PRODUCT)
+    return fail(RLBM_ERR_UNSUPPORTED, "the temperature-dependent tau is built for the on-lattice rules");
   if (m.kind == RLBM_QUAD_MASSIVE_ONLATTICE && (cfg->force[0] != 0.0 || cfg->force[1] != 0.0 || cfg->force[2] != 0.0))
     return fail(RLBM_ERR_UNSUPPORTED, "the external force is built for product rules");
   if (cfg->storage != RLBM_F64 && cfg->storage != RLBM_F32_DEV) return fail(RLBM_ERR_INVALID_ARG, "bad storage");
@@ -215,6 +218,7 @@ rlbm_status rlbm_create(const rlbm_config *cfg, rlbm_lattice **out) {
       t->g[a] = a < m.d ? cfg->force[a] : 0.0;
       t->gf[a] = (float)t->g[a];
     }
+    t->tau_T = cfg->tau_T;
     // the force term carries the mass: nothing to add for zeta = 0
     t->has_force = (m.zeta > 0.0 && m.kind == RLBM_QUAD_PRODUCT &&
                     (t->g[0] != 0.0 || t->g[1] != 0.0 || t->g[2] != 0.0)) ? 1 : 0;

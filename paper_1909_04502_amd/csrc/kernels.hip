@@ -229,6 +229,8 @@ __device__ __forceinline__ Macro<ST::D> collide(const Tables *__restrict__ tb, S
   A M[B::NM];
 #pragma unroll
   for (int k = 0; k < B::NM; ++k) M[k] = (A)Md[k];
+  // ---- step 7: the temperature-dependent part of tau ----
+  if (tb->tau_T != 0.0) tau += tb->tau_T / mac.T;
   // ---- step 8: Omega_i = (U^0 - c_i . U)/tau; f* = f + Omega (f^eq - f) ----
   const double itau = 1.0 / tau;
   const A a0 = (A)(mac.U[0] * itau);
@@ -635,7 +637,10 @@ static hipError_t launch_storage(const LaunchArgs &a) {
 }
 
 hipError_t launch(const LaunchArgs &a) {
-  if (a.stencil == ST_UR2D) return launch_storage<Stencil<ST_UR2D, 3>, 2>(a);
+  if (a.stencil == ST_UR2D) {
+    if (a.order == 2) return launch_storage<Stencil<ST_UR2D, 3>, 2>(a);
+    return launch_storage<Stencil<ST_UR2D, 4>, 3>(a);
+  }
   if (a.stencil == ST_MASSIVE2D) {
     if (a.order == 2) return launch_storage<Stencil<ST_MASSIVE2D, 2>, 2>(a);
     return launch_storage<Stencil<ST_MASSIVE2D, 3>, 3>(a);

@@ -231,6 +231,8 @@ __device__ __forceinline__ Macro<ST::D> massive_update(const Tables *__restrict_
   // ---- step 5: a' over the shifted monomials ----
   A ap[B::NM];
   massive_coefficients<D, N, DEV, A>(tb, mac, rr, ap);
+  // ---- step 7: the temperature-dependent part of tau ----
+  if (tb->tau_T != 0.0) tau += tb->tau_T / mac.T;
   // ---- step 8: Omega_i = a0 - v0 (n_i . U)/tau ----
   const double itau = 1.0 / tau;
   const A a0 = (A)(mac.U[0] * itau);

@@ -1,9 +1,10 @@
 // precompute.cpp -- host construction of quadratures, basis and tables.
 //
 // Quadratures (Sec. 5.3; App. H.2 for the printed massless rule):
-//  * RLBM_QUAD_UR_ONLATTICE: the printed (2+1)-d order-2 rule.  Shells and
-//    weights are the paper's numbers; its stencil vectors have length 5, so a
-//    massless particle crosses 5 sites per step (v0 = 1/5, Sec. 6.1).
+//  * RLBM_QUAD_UR_ONLATTICE: the printed (2+1)-d rules of orders 2 and 3.
+//    Shells and weights are the paper's numbers; the stencil vectors have
+//    length 5, so a massless particle crosses 5 sites per step (v0 = 1/5,
+//    Sec. 6.1).
 //  * RLBM_QUAD_MASSIVE_ONLATTICE: massive on-lattice rules built in
 //    massive.cpp (weights from the moment conditions, v0 by line search).
 //  * RLBM_QUAD_PRODUCT: off-lattice product rule.  In d = 2 the measure
@@ -139,6 +140,12 @@ static void gauss_radial_3d(int n, ld m, std::vector<ld> &x, std::vector<ld> &w)
 static const double kURShells[3] = {0.4157745567834790, 2.2942803602790417, 6.2899450829374791};
 static const double kURW34[3] = {0.0888866262411466, 0.0348147166961551, 0.0004218743543938};
 static const double kURW50[3] = {0.0, 0.0, 0.0017535654166088};
+// Printed massless order-3 rule (App. H.2, (2+1) dimensions, Order 3), the list
+// read as for order 2: shell-major, the (+-5,0) group first in each shell.
+static const double kUR3Shells[4] = {0.3225476896193923, 1.7457611011583465, 4.5366202969211279,
+                                     9.3950709123011331};
+static const double kUR3W34[4] = {0.0753942630427042, 0.0241670278669858, 0.0026380943565871, 0.0000365655303385};
+static const double kUR3W50[4] = {0.0, 0.0410206173754781, 0.0044457884155769, 0.0000616926157132};
 
 int build_quadrature(int d, double m, int order, int kind, double v0, QuadHost &q, std::string &err) {
   if (kind == RLBM_QUAD_MASSIVE_ONLATTICE) return build_massive(d, m, order, v0, q, err);
@@ -148,23 +155,27 @@ int build_quadrature(int d, double m, int order, int kind, double v0, QuadHost &
   q.order = order;
   q.kind = kind;
   if (kind == RLBM_QUAD_UR_ONLATTICE) {
-    if (d != 2 || order != 2 || m != 0.0) {
-      err = "the printed on-lattice rule is massless (zeta = 0), d = 2, order N = 2";
+    if (d != 2 || (order != 2 && order != 3) || m != 0.0) {
+      err = "the printed on-lattice rules are massless (zeta = 0), d = 2, order N = 2 or 3";
       return RLBM_ERR_UNSUPPORTED;
     }
-    q.nshell = 3;
+    q.nshell = order == 2 ? 3 : 4;
     q.ndir = 12;
-    for (int i = 0; i < kUR2DQ; ++i) {
-      int j = kURShell[i], k = kURDir[i];
+    q.Q = order == 2 ? kUR2DQ : kUR3Q;
+    for (int i = 0; i < q.Q; ++i) {
+      const int j = order == 2 ? kURShell[i] : ur3_shell(i), k = order == 2 ? kURDir[i] : ur3_dir(i);
       double nx = kDirUR[k][0], ny = kDirUR[k][1];
       double len = std::sqrt(nx * nx + ny * ny);   // 5
-      double wj = (nx * ny == 0.0) ? kURW50[j] : kURW34[j];
-      double p0 = kURShells[j];
+      double wj = (nx * ny == 0.0) ? (order == 2 ? kURW50[j] : kUR3W50[j]) : (order == 2 ? kURW34[j] : kUR3W34[j]);
+      double p0 = order == 2 ? kURShells[j] : kUR3Shells[j];
+      if (wj == 0.0) {
+        err = "internal: zero-weight population in the printed rule";
+        return RLBM_ERR_QUADRATURE;
+      }
       q.p.insert(q.p.end(), {p0, p0 * nx / len, p0 * ny / len});
       q.w.push_back(wj);
       q.disp.insert(q.disp.end(), {nx, ny});
     }
-    q.Q = kUR2DQ;
     return 0;
   }
   if (kind != RLBM_QUAD_PRODUCT) {

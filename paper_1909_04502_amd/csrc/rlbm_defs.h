@@ -158,6 +158,21 @@ struct Stencil<ST_UR2D, 3> {
   RLBM_HD static constexpr int dir(int i, int a) { return kDirUR[kURDir[i]][a]; }
 };
 
+// Printed massless (2+1)-d order-3 rule (App. H.2): the same 12 directions on
+// four shells; shell 0 carries no (+-5,0) population (zero weight), so the
+// populations are shell 0's eight (+-3,+-4) directions, then all twelve
+// directions of shells 1, 2, 3.
+constexpr int kUR3Q = 44;
+RLBM_HD constexpr int ur3_shell(int i) { return i < 8 ? 0 : 1 + (i - 8) / 12; }
+RLBM_HD constexpr int ur3_dir(int i) { return i < 8 ? i : (i - 8) % 12; }
+
+template <>
+struct Stencil<ST_UR2D, 4> {
+  static constexpr int D = 2, NDIR = 12, Q = kUR3Q, NSHELL = 4, RMAX = 5;
+  static constexpr bool ONLAT = true, SHIFT = false;
+  RLBM_HD static constexpr int dir(int i, int a) { return kDirUR[ur3_dir(i)][a]; }
+};
+
 // Massive on-lattice rules (d = 2: Q = 29 for N = 2, 45 for N = 3; d = 3: Q =
 // 143 for N = 3), the rest population last.  NG groups of equal weight and
 // energy, group g holding populations [gfirst(g), gfirst(g) + gcount(g)).
@@ -280,6 +295,7 @@ struct Tables {
   float mgrpf[kMaxMassiveGroups][13];
   double wrest, v0;             // rest weight, lattice-speed parameter
   float wrestf, v0f;
+  double tau_T;                 // on-lattice rules: tau(x) += tau_T / T(x) (0 = off)
   float Ref[kMaxPairs][kMaxNE]; // float copies for the F32_DEV path
   float Rof[kMaxPairs][kMaxNO];
   float cf[kMaxPairs][3];

@@ -26,6 +26,7 @@ def test_library_exports_every_declared_symbol(rlbm_lib):
 
 @pytest.mark.parametrize("d,zeta,order,kind,ref", [
     (2, 0.0, 2, "ur_onlattice", lambda: qd.ur_onlattice_2d()),
+    (2, 0.0, 3, "ur_onlattice", lambda: qd.ur_onlattice_2d(3)),
     (2, 0.0, 3, "product", lambda: qd.product_2d(0.0, 3)),
     (2, 1.0, 3, "product", lambda: qd.product_2d(1.0, 3)),
     (2, 2.5, 2, "product", lambda: qd.product_2d(2.5, 2)),
@@ -66,6 +67,12 @@ def test_create_validates_before_touching_the_device(rlbm_lib):
     cfg.tau = 0.8
     cfg.storage = 7
     assert rlbm_lib.rlbm_create(ctypes.byref(cfg), ctypes.byref(h)) == R.ERR_INVALID_ARG
+    cfg.storage = 0
+    cfg.tau_T = 0.3                                     # the tau law is built for on-lattice rules
+    assert rlbm_lib.rlbm_create(ctypes.byref(cfg), ctypes.byref(h)) == R.ERR_UNSUPPORTED
+    cfg.tau_T = float("nan")
+    assert rlbm_lib.rlbm_create(ctypes.byref(cfg), ctypes.byref(h)) == R.ERR_INVALID_ARG
+    cfg.tau_T = 0.0
     assert rlbm_lib.rlbm_step(None, None, None, 1, None, None) == R.ERR_INVALID_ARG
 
 

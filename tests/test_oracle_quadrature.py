@@ -310,3 +310,24 @@ def test_massive_3d_rule(massive3d):
     # at the window's ends one weight vanishes
     for v in (lo, hi):
         assert abs(min(qd.massive_group_weights(5.0, 3, v, d=3))) < 1e-9
+
+
+def test_printed_ur_order3_rule():
+    """App. H.2, (2+1)-d order 3: the shells are the 4-point Gauss-Laguerre nodes, the list read
+    shell-major with the (+-5,0) group first normalises (the literal caption order does not), the
+    per-shell sums are the Gauss-Laguerre weights, and the rule is exact to degree 2N = 6."""
+    tab = json.load(open(os.path.join(GOLDEN, "ur_2d_order3_table.json")))
+    wl = tab["weights_as_printed"]
+    w50, w34 = wl[0::2], wl[1::2]
+    assert 4 * sum(w50) + 8 * sum(w34) == pytest.approx(1.0, abs=1e-14)
+    assert abs(8 * sum(wl[0:4]) + 4 * sum(wl[4:8]) - 1.0) > 0.1
+    x, W = np.polynomial.laguerre.laggauss(4)
+    assert np.allclose(tab["shells"], x, rtol=1e-15)
+    assert np.allclose([8 * w34[j] + 4 * w50[j] for j in range(4)], W, rtol=1e-13)
+    q = qd.ur_onlattice_2d(3)
+    assert q.Q == 44 and q.order == 3
+    for deg in range(7):       # the printed 16-digit weights limit the agreement (~7e-13 at degree 6)
+        assert max_moment_error(q.p, q.w, 0.0, 2, deg) < 1e-11, deg
+    assert max_moment_error(q.p, q.w, 0.0, 2, 7) > 1e-6
+    assert np.all(np.abs(np.hypot(q.disp[:, 0], q.disp[:, 1]) - 5.0) == 0)
+    assert np.allclose(q.p[0:44:2, 1:], -q.p[1:44:2, 1:])
