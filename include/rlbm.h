@@ -89,8 +89,10 @@ typedef enum {
 typedef enum { RLBM_F64 = 0, RLBM_F32_DEV = 1 } rlbm_storage;
 /* RLBM_WALL: reads clamp as RLBM_OPEN, and the first and last plane of the
  * axis are no-slip walls whose collision is replaced by the local equilibrium
- * at zero flow speed (the site's own n and T; the walls of the forcing
- * validation, Sec. 7.2).  Product rules only. */
+ * at zero flow speed (the site's own n and T, or a prescribed T:
+ * rlbm_config.wall_T; the walls of the forcing validation, Sec. 7.2, and the
+ * plates of the thermal-conductivity measurement, Sec. 7.1).  Product and
+ * massive rules (not the 3D massive rule in double storage). */
 typedef enum { RLBM_PERIODIC = 0, RLBM_OPEN = 1, RLBM_WALL = 2 } rlbm_bc;
 typedef enum {
   RLBM_QUAD_UR_ONLATTICE = 0, /* printed massless (2+1)-d rules of order 2 and 3 (App. H.2), integer
@@ -136,6 +138,10 @@ typedef struct {
                         * the lattice shear viscosity eta = c_eta P (tau - 1/2), take tau = 1/2
                         * and tau_T = (eta/s)(d + 1)/c_eta in lattice units).  0 = off;
                         * RLBM_ERR_UNSUPPORTED for product rules. */
+  double wall_T[3][2]; /* RLBM_WALL axes: the temperature imposed on the first [a][0] and last
+                        * [a][1] plane (the heated and cooled plates of the thermal-conductivity
+                        * measurement, Sec. 7.1); 0 = the site's own temperature.  The wall
+                        * site keeps its own n.  >= 0; non-zero only on wall axes. */
 } rlbm_config;
 
 typedef struct {

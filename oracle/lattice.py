@@ -35,7 +35,9 @@ Boundaries: periodic, or "open" = zero-gradient: a read outside the grid
 takes the value of the nearest boundary plane, or "wall": the open read plus
 no-slip walls on the first and last plane of the axis, where the collision is
 replaced by the local equilibrium at zero flow speed (n and T of the site,
-U = (1, 0, ...)), as in the forcing validation of Sec. 7.2.
+U = (1, 0, ...)), as in the forcing validation of Sec. 7.2; a wall plane may
+instead hold a prescribed temperature (the heated and cooled plates of the
+thermal-conductivity measurement, Sec. 7.1), keeping the site's own n.
 """
 from __future__ import annotations
 
@@ -70,7 +72,7 @@ class Lattice:
     "open" in the same order; ``tau`` a float or a tensor of grid shape.
     """
 
-    def __init__(self, quad: Quadrature, tau, extent, bc=None, force=None, tau_T: float = 0.0):
+    def __init__(self, quad: Quadrature, tau, extent, bc=None, force=None, tau_T: float = 0.0, wall_T=None):
         self.quad = quad
         self.d = quad.d
         self.m = float(quad.m)
@@ -85,6 +87,8 @@ class Lattice:
         self.eta = eta_matrix(self.d)
         self.force = None if force is None else torch.as_tensor(force, dtype=torch.float64)[: self.d]
         self.tau_T = float(tau_T)
+        # per axis (T on the first plane, T on the last plane) of a "wall" axis; 0 = the site's own T
+        self.wall_T = tuple(tuple(map(float, w)) for w in wall_T) if wall_T is not None else None
 
     # -- step 1 -------------------------------------------------------------
     def moments(self, f):
@@ -189,7 +193,18 @@ class Lattice:
             if mask.any():
                 rest = torch.zeros_like(mac["U"])
                 rest[0] = 1.0
-                feq0 = self.equilibrium(mac["n"], mac["T"], rest)
+                Tw = mac["T"].clone()
+                if self.wall_T is not None:
+                    for ax in range(self.d):
+                        if self.bc[ax] != "wall":
+                            continue
+                        dim = Tw.dim() - 1 - ax
+                        for end, Tset in zip((0, Tw.shape[dim] - 1), self.wall_T[ax]):
+                            if Tset > 0.0:
+                                idx = [slice(None)] * Tw.dim()
+                                idx[dim] = end
+                                Tw[tuple(idx)] = Tset
+                feq0 = self.equilibrium(mac["n"], Tw, rest)
                 out = torch.where(mask[None], feq0, out)
         return out
 

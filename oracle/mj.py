@@ -11,7 +11,8 @@ Sources in the paper:
 * Normalisation B(n,T) of the equilibrium: Sec. 3, Eq. (phys-normalization).
 * G_d and the equation of state: Sec. 3, Eqs. (defG), (eos-ddim), and the
   limits (ultra-relativistic-eos) and eps_c = (d/2) P.
-* Chapman-Enskog shear viscosity eta = P tau a_43: App. C.1 (explicit d = 2
+* Chapman-Enskog shear viscosity eta = P tau a_43, thermal conductivity
+  lambda = n tau G (a_22 G - 1) and bulk viscosity mu: App. C (explicit d = 2
   and d = 3 forms), with Gamma(0, x) and the Bickley-Naylor function Ki_1
   as defined at the end of App. B.
 """
@@ -198,3 +199,41 @@ def ce_shear_ratio(zeta: float, d: int) -> float:
         tail = 0.0 if z == 0.0 else z ** 3 * bickley_ki1(z) / special.kv(2, z)
         return (3.0 * G - 5.0 * z * z + G * z * z - tail) / 15.0
     raise ValueError("ce_shear_ratio: d must be 2 or 3")
+
+
+def ce_conductivity_ratio(zeta: float, d: int) -> float:
+    """lambda / (n tau) from the Chapman-Enskog expansion (App. C, thermal conductivity, explicit forms):
+    d = 2: G (G/2 - 1 - G zeta^2 e^zeta Gamma(0, zeta) / (2 (zeta + 1)));
+    d = 3: G (G (5 - G)/3 - 1 + G zeta Ki_1 / (3 K_2)).
+    Both tend to (d + 1)/d as zeta -> 0."""
+    z = float(zeta)
+    G = float(G_d(z, d))
+    if d == 2:
+        tail = 0.0 if z == 0.0 else z * z * math.exp(z) * special.exp1(z) / (2.0 * (z + 1.0))
+        return G * (G / 2.0 - 1.0 - G * tail)
+    if d == 3:
+        tail = 0.0 if z == 0.0 else z * bickley_ki1(z) / (3.0 * special.kv(2, z))
+        return G * (G * (5.0 - G) / 3.0 - 1.0 + G * tail)
+    raise ValueError("ce_conductivity_ratio: d must be 2 or 3")
+
+
+def ce_bulk_ratio(zeta: float, d: int) -> float:
+    """mu / (P tau) from the Chapman-Enskog expansion (App. C, bulk viscosity).
+
+    General form: a_43 (1 + 2/d) - X / (X - 1) with X = zeta^2 - G^2 + (d + 2) G and
+    a_43 = eta / (P tau) (the shear coefficient, ``ce_shear_ratio``).  d = 2 uses the explicit form
+    (z^4 + 3 z^2 + 2 G^3 - 12 G^2 + 18 G - z^2 G^2 + 2 z^2 G) / (4 (-z^2 + G^2 - 4 G + 1))
+    + e^z z^4 Gamma(0, z) / (4 (z + 1)), which equals the general one; the printed explicit d = 3
+    form does not (it does not vanish as zeta -> 0), so d = 3 uses the general form.
+    mu vanishes for massless particles."""
+    z = float(zeta)
+    if z == 0.0:
+        return 0.0
+    G = float(G_d(z, d))
+    if d == 2:
+        num = z ** 4 + 3 * z * z + 2 * G ** 3 - 12 * G * G + 18 * G - z * z * G * G + 2 * z * z * G
+        return num / (4.0 * (-z * z + G * G - 4 * G + 1)) + math.exp(z) * z ** 4 * special.exp1(z) / (4.0 * (z + 1.0))
+    if d == 3:
+        X = z * z - G * G + (d + 2) * G
+        return ce_shear_ratio(z, d) * (1.0 + 2.0 / d) - X / (X - 1.0)
+    raise ValueError("ce_bulk_ratio: d must be 2 or 3")

@@ -83,7 +83,7 @@ rlbm::FieldPtrs field_ptrs(const rlbm_fields *f) {
 
 // the lattice needs the force / wall build of the step kernel
 int lattice_ext(const rlbm_lattice *h) {
-  if (h->cfg.model.kind != RLBM_QUAD_PRODUCT) return 0;
+  if (h->cfg.model.kind == RLBM_QUAD_UR_ONLATTICE) return 0;
   for (int a = 0; a < h->cfg.model.d; ++a) {
     if (h->cfg.bc[a] == RLBM_WALL) return 1;
     if (h->cfg.force[a] != 0.0 && h->cfg.model.zeta > 0.0) return 1;
@@ -165,8 +165,16 @@ rlbm_status rlbm_create(const rlbm_config *cfg, rlbm_lattice **out) {
     if (cfg->extent[a] < 1 || cfg->extent[a] > (1 << 20)) return fail(RLBM_ERR_INVALID_ARG, "extent out of range");
     if (cfg->bc[a] != RLBM_PERIODIC && cfg->bc[a] != RLBM_OPEN && cfg->bc[a] != RLBM_WALL)
       return fail(RLBM_ERR_INVALID_ARG, "bad bc");
-    if (cfg->bc[a] == RLBM_WALL && m.kind != RLBM_QUAD_PRODUCT)
-      return fail(RLBM_ERR_UNSUPPORTED, "walls are built for product rules");
+    if (cfg->bc[a] == RLBM_WALL && m.kind == RLBM_QUAD_UR_ONLATTICE)
+      return fail(RLBM_ERR_UNSUPPORTED, "walls are built for the product and massive rules");
+    if (cfg->bc[a] == RLBM_WALL && m.kind == RLBM_QUAD_MASSIVE_ONLATTICE && m.d == 3 && cfg->storage == RLBM_F64)
+      return fail(RLBM_ERR_UNSUPPORTED, "walls: the streaming kernel of the 3D massive rule has none");
+    for (int e = 0; e < 2; ++e) {
+      if (!(cfg->wall_T[a][e] >= 0.0) || !std::isfinite(cfg->wall_T[a][e]))
+        return fail(RLBM_ERR_INVALID_ARG, "wall temperatures must be finite and >= 0");
+      if (cfg->wall_T[a][e] != 0.0 && cfg->bc[a] != RLBM_WALL)
+        return fail(RLBM_ERR_INVALID_ARG, "a wall temperature needs a wall axis");
+    }
     if (!std::isfinite(cfg->force[a])) return fail(RLBM_ERR_INVALID_ARG, "force must be finite");
   }
   if (m.d == 3 && m.kind == RLBM_QUAD_UR_ONLATTICE) return fail(RLBM_ERR_UNSUPPORTED, "the printed massless rule is 2D");
@@ -219,6 +227,8 @@ rlbm_status rlbm_create(const rlbm_config *cfg, rlbm_lattice **out) {
       t->gf[a] = (float)t->g[a];
     }
     t->tau_T = cfg->tau_T;
+    for (int a = 0; a < 3; ++a)
+      for (int e = 0; e < 2; ++e) t->wallT[a][e] = a < m.d ? cfg->wall_T[a][e] : 0.0;
     // the force term carries the mass: nothing to add for zeta = 0
     t->has_force = (m.zeta > 0.0 && m.kind == RLBM_QUAD_PRODUCT &&
                     (t->g[0] != 0.0 || t->g[1] != 0.0 || t->g[2] != 0.0)) ? 1 : 0;

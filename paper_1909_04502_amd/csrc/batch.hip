@@ -50,8 +50,7 @@ __global__ void __launch_bounds__(BX * BY) k_step_batch(const Tables *__restrict
     }
     S f[ST::Q];
     pull_prod<ST, S, false>(tb, fi, sites, o, f);
-    const bool wall = EXT && ((tb->wall[0] && (x == 0 || x == nx - 1)) || (tb->wall[1] && (y == 0 || y == ny - 1)));
-    const Macro<ST::D> mac = collide_prod<ST, N, S, DEV, true, EXT>(tb, f, tb->tau, wall);
+    const Macro<ST::D> mac = collide_prod<ST, N, S, DEV, true, EXT>(tb, f, tb->tau, EXT ? site_wall(tb, x, y, 0) : -1.0);
     if (!mac.ok) *(volatile int *)err = 1;
     const uint32_t so = (uint32_t)site * (uint32_t)sizeof(S);
 #pragma unroll

@@ -365,21 +365,16 @@ __device__ __forceinline__ void gather(const Tables *__restrict__ tb, const S *_
   }
 }
 
+// wallT: see site_wall (negative off the walls)
 template <class ST, int N, typename S, bool DEV, bool RELAX, bool EXT = false>
 __device__ __forceinline__ Macro<ST::D> collide_site(const Tables *__restrict__ tb, S (&f)[ST::Q], double tau,
-                                                     bool wall = false) {
+                                                     double wallT = -1.0) {
   if constexpr (ST::ONLAT && ST::SHIFT)
-    return collide_massive<ST, N, S, DEV, RELAX>(tb, f, tau);
+    return collide_massive<ST, N, S, DEV, RELAX, EXT>(tb, f, tau, wallT);
   else if constexpr (ST::ONLAT)
     return collide<ST, N, S, DEV, RELAX>(tb, f, tau);
   else
-    return collide_prod<ST, N, S, DEV, RELAX, EXT>(tb, f, tau, wall);
-}
-
-// the site lies on a no-slip wall plane (first or last plane of a wall axis)
-__device__ __forceinline__ bool on_wall(const Tables *__restrict__ tb, int x, int y, int z) {
-  return (tb->wall[0] && (x == 0 || x == tb->nx - 1)) || (tb->wall[1] && (y == 0 || y == tb->ny - 1)) ||
-         (tb->wall[2] && (z == 0 || z == tb->nz - 1));
+    return collide_prod<ST, N, S, DEV, RELAX, EXT>(tb, f, tau, wallT);
 }
 
 // post-collision store: plane base (uniform) + 32-bit byte offset of the site
@@ -445,7 +440,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(OCC > 
   S f[ST::Q];
   gather<ST, S>(tb, fin, sites, x, y, z, f);
   const double tau = site_tau<S>(tb, tau_field, site);
-  const Macro<ST::D> mac = collide_site<ST, N, S, DEV, true, EXT>(tb, f, tau, EXT && on_wall(tb, x, y, z));
+  const Macro<ST::D> mac = collide_site<ST, N, S, DEV, true, EXT>(tb, f, tau, EXT ? site_wall(tb, x, y, z) : -1.0);
   if (!mac.ok) flag_error(err);
   // a fresh copy of the plane size for the store addresses: otherwise the compiler keeps the
   // load phase's plane offsets alive (in spilled scalar registers) for reuse here
@@ -481,8 +476,8 @@ k_step_stream(const Tables *__restrict__ tb, const S *__restrict__ fin, S *__res
                         oz[R - dir_z<ST>(i)]);
   };
   const double tau = site_tau<S>(tb, tau_field, site);
-  const Macro<ST::D> mac = massive_update<ST, N, S, DEV, true>(
-      tb, tau, [&](int i) { return load(fin, i); }, [&](int i) { return load(fin2, i); },
+  const Macro<ST::D> mac = massive_update<ST, N, S, DEV, true, false>(
+      tb, tau, -1.0, [&](int i) { return load(fin, i); }, [&](int i) { return load(fin2, i); },
       [&](int i, S v) { *(S *)((char *)(fout + (int64_t)i * sites) + site_off) = v; });
   if (!mac.ok) flag_error(err);
   if (last.any) write_fields<ST::D>(last, site, sites, mac);
@@ -563,7 +558,7 @@ __global__ void __launch_bounds__(256) k_init(const Tables *__restrict__ tb, con
 #pragma unroll
   for (int i = 0; i < Q; ++i) f[i] = DEV ? (S)(fd[i] - tb->fref[i]) : (S)fd[i];
   const double tau = site_tau<S>(tb, tau_field, site);
-  const Macro<D> mac = collide_site<ST, N, S, DEV, true, true>(tb, f, tau, on_wall(tb, x, y, z));
+  const Macro<D> mac = collide_site<ST, N, S, DEV, true, true>(tb, f, tau, site_wall(tb, x, y, z));
   if (!mac.ok) flag_error(err);
   store_site<ST, S>(fout, sites, (uint32_t)site * (uint32_t)sizeof(S), f);
   if (fields0.any) write_fields<D>(fields0, site, sites, mac);

@@ -117,9 +117,12 @@ __device__ __forceinline__ void massive_coefficients(const Tables *__restrict__ 
 // register-resident collide passes its array; the streaming kernel loads from
 // memory twice and stores directly, so that no population stays live across
 // the eigen-solve and the projection.
-template <class ST, int N, typename S, bool DEV, bool RELAX, class Fetch, class Refetch, class Put>
-__device__ __forceinline__ Macro<ST::D> massive_update(const Tables *__restrict__ tb, double tau, Fetch &&fetch,
-                                                       Refetch &&refetch, Put &&put) {
+// EXT: no-slip wall planes (site_wall), in a separate instantiation: a wall
+// site takes the equilibrium at rest of its own n and its own or the plane's
+// prescribed temperature (Omega = 1).
+template <class ST, int N, typename S, bool DEV, bool RELAX, bool EXT, class Fetch, class Refetch, class Put>
+__device__ __forceinline__ Macro<ST::D> massive_update(const Tables *__restrict__ tb, double tau, double wallT,
+                                                       Fetch &&fetch, Refetch &&refetch, Put &&put) {
   constexpr int D = ST::D, Q = ST::Q, NG = ST::NG, NT = D * (D + 1) / 2;
   using B = BasisDef<D, N>;
   constexpr AngTable<D, N> AT{};
@@ -230,12 +233,23 @@ __device__ __forceinline__ Macro<ST::D> massive_update(const Tables *__restrict_
   if constexpr (!RELAX) return mac;
   // ---- step 5: a' over the shifted monomials ----
   A ap[B::NM];
-  massive_coefficients<D, N, DEV, A>(tb, mac, rr, ap);
+  const bool wall = EXT && wallT >= 0.0;
+  if (wall) {
+    Macro<D> meq = mac;
+    Ratios req;
+    equilibrium_state<D>(tb, mac, rr, wallT, meq.T, req);
+    meq.U[0] = 1.0;
+#pragma unroll
+    for (int a = 1; a <= D; ++a) meq.U[a] = 0.0;
+    massive_coefficients<D, N, DEV, A>(tb, meq, req, ap);
+  } else {
+    massive_coefficients<D, N, DEV, A>(tb, mac, rr, ap);
+  }
   // ---- step 7: the temperature-dependent part of tau ----
   if (tb->tau_T != 0.0) tau += tb->tau_T / mac.T;
-  // ---- step 8: Omega_i = a0 - v0 (n_i . U)/tau ----
-  const double itau = 1.0 / tau;
-  const A a0 = (A)(mac.U[0] * itau);
+  // ---- step 8: Omega_i = a0 - v0 (n_i . U)/tau (1 on a wall) ----
+  const double itau = wall ? 0.0 : 1.0 / tau;
+  const A a0 = wall ? (A)1 : (A)(mac.U[0] * itau);
   A ub[D];
 #pragma unroll
   for (int a = 0; a < D; ++a) ub[a] = (A)(tb->v0 * mac.U[a + 1] * itau);
@@ -284,10 +298,11 @@ __device__ __forceinline__ Macro<ST::D> massive_update(const Tables *__restrict_
   return mac;
 }
 
-template <class ST, int N, typename S, bool DEV, bool RELAX>
-__device__ __forceinline__ Macro<ST::D> collide_massive(const Tables *__restrict__ tb, S (&f)[ST::Q], double tau) {
+template <class ST, int N, typename S, bool DEV, bool RELAX, bool EXT = false>
+__device__ __forceinline__ Macro<ST::D> collide_massive(const Tables *__restrict__ tb, S (&f)[ST::Q], double tau,
+                                                        double wallT = -1.0) {
   auto get = [&](int i) { return f[i]; };
-  return massive_update<ST, N, S, DEV, RELAX>(tb, tau, get, get, [&](int i, S v) { f[i] = v; });
+  return massive_update<ST, N, S, DEV, RELAX, EXT>(tb, tau, wallT, get, get, [&](int i, S v) { f[i] = v; });
 }
 
 }  // namespace rlbm

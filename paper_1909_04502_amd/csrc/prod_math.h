@@ -172,12 +172,42 @@ __device__ __forceinline__ void pull_prod(const Tables *__restrict__ tb, const S
   }
 }
 
+// Wall temperature of a site: negative off the walls; on the first or last
+// plane of a wall axis the prescribed temperature of that plane, or 0 for the
+// site's own temperature.
+__device__ __forceinline__ double site_wall(const Tables *__restrict__ tb, int x, int y, int z) {
+  if (tb->wall[0] && (x == 0 || x == tb->nx - 1)) return tb->wallT[0][x == 0 ? 0 : 1];
+  if (tb->wall[1] && (y == 0 || y == tb->ny - 1)) return tb->wallT[1][y == 0 ? 0 : 1];
+  if (tb->wall[2] && (z == 0 || z == tb->nz - 1)) return tb->wallT[2][z == 0 ? 0 : 1];
+  return -1.0;
+}
+
+// The temperature and moment ratios the equilibrium is built from: the
+// site's own, or a wall plane's prescribed temperature.
+template <int D>
+__device__ __forceinline__ void equilibrium_state(const Tables *__restrict__ tb, const Macro<D> &mac,
+                                                  const Ratios &rr, double wallT, double &Te, Ratios &re) {
+  Te = mac.T;
+  re = rr;
+  if (wallT > 0.0) {
+    Te = wallT;
+    if constexpr (D == 2) {
+      re = ratios_2d(tb->m / Te);
+    } else {
+      bool inr = true;
+      const double r = tb->m == 0.0 ? 0.0 : cheb_r(tb, tb->m / Te, inr);
+      re = ratios_3d(tb->m / Te, r);
+    }
+  }
+}
+
 // EXT: build the external-force term and the no-slip wall sites in (a separate
 // instantiation, so that lattices without them keep the leaner kernel).
+// wallT: see site_wall.
 template <class ST, int N, typename S, bool DEV, bool RELAX, bool EXT = false>
 __device__ __forceinline__ Macro<ST::D> collide_prod(const Tables *__restrict__ tb, S (&f)[ST::Q], double tau,
-                                                     bool wall_site = false) {
-  const bool wall = EXT && wall_site;
+                                                     double wallT = -1.0) {
+  const bool wall = EXT && wallT >= 0.0;
   constexpr int D = ST::D, ND = ST::NDIR, NPD = ND / 2, KR = ST::NSHELL;
   using B = BasisDef<D, N>;
   constexpr AngTable<D, N> AT{};
@@ -279,10 +309,14 @@ __device__ __forceinline__ Macro<ST::D> collide_prod(const Tables *__restrict__ 
   }
   mac.ok = mac.ok && mac.n > 0.0 && mac.eps > 0.0;
   if constexpr (!RELAX) return mac;
-  // a no-slip wall site relaxes fully (Omega = 1) to the equilibrium at rest of its own n, T
+  // a no-slip wall site relaxes fully (Omega = 1) to the equilibrium at rest of its own n and
+  // its own or the wall's prescribed T
   double Ue[D + 1];
 #pragma unroll
   for (int a = 0; a <= D; ++a) Ue[a] = wall ? (a == 0 ? 1.0 : 0.0) : mac.U[a];
+  double Te = mac.T;
+  Ratios re = rr;
+  if (wall) equilibrium_state<D>(tb, mac, rr, wallT, Te, re);
   // ---- step 5: a' = G^{-1} M over parity blocks ----
   A ap[B::NM];
   if constexpr (D == 3) {
@@ -302,7 +336,7 @@ __device__ __forceinline__ Macro<ST::D> collide_prod(const Tables *__restrict__ 
 #pragma unroll
       for (int t = 0; t < CL.cnt[c]; ++t) {
         const int k = CL.idx[c][t];
-        mc[t] = basis_moment<D, N>(k, mac.n, mac.T, Ue, rr);
+        mc[t] = basis_moment<D, N>(k, mac.n, Te, Ue, re);
         if constexpr (DEV) mc[t] -= tb->Mref[k];
       }
       // moments of the shifted monomials (p^0 - m) p^e = p^0 p^e - m p^e
@@ -331,7 +365,7 @@ __device__ __forceinline__ Macro<ST::D> collide_prod(const Tables *__restrict__ 
     }
   } else {
     double Md[B::NM];
-    basis_moments<D, N>(mac.n, mac.T, Ue, rr, Md);
+    basis_moments<D, N>(mac.n, Te, Ue, re, Md);
     if constexpr (DEV) {
 #pragma unroll
       for (int k = 0; k < B::NM; ++k) Md[k] -= tb->Mref[k];

@@ -296,6 +296,7 @@ struct Tables {
   double wrest, v0;             // rest weight, lattice-speed parameter
   float wrestf, v0f;
   double tau_T;                 // on-lattice rules: tau(x) += tau_T / T(x) (0 = off)
+  double wallT[3][2];           // prescribed temperature of the first / last plane of a wall axis (0 = own)
   float Ref[kMaxPairs][kMaxNE]; // float copies for the F32_DEV path
   float Rof[kMaxPairs][kMaxNO];
   float cf[kMaxPairs][3];

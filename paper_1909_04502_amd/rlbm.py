@@ -30,7 +30,7 @@ class Model(Structure):
 class Config(Structure):
     _fields_ = [("model", Model), ("extent", c_int64 * 3), ("bc", c_int32 * 3), ("storage", c_int32),
                 ("tau", c_double), ("tau_field", c_void_p), ("n_ref", c_double), ("force", c_double * 3),
-                ("tau_T", c_double)]
+                ("tau_T", c_double), ("wall_T", (c_double * 2) * 3)]
 
 
 class Info(Structure):
@@ -187,7 +187,8 @@ class Lattice:
     """One lattice: handle of the C ABI plus the torch-side shapes."""
 
     def __init__(self, d=2, zeta=1.0, order=3, kind="product", extent=(64, 64), bc=None, storage="f64",
-                 tau=0.8, tau_field=None, n_ref=1.0, force=None, v0=0.0, tau_T=0.0, _handle=None):
+                 tau=0.8, tau_field=None, n_ref=1.0, force=None, v0=0.0, tau_T=0.0, wall_T=None,
+                 _handle=None):
         L = lib()
         self._owned = _handle is None
         self.d = d
@@ -212,6 +213,9 @@ class Lattice:
         cfg.tau_field = tau_field.data_ptr() if tau_field is not None else None
         cfg.n_ref = float(n_ref)
         cfg.tau_T = float(tau_T)
+        if wall_T is not None:          # per axis (first plane, last plane); 0 = own temperature
+            for a, pair in enumerate(wall_T):
+                cfg.wall_T[a][0], cfg.wall_T[a][1] = float(pair[0]), float(pair[1])
         self.force = tuple(float(g) for g in force) if force is not None else (0.0,) * d
         for a in range(3):
             cfg.force[a] = self.force[a] if a < len(self.force) else 0.0

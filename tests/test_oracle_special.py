@@ -173,3 +173,23 @@ def test_bickley_against_mpmath():
     for x in (0.5, 1.6, 4.0):
         ref = mpmath.quad(lambda t: mpmath.exp(-x * mpmath.cosh(t)) / mpmath.cosh(t), [0, 2, 4, 8])
         assert mj.bickley_ki1(x) == pytest.approx(float(ref), rel=1e-12)
+
+
+@pytest.mark.parametrize("d", [2, 3])
+def test_ce_conductivity_and_bulk_viscosity(d):
+    """App. C: the explicit lambda forms equal the general lambda = n tau G (chi G - 1) with chi from
+    a_43 = (G - zeta^2 chi)/(d + 2) = eta / (P tau) (the pinned shear coefficient); the explicit d = 2
+    bulk form equals the general mu = P tau [a_43 (1 + 2/d) - X/(X - 1)], X = zeta^2 - G^2 + (d+2) G;
+    the massless limits lambda -> (d + 1)/d n tau and mu -> 0; mu > 0 for massive particles."""
+    for z in (0.3, 1.0, 2.5, 5.0):
+        G = float(mj.G_d(z, d))
+        a43 = mj.ce_shear_ratio(z, d)
+        chi = (G - (d + 2) * a43) / (z * z)
+        assert mj.ce_conductivity_ratio(z, d) == pytest.approx(G * (chi * G - 1.0), rel=1e-11)
+        X = z * z - G * G + (d + 2) * G
+        general = a43 * (1.0 + 2.0 / d) - X / (X - 1.0)
+        assert mj.ce_bulk_ratio(z, d) == pytest.approx(general, rel=1e-9)
+        assert mj.ce_bulk_ratio(z, d) > 0
+    assert mj.ce_conductivity_ratio(0.0, d) == pytest.approx((d + 1) / d, rel=1e-14)
+    assert mj.ce_conductivity_ratio(1e-4, d) == pytest.approx((d + 1) / d, rel=1e-3)
+    assert mj.ce_bulk_ratio(1e-3, d) < 1e-5
