@@ -35,95 +35,6 @@ __device__ __forceinline__ int wrap_or_clamp(int v, int n, int open) {
   return v >= n ? v - n : v;
 }
 
-// Coordinates of the upstream neighbours -1, 0, +1 along each axis.
-struct Nbr {
-  int x[3], y[3], z[3];
-};
-
-template <class ST>
-__device__ __forceinline__ Nbr make_nbr(const Tables *__restrict__ tb, int x, int y, int z) {
-  Nbr nb;
-#pragma unroll
-  for (int o = -1; o <= 1; ++o) {
-    nb.x[o + 1] = wrap_or_clamp(x + o, tb->nx, tb->open[0]);
-    nb.y[o + 1] = wrap_or_clamp(y + o, tb->ny, tb->open[1]);
-    nb.z[o + 1] = ST::D == 3 ? wrap_or_clamp(z + o, tb->nz, tb->open[2]) : 0;
-  }
-  return nb;
-}
-
-template <typename S>
-struct Acc;
-template <>
-struct Acc<double> {
-  typedef double T;
-};
-template <>
-struct Acc<float> {
-  typedef float T;
-};
-
-// Pre-collision value of population I at the site (pull from post-collision planes).
-template <class ST, int I, typename S>
-__device__ __forceinline__ S pull(const Tables *__restrict__ tb, const S *__restrict__ f, int64_t sites,
-                                  const Nbr &nb, int x, int y, int z) {
-  const S *plane = f + (int64_t)I * sites;
-  const int nx = tb->nx, ny = tb->ny;
-  if constexpr (ST::ONLAT) {
-    constexpr int dx = ST::dir(I, 0), dy = ST::dir(I, 1);
-    const int sx = dx == 0 ? x : wrap_or_clamp(x - dx, nx, tb->open[0]);
-    const int sy = dy == 0 ? y : wrap_or_clamp(y - dy, ny, tb->open[1]);
-    return plane[(int64_t)sy * nx + sx];
-  } else {
-    constexpr int dx = ST::dir(I, 0), dy = ST::dir(I, 1);
-    constexpr int dz = ST::D == 3 ? ST::dir(I, ST::D - 1) : 0;
-    constexpr int nzc = (dx != 0) + (dy != 0) + (dz != 0);
-    S acc = 0;
-#pragma unroll
-    for (int tap = 0; tap < (1 << nzc); ++tap) {
-      int bit = 0, ox = 0, oy = 0, oz = 0;
-      if (dx != 0) {
-        const int c = (tap >> bit++) & 1;
-        ox = dx > 0 ? (c ? 0 : -1) : (c ? 1 : 0);
-      }
-      if (dy != 0) {
-        const int c = (tap >> bit++) & 1;
-        oy = dy > 0 ? (c ? 0 : -1) : (c ? 1 : 0);
-      }
-      if (dz != 0) {
-        const int c = (tap >> bit++) & 1;
-        oz = dz > 0 ? (c ? 0 : -1) : (c ? 1 : 0);
-      }
-      const int64_t idx = ((int64_t)nb.z[oz + 1] * ny + nb.y[oy + 1]) * nx + nb.x[ox + 1];
-      S wgt;
-      if constexpr (sizeof(S) == 8)
-        wgt = tb->tapw[I][tap];
-      else
-        wgt = tb->tapwf[I][tap];
-      acc += wgt * plane[idx];
-    }
-    return acc;
-  }
-}
-
-template <class ST, typename S, int... I>
-__device__ __forceinline__ void pull_all_impl(const Tables *__restrict__ tb, const S *__restrict__ f, int64_t sites,
-                                              const Nbr &nb, int x, int y, int z, S (&v)[ST::Q],
-                                              std::integer_sequence<int, I...>) {
-  ((v[I] = pull<ST, I, S>(tb, f, sites, nb, x, y, z)), ...);
-}
-
-template <class ST, typename S>
-__device__ __forceinline__ void pull_all(const Tables *__restrict__ tb, const S *__restrict__ f, int64_t sites,
-                                         const Nbr &nb, int x, int y, int z, S (&v)[ST::Q]) {
-  pull_all_impl<ST, S>(tb, f, sites, nb, x, y, z, v, std::make_integer_sequence<int, ST::Q>{});
-}
-
-// ---------------------------------------------------------------------------
-// Collision of one site: f (pre-collision, storage precision; deviations in
-// the F32_DEV mode) is replaced by f* in place.  Returns the macro state of
-// the pre-collision populations.
-// ---------------------------------------------------------------------------
 // Moments of the shifted monomials (p^0 - m) p^e = p^0 p^e - m p^e, in place
 // (stencils whose projection rows act on the shifted basis).
 template <int D, int N>
@@ -132,145 +43,6 @@ __device__ __forceinline__ void shift_basis_moments(double m, double (&M)[BasisD
 #pragma unroll
   for (int k = 0; k < BasisDef<D, N>::NM; ++k)
     if (CL.partner[k] >= 0) M[k] -= m * M[CL.partner[k]];
-}
-
-// Stencils with an odd population count carry a rest population (p = (m, 0))
-// as their last one; it has no partner, feeds only N^0 and T^00, and relaxes
-// with Omega = U^0 / tau towards the even part of the equilibrium.
-template <class ST, int N, typename S, bool DEV, bool RELAX>
-__device__ __forceinline__ Macro<ST::D> collide(const Tables *__restrict__ tb, S (&f)[ST::Q], double tau) {
-  constexpr int D = ST::D, Q = ST::Q, NP = Q / 2;
-  constexpr bool REST = (Q & 1) != 0;
-  using B = BasisDef<D, N>;
-  constexpr int NE = B::NE, NO = B::NO;
-  typedef typename Acc<S>::T A;
-  // ---- step 1: moments (pairs: s = f_i + f_i', d = f_i - f_i') ----
-  A me[2 + D * (D + 1) / 2];   // N^0, T^00, T^ab (a <= b spatial)
-  A mo[2 * D];                 // N^a, T^0a
-#pragma unroll
-  for (int k = 0; k < 2 + D * (D + 1) / 2; ++k) me[k] = 0;
-#pragma unroll
-  for (int k = 0; k < 2 * D; ++k) mo[k] = 0;
-#pragma unroll
-  for (int pr = 0; pr < NP; ++pr) {
-    const A s = (A)f[2 * pr] + (A)f[2 * pr + 1];
-    const A d = (A)f[2 * pr] - (A)f[2 * pr + 1];
-#pragma unroll
-    for (int k = 0; k < 2 + D * (D + 1) / 2; ++k) {
-      if constexpr (sizeof(A) == 8) me[k] += (A)tb->mom_e[pr][k] * s;
-      else me[k] += tb->mom_ef[pr][k] * s;
-    }
-#pragma unroll
-    for (int k = 0; k < 2 * D; ++k) {
-      if constexpr (sizeof(A) == 8) mo[k] += (A)tb->mom_o[pr][k] * d;
-      else mo[k] += tb->mom_of[pr][k] * d;
-    }
-  }
-  if constexpr (REST) {
-    const A mr = (A)tb->m, s = (A)f[Q - 1];
-    me[0] += mr * s;
-    me[1] += mr * mr * s;
-  }
-  double Nv[D + 1], T[D + 1][D + 1];
-  Nv[0] = (double)me[0];
-  T[0][0] = (double)me[1];
-  {
-    int e = 2;
-#pragma unroll
-    for (int a = 1; a <= D; ++a)
-#pragma unroll
-      for (int b = a; b <= D; ++b) {
-        T[a][b] = T[b][a] = (double)me[e];
-        ++e;
-      }
-  }
-#pragma unroll
-  for (int a = 1; a <= D; ++a) {
-    Nv[a] = (double)mo[a - 1];
-    T[0][a] = T[a][0] = (double)mo[D + a - 1];
-  }
-  if constexpr (DEV) {
-    int s = 0;
-#pragma unroll
-    for (int a = 0; a <= D; ++a) {
-      Nv[a] += tb->Nref[a];
-#pragma unroll
-      for (int b = a; b <= D; ++b) {
-        T[a][b] += tb->Tref[s];
-        if (a != b) T[b][a] = T[a][b];
-        ++s;
-      }
-    }
-  }
-  // ---- steps 2-4 ----
-  Macro<D> mac;
-  mac.ok = landau_frame<D, 3>(T, mac.eps, mac.U);
-  mac.n = lorentz_dot<D>(mac.U, Nv);
-  const double m = tb->m;
-  Ratios rr;
-  if constexpr (D == 2) {
-    mac.ok = temperature_2d(mac.eps / mac.n, m, mac.T) && mac.ok;
-    rr = ratios_2d(m / mac.T);
-  } else {
-    double r;
-    mac.ok = temperature_3d(tb, mac.eps / mac.n, m, mac.T, r) && mac.ok;
-    rr = ratios_3d(m / mac.T, r);
-  }
-  mac.ok = mac.ok && mac.n > 0.0 && mac.eps > 0.0;
-  if constexpr (!RELAX) return mac;
-  // ---- step 5: equilibrium moments (deviation from the reference in F32_DEV) ----
-  double Md[B::NM];
-  basis_moments<D, N>(mac.n, mac.T, mac.U, rr, Md);
-  if constexpr (DEV) {
-#pragma unroll
-    for (int k = 0; k < B::NM; ++k) Md[k] -= tb->Mref[k];
-  }
-  if constexpr (ST::SHIFT) shift_basis_moments<D, N>(m, Md);
-  A M[B::NM];
-#pragma unroll
-  for (int k = 0; k < B::NM; ++k) M[k] = (A)Md[k];
-  // ---- step 7: the temperature-dependent part of tau ----
-  if (tb->tau_T != 0.0) tau += tb->tau_T / mac.T;
-  // ---- step 8: Omega_i = (U^0 - c_i . U)/tau; f* = f + Omega (f^eq - f) ----
-  const double itau = 1.0 / tau;
-  const A a0 = (A)(mac.U[0] * itau);
-  A ub[D];
-#pragma unroll
-  for (int a = 0; a < D; ++a) ub[a] = (A)(mac.U[a + 1] * itau);
-#pragma unroll
-  for (int pr = 0; pr < NP; ++pr) {
-    A E = 0, O = 0, cb = 0;
-#pragma unroll
-    for (int k = 0; k < NE; ++k) {
-      if constexpr (sizeof(A) == 8) E += (A)tb->Re[pr][k] * M[k];
-      else E += tb->Ref[pr][k] * M[k];
-    }
-#pragma unroll
-    for (int k = 0; k < NO; ++k) {
-      if constexpr (sizeof(A) == 8) O += (A)tb->Ro[pr][k] * M[NE + k];
-      else O += tb->Rof[pr][k] * M[NE + k];
-    }
-#pragma unroll
-    for (int a = 0; a < D; ++a) {
-      if constexpr (sizeof(A) == 8) cb += (A)tb->c[pr][a] * ub[a];
-      else cb += tb->cf[pr][a] * ub[a];
-    }
-    const A om0 = a0 - cb, om1 = a0 + cb;
-    const A f0 = (A)f[2 * pr], f1 = (A)f[2 * pr + 1];
-    f[2 * pr] = (S)(f0 + om0 * ((E + O) - f0));
-    f[2 * pr + 1] = (S)(f1 + om1 * ((E - O) - f1));
-  }
-  if constexpr (REST) {
-    A E = 0;
-#pragma unroll
-    for (int k = 0; k < NE; ++k) {
-      if constexpr (sizeof(A) == 8) E += (A)tb->Rrest[k] * M[k];
-      else E += tb->Rrestf[k] * M[k];
-    }
-    const A fr = (A)f[Q - 1];
-    f[Q - 1] = (S)(fr + a0 * (E - fr));
-  }
-  return mac;
 }
 
 template <int D>
@@ -365,14 +137,14 @@ __device__ __forceinline__ void gather(const Tables *__restrict__ tb, const S *_
   }
 }
 
-// wallT: see site_wall (negative off the walls)
+// Collision of one site: f (pre-collision, storage precision; deviations in
+// the F32_DEV mode) is replaced by f* in place; returns the macro state of the
+// pre-collision populations.  wallT: see site_wall (negative off the walls).
 template <class ST, int N, typename S, bool DEV, bool RELAX, bool EXT = false>
 __device__ __forceinline__ Macro<ST::D> collide_site(const Tables *__restrict__ tb, S (&f)[ST::Q], double tau,
                                                      double wallT = -1.0) {
-  if constexpr (ST::ONLAT && ST::SHIFT)
+  if constexpr (ST::ONLAT)
     return collide_massive<ST, N, S, DEV, RELAX, EXT>(tb, f, tau, wallT);
-  else if constexpr (ST::ONLAT)
-    return collide<ST, N, S, DEV, RELAX>(tb, f, tau);
   else
     return collide_prod<ST, N, S, DEV, RELAX, EXT>(tb, f, tau, wallT);
 }

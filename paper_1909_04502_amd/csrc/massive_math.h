@@ -1,9 +1,11 @@
-// massive_math.h -- collide for the massive on-lattice rules (HIP device code).
+// massive_math.h -- collide for the on-lattice rules (HIP device code).
 //
-// A massive on-lattice rule (Sec. 5.3) is a union of full-symmetric groups of
-// integer vectors n; the members of group g share the energy p0_g and the
-// weight w_g, and p = (p0_g, v_g n) with v_g = v0 p0_g.  The integer vectors
-// are compile-time constants, so the update needs only a few scalars per group:
+// An on-lattice rule (Sec. 5.3) is a union of groups of integer vectors n whose
+// members share the energy p0_g and the weight w_g, with p = (p0_g, v_g n):
+// for the massive rules the full-symmetric groups of the stencil, v_g = v0 p0_g
+// (plus a rest vector); for the printed massless rules each (energy shell,
+// full-symmetric group) pair, v_g = p0_g / |n|.  The integer vectors are
+// compile-time constants, so the update needs only a few scalars per group:
 //  * moments: per group, S = sum f, D^a = sum n^a f, S^ab = sum n^a n^b f
 //    (antipodal pairs give sums and differences; the integer factors are
 //    literals), then N^0 = sum_g p0 S, N^a = sum_g v D^a, T^00 = sum_g p0^2 S,
@@ -124,6 +126,7 @@ template <class ST, int N, typename S, bool DEV, bool RELAX, bool EXT, class Fet
 __device__ __forceinline__ Macro<ST::D> massive_update(const Tables *__restrict__ tb, double tau, double wallT,
                                                        Fetch &&fetch, Refetch &&refetch, Put &&put) {
   constexpr int D = ST::D, Q = ST::Q, NG = ST::NG, NT = D * (D + 1) / 2;
+  constexpr bool REST = (Q & 1) != 0;   // an odd count carries a rest population, the last one
   using B = BasisDef<D, N>;
   constexpr AngTable<D, N> AT{};
   typedef S A;
@@ -180,7 +183,7 @@ __device__ __forceinline__ Macro<ST::D> massive_update(const Tables *__restrict_
 #pragma unroll
     for (int a = 0; a < NT; ++a) Tab[a] += vv * Sab[a];
   }
-  {
+  if constexpr (REST) {
     const double m = tb->m;
     const A fr = fetch(Q - 1);
     N0 += (A)m * fr;
@@ -290,7 +293,7 @@ __device__ __forceinline__ Macro<ST::D> massive_update(const Tables *__restrict_
       put(i + 1, f1 + om1 * ((E - O) - f1));
     }
   }
-  {
+  if constexpr (REST) {
     const A E = ap[0] * tab<A>(tb->wrest, tb->wrestf);   // the constant monomial is basis entry 0
     const A fr = refetch(Q - 1);
     put(Q - 1, fr + a0 * (E - fr));

@@ -176,6 +176,13 @@ int build_quadrature(int d, double m, int order, int kind, double v0, QuadHost &
       q.w.push_back(wj);
       q.disp.insert(q.disp.end(), {nx, ny});
     }
+    // groups of equal energy and weight (the (+-3,+-4) and (+-5,0) directions of each shell)
+    for (int i = 0; i < q.Q; ++i) {
+      const int j = order == 2 ? kURShell[i] : ur3_shell(i), k = order == 2 ? kURDir[i] : ur3_dir(i);
+      const int jp = i ? (order == 2 ? kURShell[i - 1] : ur3_shell(i - 1)) : -1;
+      const int kp = i ? (order == 2 ? kURDir[i - 1] : ur3_dir(i - 1)) : -1;
+      if (i == 0 || j != jp || (k >= 8) != (kp >= 8)) q.gfirst.push_back(i);
+    }
     return 0;
   }
   if (kind != RLBM_QUAD_PRODUCT) {
@@ -608,12 +615,12 @@ int build_tables(const QuadHost &q, double tau, double n_ref, int storage, const
       }
     }
   }
-  // Product and massive on-lattice rules evaluate the equilibrium as
+  // The kernels evaluate the equilibrium as
   // f^eq_i = w_i psi(p_i)^T G'^{-1} M' over the shifted monomials
   // psi = (p^0 - m)^a p^e (M' the matching moments).  With the kinetic energy
   // p^0 - m instead of p^0 the Gram matrix stays well conditioned for large m
   // (1 and p^0 are nearly collinear over the shells when m >> 1).
-  if (q.kind != RLBM_QUAD_UR_ONLATTICE) {
+  {
     std::vector<ld> Ps(Q * NM);
     for (int i = 0; i < Q; ++i)
       for (int k = 0; k < NM; ++k) {
@@ -661,15 +668,17 @@ int build_tables(const QuadHost &q, double tau, double n_ref, int storage, const
       else pack_linv<3, 3>(t);
     }
   }
-  if (q.kind == RLBM_QUAD_MASSIVE_ONLATTICE) {
-    // group factors: p = (p0, v n) with v = v0 p0 for every member n of a group
+  if (!q.gfirst.empty()) {
+    // group factors: p = (p0, v n) with v = v0 p0 for every member n of a group (v0 = 1/|n| = 1/5
+    // for the printed massless rules)
+    const double v0 = q.kind == RLBM_QUAD_UR_ONLATTICE ? 0.2 : q.v0;
     if ((int)q.gfirst.size() > kMaxMassiveGroups) {
       err = "internal: too many groups";
       return RLBM_ERR_UNSUPPORTED;
     }
     for (size_t g = 0; g < q.gfirst.size(); ++g) {
       const int i = q.gfirst[g];
-      const ld p0 = (ld)q.p[i * D1], v = (ld)q.v0 * p0, w = (ld)q.w[i], dl = p0 - (ld)q.m;
+      const ld p0 = (ld)q.p[i * D1], v = (ld)v0 * p0, w = (ld)q.w[i], dl = p0 - (ld)q.m;
       ld f[13] = {p0, p0 * p0, v, p0 * v, v * v};
       ld vl = 1.0L;
       for (int l = 0; l < 4; ++l) {
@@ -682,10 +691,10 @@ int build_tables(const QuadHost &q, double tau, double n_ref, int storage, const
         t.mgrpf[g][k] = (float)f[k];
       }
     }
-    t.wrest = q.w[Q - 1];
+    t.wrest = rest ? q.w[Q - 1] : 0.0;
     t.wrestf = (float)t.wrest;
-    t.v0 = q.v0;
-    t.v0f = (float)q.v0;
+    t.v0 = v0;
+    t.v0f = (float)v0;
   }
   if (q.kind == RLBM_QUAD_PRODUCT) {
     // shell factors: the radial weight W_j is w_i / (direction weight)

@@ -150,12 +150,20 @@ struct Stencil<ST_PROD3D, KR> {
   RLBM_HD static constexpr int dir(int i, int a) { return kDir3D[i % 26][a]; }
 };
 
+// Groups of equal energy and weight of the printed massless rules: the
+// (+-3,+-4) directions (eight) and the (+-5,0) directions (four) of each shell.
+constexpr int kURGroups2 = 4;
+constexpr int kURFirst2[kURGroups2] = {0, 8, 16, 24};
+constexpr int kURCount2[kURGroups2] = {8, 8, 8, 4};
+
 template <>
 struct Stencil<ST_UR2D, 3> {
-  static constexpr int D = 2, NDIR = 12, Q = kUR2DQ, NSHELL = 3, RMAX = 5;
+  static constexpr int D = 2, NDIR = 12, Q = kUR2DQ, NSHELL = 3, RMAX = 5, NG = kURGroups2;
   static constexpr bool ONLAT = true, SHIFT = false;
   // integer displacement of population i (sites per step)
   RLBM_HD static constexpr int dir(int i, int a) { return kDirUR[kURDir[i]][a]; }
+  RLBM_HD static constexpr int gfirst(int g) { return kURFirst2[g]; }
+  RLBM_HD static constexpr int gcount(int g) { return kURCount2[g]; }
 };
 
 // Printed massless (2+1)-d order-3 rule (App. H.2): the same 12 directions on
@@ -166,11 +174,17 @@ constexpr int kUR3Q = 44;
 RLBM_HD constexpr int ur3_shell(int i) { return i < 8 ? 0 : 1 + (i - 8) / 12; }
 RLBM_HD constexpr int ur3_dir(int i) { return i < 8 ? i : (i - 8) % 12; }
 
+constexpr int kURGroups3 = 7;
+constexpr int kURFirst3[kURGroups3] = {0, 8, 16, 20, 28, 32, 40};
+constexpr int kURCount3[kURGroups3] = {8, 8, 4, 8, 4, 8, 4};
+
 template <>
 struct Stencil<ST_UR2D, 4> {
-  static constexpr int D = 2, NDIR = 12, Q = kUR3Q, NSHELL = 4, RMAX = 5;
+  static constexpr int D = 2, NDIR = 12, Q = kUR3Q, NSHELL = 4, RMAX = 5, NG = kURGroups3;
   static constexpr bool ONLAT = true, SHIFT = false;
   RLBM_HD static constexpr int dir(int i, int a) { return kDirUR[ur3_dir(i)][a]; }
+  RLBM_HD static constexpr int gfirst(int g) { return kURFirst3[g]; }
+  RLBM_HD static constexpr int gcount(int g) { return kURCount3[g]; }
 };
 
 // Massive on-lattice rules (d = 2: Q = 29 for N = 2, 45 for N = 3; d = 3: Q =
@@ -289,11 +303,11 @@ struct Tables {
   double Ro[kMaxPairs][kMaxNO]; // projection rows, odd basis part
   double Rrest[kMaxNE];         // projection row of a rest population (p = (m, 0)), even part
   float Rrestf[kMaxNE];
-  // massive on-lattice rules, per group g (p = (p0, v n), v = v0 p0, weight w, D = p0 - m):
+  // on-lattice rules, per group g (p = (p0, v n), v = v0 p0, weight w, D = p0 - m):
   // p0, p0^2, v, p0 v, v^2, w v^l (l = 0..3), w D v^l (l = 0..3)
   double mgrp[kMaxMassiveGroups][13];
   float mgrpf[kMaxMassiveGroups][13];
-  double wrest, v0;             // rest weight, lattice-speed parameter
+  double wrest, v0;             // rest weight, lattice-speed parameter (1/5 for the printed massless rules)
   float wrestf, v0f;
   double tau_T;                 // on-lattice rules: tau(x) += tau_T / T(x) (0 = off)
   double wallT[3][2];           // prescribed temperature of the first / last plane of a wall axis (0 = own)
