@@ -45,7 +45,18 @@ def parse():
     ap.add_argument("--no-onlattice", action="store_true")
     ap.add_argument("--no-forcing", action="store_true")
     ap.add_argument("--size-3d", type=int, default=256)
-    return ap.parse_args()
+    ap.add_argument("--only", default=None,
+                    help="run the headline and this one optional leg (onlattice_ur, massive_onlattice, sod_ur, "
+                         "calibrations, forcing_walls, shock_tube_3d, adjoint, batched, variants)")
+    a = ap.parse_args()
+    if a.only is not None:
+        a.no_variants = a.only != "variants"
+        a.no_adjoint = a.only != "adjoint"
+        a.no_3d = a.only != "shock_tube_3d"
+        a.no_batch = a.only != "batched"
+        a.no_forcing = a.only != "forcing_walls"
+        a.no_onlattice = a.only not in ("onlattice_ur", "massive_onlattice", "sod_ur", "calibrations")
+    return a
 
 
 def time_steps(lat, fa, fb, warmup, steps):
@@ -543,10 +554,15 @@ def main():
         out["batched_f32dev"] = batched(args.batch_count, max(2, args.warmup // 4), max(4, args.steps // 10),
                                         "f32dev")
     if not args.no_onlattice:
-        out["onlattice_ur"] = onlattice_leg(args.warmup, args.steps)
-        out["massive_onlattice"] = massive_leg(args.warmup, args.steps)
-        out["sod_ur"] = sod_leg(args.warmup, args.steps)
-        out["calibrations"] = calibration_leg()
+        want = (lambda name: args.only in (None, name))
+        if want("onlattice_ur"):
+            out["onlattice_ur"] = onlattice_leg(args.warmup, args.steps)
+        if want("massive_onlattice"):
+            out["massive_onlattice"] = massive_leg(args.warmup, args.steps)
+        if want("sod_ur"):
+            out["sod_ur"] = sod_leg(args.warmup, args.steps)
+        if want("calibrations"):
+            out["calibrations"] = calibration_leg()
     if not args.no_forcing:
         out["forcing_walls"] = forcing_leg(L, args.warmup, args.steps)
     if not args.no_copy:

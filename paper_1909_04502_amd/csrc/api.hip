@@ -199,8 +199,10 @@ rlbm_status rlbm_create(const rlbm_config *cfg, rlbm_lattice **out) {
   h->stencil = stencil_of(m);
   // default launch shapes (from autotuning sweeps on MI355X): 3D keeps ~100 populations in
   // registers and takes the occupancy-2 build in untiled order; 2D product rules in double take
-  // rows of 64 sites; the 2D on-lattice rules 64 x 4 tiles of the occupancy-2 build
-  if (m.d == 3) h->variant = 2;
+  // rows of 64 sites; the 2D on-lattice rules 64 x 4 tiles of the occupancy-2 build; the 3D
+  // massive rule 64 x 2 XCD-ordered tiles (double, streaming kernel) or 64 x 1 patches (float)
+  if (m.d == 3 && m.kind == RLBM_QUAD_MASSIVE_ONLATTICE) h->variant = cfg->storage == RLBM_F64 ? 4 : 8;
+  else if (m.d == 3) h->variant = 2;
   else if (m.kind == RLBM_QUAD_PRODUCT && cfg->storage == RLBM_F64) h->variant = 5;
   else if (m.kind != RLBM_QUAD_PRODUCT) h->variant = 3;   // on-lattice 2D: 64 x 4, occupancy-2 build
   h->sites = sites;

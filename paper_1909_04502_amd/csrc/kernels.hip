@@ -224,9 +224,10 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(OCC > 
 
 // Massive rules whose populations do not fit in registers (the 143-vector 3D
 // stencil in double storage): every population is loaded once for the
-// moments, loaded again (normally from the caches) for the relaxation, and
-// stored at once, so that none stays live across the eigen-solve and the
-// projection.
+// moments; the first kStreamKeep of them stay in registers, the others are
+// loaded again (from the caches or memory) for the relaxation; every result is
+// stored at once.  Keeping about a third of them balances the re-read traffic
+// against the registers the eigen-solve and the projection need.
 template <class ST, int N, typename S, bool DEV, int OCC>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(OCC > 0 ? OCC : 1, 8)))
 k_step_stream(const Tables *__restrict__ tb, const S *__restrict__ fin, S *__restrict__ fout,
@@ -248,8 +249,16 @@ k_step_stream(const Tables *__restrict__ tb, const S *__restrict__ fin, S *__res
                         oz[R - dir_z<ST>(i)]);
   };
   const double tau = site_tau<S>(tb, tau_field, site);
+  constexpr int kStreamKeep = 48;
+  S keep[kStreamKeep];
   const Macro<ST::D> mac = massive_update<ST, N, S, DEV, true, false>(
-      tb, tau, -1.0, [&](int i) { return load(fin, i); }, [&](int i) { return load(fin2, i); },
+      tb, tau, -1.0,
+      [&](int i) {
+        const S v = load(fin, i);
+        if (i < kStreamKeep) keep[i < kStreamKeep ? i : 0] = v;
+        return v;
+      },
+      [&](int i) { return i < kStreamKeep ? keep[i < kStreamKeep ? i : 0] : load(fin2, i); },
       [&](int i, S v) { *(S *)((char *)(fout + (int64_t)i * sites) + site_off) = v; });
   if (!mac.ok) flag_error(err);
   if (last.any) write_fields<ST::D>(last, site, sites, mac);
