@@ -298,6 +298,30 @@ rlbm_status rlbm_set_variant(rlbm_lattice *h, int32_t variant);
 rlbm_status rlbm_get_variant(const rlbm_lattice *h, int32_t *variant);
 rlbm_status rlbm_autotune(rlbm_lattice *h, int32_t steps, float *ms_out, hipStream_t stream);
 
+/* How rlbm_step writes the post-collision populations (results do not depend
+ * on it).  RLBM_STORES_AUTO (the default) uses non-temporal stores, which are
+ * not kept in the L2 or the 256 MiB last-level cache, when the two state
+ * buffers together (2 Q sites x element size) exceed 384 MiB, so that the
+ * next step reads nearly all populations from memory anyway, and a row of
+ * sites (extent[0] x element size) is a multiple of 64 bytes (with ragged
+ * rows they were measured slower).  Otherwise ordinary stores are kept, and
+ * smaller lattices find the populations in the cache on the next step.
+ * RLBM_STORES_CACHED and RLBM_STORES_NONTEMPORAL force one kind.
+ * rlbm_get_store_mode returns the mode and (nontemporal, may be NULL)
+ * whether rlbm_step uses non-temporal stores for this lattice; an unknown
+ * mode is RLBM_ERR_INVALID_ARG. */
+typedef enum {
+  RLBM_STORES_AUTO = 0,
+  RLBM_STORES_CACHED = 1,
+  RLBM_STORES_NONTEMPORAL = 2
+} rlbm_store_mode;
+rlbm_status rlbm_set_store_mode(rlbm_lattice *h, int32_t mode);
+rlbm_status rlbm_get_store_mode(const rlbm_lattice *h, int32_t *mode, int32_t *nontemporal);
+/* The same for the batched step: the footprint is that of the whole batch,
+ * and every member's rows must be multiples of 64 bytes. */
+rlbm_status rlbm_batch_set_store_mode(rlbm_batch *b, int32_t mode);
+rlbm_status rlbm_batch_get_store_mode(const rlbm_batch *b, int32_t *mode, int32_t *nontemporal);
+
 #ifdef __cplusplus
 }
 #endif

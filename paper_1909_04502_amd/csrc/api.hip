@@ -18,6 +18,7 @@ struct rlbm_lattice {
   int *d_err = nullptr;
   int stencil = 0;
   int variant = 1;
+  int store_mode = RLBM_STORES_AUTO;
   int64_t sites = 0;
   std::string last_error;
   // launch graphs of recent multi-step rlbm_step calls (buffers, step count, variant), least
@@ -25,7 +26,7 @@ struct rlbm_lattice {
   struct StepGraph {
     hipGraphExec_t exec = nullptr;
     const void *fa = nullptr, *fb = nullptr;
-    int n = -1, variant = -1;
+    int n = -1, variant = -1, nt = -1;
     uint64_t used = 0;
   };
   static constexpr int kGraphs = 4;
@@ -47,11 +48,12 @@ struct rlbm_batch {
   int *d_err = nullptr;
   int stencil = 0, order = 0, storage = 0, elem = 8;
   int variant = 0;
-  // cached launch graph of the last (f_a, f_b, nsteps, variant)
+  int store_mode = RLBM_STORES_AUTO;
+  // cached launch graph of the last (f_a, f_b, nsteps, variant, store kind)
   hipStream_t cap_stream = nullptr;
   hipGraphExec_t gexec = nullptr;
   const void *g_fa = nullptr, *g_fb = nullptr;
-  int g_n = -1, g_variant = -1;
+  int g_n = -1, g_variant = -1, g_nt = -1;
 };
 
 namespace {
@@ -91,6 +93,20 @@ int lattice_ext(const rlbm_lattice *h) {
   return 0;
 }
 
+// Non-temporal population stores pay once the two state buffers are well beyond the 256 MiB
+// last-level cache (just above it, much of the next step's input is still found there), and only
+// when every row of sites starts on a 64-byte boundary: with ragged rows a wave's stores cover
+// partial lines.  Measured on the step kernels: slower up to 281 MiB, 3-10 % faster from 405 MiB
+// on with aligned rows, 3-14 % slower with ragged ones.
+constexpr int64_t kNontemporalFootprint = 384ll << 20;
+constexpr int64_t kNontemporalRowAlign = 64;
+
+int uses_nontemporal(const rlbm_lattice *h) {
+  if (h->store_mode != RLBM_STORES_AUTO) return h->store_mode == RLBM_STORES_NONTEMPORAL;
+  const int64_t s = h->cfg.storage == RLBM_F64 ? 8 : 4;
+  return 2 * s * h->quad.Q * h->sites > kNontemporalFootprint && (h->cfg.extent[0] * s) % kNontemporalRowAlign == 0;
+}
+
 rlbm::LaunchArgs base_args(const rlbm_lattice *h, hipStream_t stream) {
   rlbm::LaunchArgs a;
   a.stencil = h->stencil;
@@ -105,6 +121,7 @@ rlbm::LaunchArgs base_args(const rlbm_lattice *h, hipStream_t stream) {
   a.stream = stream;
   a.variant = h->variant;
   a.ext = lattice_ext(h);
+  a.nt = uses_nontemporal(h);
   return a;
 }
 
@@ -321,7 +338,9 @@ rlbm_status rlbm_step(rlbm_lattice *h, void *f_a, void *f_b, int32_t nsteps, con
     hipError_t he = hipSuccess;
     rlbm_lattice::StepGraph *sg = nullptr;
     for (auto &g : h->graphs)
-      if (g.exec && g.fa == f_a && g.fb == f_b && g.n == nsteps && g.variant == h->variant) sg = &g;
+      if (g.exec && g.fa == f_a && g.fb == f_b && g.n == nsteps && g.variant == h->variant &&
+          g.nt == uses_nontemporal(h))
+        sg = &g;
     if (!sg) {
       sg = &h->graphs[0];
       for (auto &g : h->graphs)
@@ -343,6 +362,7 @@ rlbm_status rlbm_step(rlbm_lattice *h, void *f_a, void *f_b, int32_t nsteps, con
         sg->fb = f_b;
         sg->n = nsteps;
         sg->variant = h->variant;
+        sg->nt = uses_nontemporal(h);
       } else {
         sg->exec = nullptr;
       }
@@ -589,6 +609,13 @@ rlbm_status rlbm_batch_moments(rlbm_batch *b, const void *f, const rlbm_fields *
   return RLBM_OK;
 }
 
+static int batch_nontemporal(const rlbm_batch *b) {
+  if (b->store_mode != RLBM_STORES_AUTO) return b->store_mode == RLBM_STORES_NONTEMPORAL;
+  for (auto *h : b->lats)
+    if ((h->cfg.extent[0] * b->elem) % kNontemporalRowAlign != 0) return 0;
+  return 2 * b->total_elems * b->elem > kNontemporalFootprint;
+}
+
 static hipError_t batch_enqueue(rlbm_batch *b, void *f_a, void *f_b, int32_t nsteps, hipStream_t stream) {
   rlbm::BatchArgs a;
   a.stencil = b->stencil;
@@ -604,6 +631,7 @@ static hipError_t batch_enqueue(rlbm_batch *b, void *f_a, void *f_b, int32_t nst
   a.stream = stream;
   a.ext = 0;
   for (auto *h : b->lats) a.ext |= lattice_ext(h);
+  a.nt = batch_nontemporal(b);
   for (int32_t s = 0; s < nsteps; ++s) {
     a.fin = (s & 1) ? f_b : f_a;
     a.fout = (s & 1) ? f_a : f_b;
@@ -624,7 +652,8 @@ rlbm_status rlbm_batch_step(rlbm_batch *b, void *f_a, void *f_b, int32_t nsteps,
   if (!use_graph) {
     he = batch_enqueue(b, f_a, f_b, nsteps, stream);
   } else {
-    if (!(b->gexec && b->g_fa == f_a && b->g_fb == f_b && b->g_n == nsteps && b->g_variant == b->variant)) {
+    if (!(b->gexec && b->g_fa == f_a && b->g_fb == f_b && b->g_n == nsteps && b->g_variant == b->variant &&
+          b->g_nt == batch_nontemporal(b))) {
       if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
       b->gexec = nullptr;
       hipGraph_t g = nullptr;
@@ -641,6 +670,7 @@ rlbm_status rlbm_batch_step(rlbm_batch *b, void *f_a, void *f_b, int32_t nsteps,
         b->g_fb = f_b;
         b->g_n = nsteps;
         b->g_variant = b->variant;
+        b->g_nt = batch_nontemporal(b);
       }
     }
     if (he == hipSuccess) he = hipGraphLaunch(b->gexec, stream);
@@ -684,6 +714,19 @@ rlbm_status rlbm_batch_set_variant(rlbm_batch *b, int32_t v) {
 rlbm_status rlbm_batch_get_variant(const rlbm_batch *b, int32_t *v) {
   if (!b || !v) return fail(RLBM_ERR_INVALID_ARG, "null argument");
   *v = b->variant;
+  return RLBM_OK;
+}
+
+rlbm_status rlbm_batch_set_store_mode(rlbm_batch *b, int32_t mode) {
+  if (!b || mode < RLBM_STORES_AUTO || mode > RLBM_STORES_NONTEMPORAL) return fail(RLBM_ERR_INVALID_ARG, "bad store mode");
+  b->store_mode = mode;
+  return RLBM_OK;
+}
+
+rlbm_status rlbm_batch_get_store_mode(const rlbm_batch *b, int32_t *mode, int32_t *nontemporal) {
+  if (!b || !mode) return fail(RLBM_ERR_INVALID_ARG, "null argument");
+  *mode = b->store_mode;
+  if (nontemporal) *nontemporal = batch_nontemporal(b);
   return RLBM_OK;
 }
 
@@ -734,6 +777,19 @@ rlbm_status rlbm_set_variant(rlbm_lattice *h, int32_t v) {
 rlbm_status rlbm_get_variant(const rlbm_lattice *h, int32_t *v) {
   if (!h || !v) return fail(RLBM_ERR_INVALID_ARG, "null argument");
   *v = h->variant;
+  return RLBM_OK;
+}
+
+rlbm_status rlbm_set_store_mode(rlbm_lattice *h, int32_t mode) {
+  if (!h || mode < RLBM_STORES_AUTO || mode > RLBM_STORES_NONTEMPORAL) return fail(RLBM_ERR_INVALID_ARG, "bad store mode");
+  h->store_mode = mode;
+  return RLBM_OK;
+}
+
+rlbm_status rlbm_get_store_mode(const rlbm_lattice *h, int32_t *mode, int32_t *nontemporal) {
+  if (!h || !mode) return fail(RLBM_ERR_INVALID_ARG, "null argument");
+  *mode = h->store_mode;
+  if (nontemporal) *nontemporal = uses_nontemporal(h);
   return RLBM_OK;
 }
 

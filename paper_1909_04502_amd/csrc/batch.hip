@@ -19,7 +19,7 @@ __device__ __forceinline__ int wrap_b(int v, int n, int open) {
   return v >= n ? v - n : v;
 }
 
-template <class ST, int N, typename S, bool DEV, int BX, int BY, bool EXT>
+template <class ST, int N, typename S, bool DEV, int BX, int BY, bool EXT, bool NT>
 __global__ void __launch_bounds__(BX * BY) k_step_batch(const Tables *__restrict__ tabs,
                                                         const int64_t *__restrict__ elem_off,
                                                         const int2 *__restrict__ tiles, int ntiles,
@@ -54,32 +54,50 @@ __global__ void __launch_bounds__(BX * BY) k_step_batch(const Tables *__restrict
     if (!mac.ok) *(volatile int *)err = 1;
     const uint32_t so = (uint32_t)site * (uint32_t)sizeof(S);
 #pragma unroll
-    for (int i = 0; i < ST::Q; ++i) *(S *)((char *)(fo + (int64_t)i * sites) + so) = f[i];
+    for (int i = 0; i < ST::Q; ++i) put_pop<NT>(fo, sites, so, i, f[i]);
   }
 }
 
-template <class ST, int N, typename S, bool DEV, bool EXT>
+template <class ST, int N, typename S, bool DEV, bool EXT, bool NT>
 static hipError_t launch_batch_t(const BatchArgs &a) {
   const int nb = a.blocks;
   switch (a.tile) {
     case 0:
-      hipLaunchKernelGGL((k_step_batch<ST, N, S, DEV, 64, 4, EXT>), dim3(nb), dim3(64, 4), 0, a.stream, a.tabs,
+      hipLaunchKernelGGL((k_step_batch<ST, N, S, DEV, 64, 4, EXT, NT>), dim3(nb), dim3(64, 4), 0, a.stream, a.tabs,
                          a.elem_off, a.tiles, a.ntiles, (const S *)a.fin, (S *)a.fout, a.err);
       break;
     case 1:
-      hipLaunchKernelGGL((k_step_batch<ST, N, S, DEV, 64, 2, EXT>), dim3(nb), dim3(64, 2), 0, a.stream, a.tabs,
+      hipLaunchKernelGGL((k_step_batch<ST, N, S, DEV, 64, 2, EXT, NT>), dim3(nb), dim3(64, 2), 0, a.stream, a.tabs,
                          a.elem_off, a.tiles, a.ntiles, (const S *)a.fin, (S *)a.fout, a.err);
       break;
     case 2:
-      hipLaunchKernelGGL((k_step_batch<ST, N, S, DEV, 128, 2, EXT>), dim3(nb), dim3(128, 2), 0, a.stream, a.tabs,
+      hipLaunchKernelGGL((k_step_batch<ST, N, S, DEV, 128, 2, EXT, NT>), dim3(nb), dim3(128, 2), 0, a.stream, a.tabs,
                          a.elem_off, a.tiles, a.ntiles, (const S *)a.fin, (S *)a.fout, a.err);
       break;
     default:
-      hipLaunchKernelGGL((k_step_batch<ST, N, S, DEV, 256, 1, EXT>), dim3(nb), dim3(256, 1), 0, a.stream, a.tabs,
+      hipLaunchKernelGGL((k_step_batch<ST, N, S, DEV, 256, 1, EXT, NT>), dim3(nb), dim3(256, 1), 0, a.stream, a.tabs,
                          a.elem_off, a.tiles, a.ntiles, (const S *)a.fin, (S *)a.fout, a.err);
       break;
   }
   return hipGetLastError();
+}
+
+template <bool NT>
+static hipError_t launch_batch_ext(const BatchArgs &a) {
+  if (a.ext) {
+    if (a.order == 2) {
+      if (a.storage == 0) return launch_batch_t<Stencil<ST_PROD2D, 3>, 2, double, false, true, NT>(a);
+      return launch_batch_t<Stencil<ST_PROD2D, 3>, 2, float, true, true, NT>(a);
+    }
+    if (a.storage == 0) return launch_batch_t<Stencil<ST_PROD2D, 4>, 3, double, false, true, NT>(a);
+    return launch_batch_t<Stencil<ST_PROD2D, 4>, 3, float, true, true, NT>(a);
+  }
+  if (a.order == 2) {
+    if (a.storage == 0) return launch_batch_t<Stencil<ST_PROD2D, 3>, 2, double, false, false, NT>(a);
+    return launch_batch_t<Stencil<ST_PROD2D, 3>, 2, float, true, false, NT>(a);
+  }
+  if (a.storage == 0) return launch_batch_t<Stencil<ST_PROD2D, 4>, 3, double, false, false, NT>(a);
+  return launch_batch_t<Stencil<ST_PROD2D, 4>, 3, float, true, false, NT>(a);
 }
 
 hipError_t launch_batch(const BatchArgs &a) {
@@ -87,20 +105,7 @@ hipError_t launch_batch(const BatchArgs &a) {
   if (a.stencil != ST_PROD2D || a.blocks < 8 || a.blocks % 8 != 0 || a.tile < 0 || a.tile > 3)
     return hipErrorInvalidValue;
   if (a.ntiles == 0) return hipSuccess;
-  if (a.ext) {
-    if (a.order == 2) {
-      if (a.storage == 0) return launch_batch_t<Stencil<ST_PROD2D, 3>, 2, double, false, true>(a);
-      return launch_batch_t<Stencil<ST_PROD2D, 3>, 2, float, true, true>(a);
-    }
-    if (a.storage == 0) return launch_batch_t<Stencil<ST_PROD2D, 4>, 3, double, false, true>(a);
-    return launch_batch_t<Stencil<ST_PROD2D, 4>, 3, float, true, true>(a);
-  }
-  if (a.order == 2) {
-    if (a.storage == 0) return launch_batch_t<Stencil<ST_PROD2D, 3>, 2, double, false, false>(a);
-    return launch_batch_t<Stencil<ST_PROD2D, 3>, 2, float, true, false>(a);
-  }
-  if (a.storage == 0) return launch_batch_t<Stencil<ST_PROD2D, 4>, 3, double, false, false>(a);
-  return launch_batch_t<Stencil<ST_PROD2D, 4>, 3, float, true, false>(a);
+  return a.nt ? launch_batch_ext<true>(a) : launch_batch_ext<false>(a);
 }
 
 }  // namespace rlbm

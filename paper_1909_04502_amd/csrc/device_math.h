@@ -297,4 +297,15 @@ __device__ __forceinline__ void basis_moments(double n, double T, const double (
   }
 }
 
+// One post-collision population: plane base (uniform) + 32-bit byte offset of the site.  NT marks
+// the store non-temporal: the line is written towards memory without being kept in the L2 or the
+// last-level cache, which pays when the two state buffers are larger than that cache (the next
+// step reads the populations from memory either way) and costs when they would fit in it.
+template <bool NT, typename S>
+__device__ __forceinline__ void put_pop(S *__restrict__ fout, int64_t sites, uint32_t site_off, int i, S v) {
+  S *p = (S *)((char *)(fout + (int64_t)i * sites) + site_off);
+  if constexpr (NT) __builtin_nontemporal_store(v, p);
+  else *p = v;
+}
+
 }  // namespace rlbm

@@ -40,6 +40,7 @@ struct LaunchArgs {
   double amp = 0.0;
   int *err = nullptr;               // device error flag
   int ext = 0;                      // the lattice has an external force or no-slip walls
+  int nt = 0;                       // step kernels store the populations non-temporally
   hipStream_t stream = 0;
 };
 
@@ -83,6 +84,7 @@ struct BatchArgs {
   int *err = nullptr;
   hipStream_t stream = 0;
   int ext = 0;                   // some member has an external force or no-slip walls
+  int nt = 0;                    // non-temporal population stores
 };
 hipError_t launch_batch(const BatchArgs &a);
 

@@ -20,6 +20,7 @@
 
 #include <algorithm>
 
+#include <type_traits>
 #include <utility>
 
 #include "device_math.h"
@@ -149,12 +150,11 @@ __device__ __forceinline__ Macro<ST::D> collide_site(const Tables *__restrict__ 
     return collide_prod<ST, N, S, DEV, RELAX, EXT>(tb, f, tau, wallT);
 }
 
-// post-collision store: plane base (uniform) + 32-bit byte offset of the site
-template <class ST, typename S>
+template <class ST, typename S, bool NT = false>
 __device__ __forceinline__ void store_site(S *__restrict__ fout, int64_t sites, uint32_t site_off,
                                            const S (&f)[ST::Q]) {
 #pragma unroll
-  for (int i = 0; i < ST::Q; ++i) *(S *)((char *)(fout + (int64_t)i * sites) + site_off) = f[i];
+  for (int i = 0; i < ST::Q; ++i) put_pop<NT>(fout, sites, site_off, i, f[i]);
 }
 
 // Site of this thread.  Blocks form a 1D grid over tiles of blockDim.x x
@@ -201,7 +201,7 @@ __device__ __forceinline__ bool site_coords(const Tables *__restrict__ tb, int x
   return x < tb->nx && y < tb->ny && z < tb->nz;
 }
 
-template <class ST, int N, typename S, bool DEV, int OCC, bool EXT = false>
+template <class ST, int N, typename S, bool DEV, int OCC, bool EXT, bool NT>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(OCC > 0 ? OCC : 1, 8))) k_step(const Tables *__restrict__ tb, const S *__restrict__ fin,
                                               S *__restrict__ fout, const void *__restrict__ tau_field,
                                               FieldPtrs last, int *err, int xcd) {
@@ -218,7 +218,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(OCC > 
   // load phase's plane offsets alive (in spilled scalar registers) for reuse here
   int64_t sites_st = sites;
   if constexpr (ST::D == 3) asm volatile("" : "+s"(sites_st));
-  store_site<ST, S>(fout, sites_st, (uint32_t)site * (uint32_t)sizeof(S), f);
+  store_site<ST, S, NT>(fout, sites_st, (uint32_t)site * (uint32_t)sizeof(S), f);
   if (last.any) write_fields<ST::D>(last, site, sites, mac);
 }
 
@@ -228,7 +228,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(OCC > 
 // loaded again (from the caches or memory) for the relaxation; every result is
 // stored at once.  Keeping about a third of them balances the re-read traffic
 // against the registers the eigen-solve and the projection need.
-template <class ST, int N, typename S, bool DEV, int OCC>
+template <class ST, int N, typename S, bool DEV, int OCC, bool NT>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(OCC > 0 ? OCC : 1, 8)))
 k_step_stream(const Tables *__restrict__ tb, const S *__restrict__ fin, S *__restrict__ fout,
               const void *__restrict__ tau_field, FieldPtrs last, int *err, int xcd) {
@@ -259,7 +259,7 @@ k_step_stream(const Tables *__restrict__ tb, const S *__restrict__ fin, S *__res
         return v;
       },
       [&](int i) { return i < kStreamKeep ? keep[i < kStreamKeep ? i : 0] : load(fin2, i); },
-      [&](int i, S v) { *(S *)((char *)(fout + (int64_t)i * sites) + site_off) = v; });
+      [&](int i, S v) { put_pop<NT>(fout, sites, site_off, i, v); });
   if (!mac.ok) flag_error(err);
   if (last.any) write_fields<ST::D>(last, site, sites, mac);
 }
@@ -366,32 +366,35 @@ static hipError_t launch_t(const LaunchArgs &a) {
   // 143 floats fit, and there the single load is faster
   constexpr bool kStream = ST::ONLAT && ST::SHIFT && ST::D == 3 && sizeof(S) == 8;
   switch (a.op) {
-    case OP_STEP:
-      if constexpr (kStream) {
-        if (vr.occ == 2)
-          hipLaunchKernelGGL((k_step_stream<ST, N, S, DEV, 2>), grid, block, 0, a.stream, a.tb, (const S *)a.fin,
-                             (S *)a.fout, a.tau_field, a.fields, a.err, order);
-        else if (vr.occ == 3)
-          hipLaunchKernelGGL((k_step_stream<ST, N, S, DEV, 3>), grid, block, 0, a.stream, a.tb, (const S *)a.fin,
-                             (S *)a.fout, a.tau_field, a.fields, a.err, order);
+    case OP_STEP: {
+      // one instantiation per (occupancy target 0 or 2, force/walls, store kind)
+      auto go = [&](auto occ, auto ext, auto nt) {
+        constexpr int O = decltype(occ)::value;
+        constexpr bool E = decltype(ext)::value, T = decltype(nt)::value;
+        if constexpr (kStream)
+          hipLaunchKernelGGL((k_step_stream<ST, N, S, DEV, O, T>), grid, block, 0, a.stream, a.tb,
+                             (const S *)a.fin, (S *)a.fout, a.tau_field, a.fields, a.err, order);
         else
-          hipLaunchKernelGGL((k_step_stream<ST, N, S, DEV, 0>), grid, block, 0, a.stream, a.tb, (const S *)a.fin,
+          hipLaunchKernelGGL((k_step<ST, N, S, DEV, O, E, T>), grid, block, 0, a.stream, a.tb, (const S *)a.fin,
                              (S *)a.fout, a.tau_field, a.fields, a.err, order);
-        break;
+      };
+      using O0 = std::integral_constant<int, 0>;
+      using O2 = std::integral_constant<int, 2>;
+      using F = std::false_type;
+      using T = std::true_type;
+      const bool ext = a.ext && !kStream;
+      if (ext) {
+        if (a.nt) go(O0{}, T{}, T{});
+        else go(O0{}, T{}, F{});
+      } else if (vr.occ == 2) {
+        if (a.nt) go(O2{}, F{}, T{});
+        else go(O2{}, F{}, F{});
+      } else {
+        if (a.nt) go(O0{}, F{}, T{});
+        else go(O0{}, F{}, F{});
       }
-      if (a.ext)
-        hipLaunchKernelGGL((k_step<ST, N, S, DEV, 0, true>), grid, block, 0, a.stream, a.tb, (const S *)a.fin,
-                           (S *)a.fout, a.tau_field, a.fields, a.err, order);
-      else if (vr.occ == 2)
-        hipLaunchKernelGGL((k_step<ST, N, S, DEV, 2>), grid, block, 0, a.stream, a.tb, (const S *)a.fin,
-                           (S *)a.fout, a.tau_field, a.fields, a.err, order);
-      else if (vr.occ == 3)
-        hipLaunchKernelGGL((k_step<ST, N, S, DEV, 3>), grid, block, 0, a.stream, a.tb, (const S *)a.fin,
-                           (S *)a.fout, a.tau_field, a.fields, a.err, order);
-      else
-        hipLaunchKernelGGL((k_step<ST, N, S, DEV, 0>), grid, block, 0, a.stream, a.tb, (const S *)a.fin,
-                           (S *)a.fout, a.tau_field, a.fields, a.err, order);
       break;
+    }
     case OP_MOMENTS:
       hipLaunchKernelGGL((k_moments<ST, N, S, DEV>), grid, block, 0, a.stream, a.tb, (const S *)a.fin, a.fields,
                          a.err);

@@ -110,6 +110,10 @@ def lib():
     L.rlbm_set_variant.argtypes = [c_void_p, c_int32]
     L.rlbm_get_variant.restype = st
     L.rlbm_get_variant.argtypes = [c_void_p, POINTER(c_int32)]
+    L.rlbm_set_store_mode.restype = st
+    L.rlbm_set_store_mode.argtypes = [c_void_p, c_int32]
+    L.rlbm_get_store_mode.restype = st
+    L.rlbm_get_store_mode.argtypes = [c_void_p, POINTER(c_int32), POINTER(c_int32)]
     L.rlbm_autotune.restype = st
     L.rlbm_autotune.argtypes = [c_void_p, c_int32, c_void_p, c_void_p]
     L.rlbm_batch_create.restype = st
@@ -134,6 +138,10 @@ def lib():
     L.rlbm_batch_set_variant.argtypes = [c_void_p, c_int32]
     L.rlbm_batch_get_variant.restype = st
     L.rlbm_batch_get_variant.argtypes = [c_void_p, POINTER(c_int32)]
+    L.rlbm_batch_set_store_mode.restype = st
+    L.rlbm_batch_set_store_mode.argtypes = [c_void_p, c_int32]
+    L.rlbm_batch_get_store_mode.restype = st
+    L.rlbm_batch_get_store_mode.argtypes = [c_void_p, POINTER(c_int32), POINTER(c_int32)]
     L.rlbm_batch_autotune.restype = st
     L.rlbm_batch_autotune.argtypes = [c_void_p, c_void_p, c_void_p, c_int32, c_void_p, c_void_p]
     _lib = L
@@ -347,6 +355,27 @@ class Lattice:
     def variant(self, v):
         _check(lib().rlbm_set_variant(self.h, int(v)))
 
+    STORE_MODES = {"auto": 0, "cached": 1, "nontemporal": 2}
+
+    @property
+    def store_mode(self):
+        """How the step writes populations: "auto" (non-temporal once both state buffers together exceed
+        384 MiB, 1.5 times the last-level cache, and a row of sites is a multiple of 64 bytes), "cached" or "nontemporal" (rlbm_set_store_mode)."""
+        m, nt = c_int32(0), c_int32(0)
+        _check(lib().rlbm_get_store_mode(self.h, ctypes.byref(m), ctypes.byref(nt)))
+        return {v: k for k, v in self.STORE_MODES.items()}[m.value]
+
+    @store_mode.setter
+    def store_mode(self, mode):
+        _check(lib().rlbm_set_store_mode(self.h, self.STORE_MODES[mode]))
+
+    @property
+    def nontemporal_stores(self):
+        """Whether the step currently uses non-temporal population stores."""
+        m, nt = c_int32(0), c_int32(0)
+        _check(lib().rlbm_get_store_mode(self.h, ctypes.byref(m), ctypes.byref(nt)))
+        return bool(nt.value)
+
     def autotune(self, steps=5):
         """Time every launch variant on scratch buffers; keep the fastest. Returns ms per step per variant."""
         n = lib().rlbm_variant_count()
@@ -465,6 +494,23 @@ class Batch:
     @variant.setter
     def variant(self, v):
         _check(lib().rlbm_batch_set_variant(self.h, int(v)))
+
+    @property
+    def store_mode(self):
+        """"auto", "cached" or "nontemporal" population stores (rlbm_batch_set_store_mode)."""
+        m, nt = c_int32(0), c_int32(0)
+        _check(lib().rlbm_batch_get_store_mode(self.h, ctypes.byref(m), ctypes.byref(nt)))
+        return {v: k for k, v in Lattice.STORE_MODES.items()}[m.value]
+
+    @store_mode.setter
+    def store_mode(self, mode):
+        _check(lib().rlbm_batch_set_store_mode(self.h, Lattice.STORE_MODES[mode]))
+
+    @property
+    def nontemporal_stores(self):
+        m, nt = c_int32(0), c_int32(0)
+        _check(lib().rlbm_batch_get_store_mode(self.h, ctypes.byref(m), ctypes.byref(nt)))
+        return bool(nt.value)
 
     def autotune(self, f_a, f_b, steps=4):
         """Time every batch variant on (f_a, f_b) (state ends in f_a); keep the fastest."""

@@ -1,0 +1,167 @@
+"""Non-temporal population stores (rlbm_set_store_mode).
+
+* Every step kernel (2D and 3D product rules, force and walls, the printed massless rules, the massive
+  rules including the streaming 3D kernel, both storages) gives the same state bit for bit with
+  ordinary and with non-temporal stores, through single launches and through the cached step graphs,
+  also after the mode changes between graph replays on the same buffers.
+* One case with non-temporal stores against the FP64 oracle.
+* The automatic choice follows the state footprint (2 Q sites x element size against 384 MiB) and
+  the row alignment (extent[0] x element size a multiple of 64 bytes).
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import lattice as OL
+from oracle import quadrature as qd
+
+pytestmark = pytest.mark.gpu
+
+
+def fields(d, ext, seed):
+    shape = tuple(reversed(ext))
+    g = np.random.default_rng(seed)
+    n = 1.0 + 0.02 * g.standard_normal(shape)
+    T = 1.0 + 0.05 * g.uniform(-1, 1, shape)
+    u = 0.05 * g.uniform(-1, 1, (d,) + shape)
+    return [torch.tensor(a) for a in (n, T, u)]
+
+
+# name: (d, zeta, order, kind, extent, bc, storage, force)
+CASES = {
+    "prod2d_f64": (2, 1.0, 3, "product", (96, 70), ("periodic", "periodic"), "f64", None),
+    "prod2d_f32dev": (2, 1.0, 3, "product", (96, 70), ("periodic", "periodic"), "f32dev", None),
+    "prod2d_force_walls": (2, 2.5, 3, "product", (19, 12), ("wall", "periodic"), "f64", (0.0, 3e-4)),
+    "prod3d_f32dev": (3, 1.0, 3, "product", (13, 9, 7), ("periodic",) * 3, "f32dev", None),
+    "ur_order3": (2, 0.0, 3, "ur_onlattice", (37, 11), ("periodic", "periodic"), "f64", None),
+    "massive2d_n3": (2, 5.0, 3, "massive_onlattice", (41, 12), ("open", "periodic"), "f64", None),
+    "massive3d_f64": (3, 5.0, 3, "massive_onlattice", (9, 7, 6), ("periodic",) * 3, "f64", None),
+    "massive3d_f32dev": (3, 5.0, 3, "massive_onlattice", (9, 7, 6), ("periodic",) * 3, "f32dev", None),
+}
+
+
+def make(name):
+    from paper_1909_04502_amd import rlbm as R
+    d, zeta, order, kind, ext, bc, storage, force = CASES[name]
+    kw = {"force": force} if force else {}
+    return R.Lattice(d=d, zeta=zeta, order=order, kind=kind, extent=ext, bc=bc, storage=storage, tau=0.9, **kw)
+
+
+def run(gl, f0, mode, plan):
+    """Advance a copy of f0 by the step counts in plan (each an rlbm_step call) with one store mode."""
+    gl.store_mode = mode
+    a, b = f0.clone(), gl.new_state()
+    for k in plan:
+        r = gl.step(a, b, k)
+        a, b = r, (b if r is a else a)
+    gl.sync()
+    return a
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_nontemporal_stores_bit_identical(name):
+    print(f"[case] stores {name}", flush=True)
+    gl = make(name)
+    d = CASES[name][0]
+    f0 = gl.init(*fields(d, CASES[name][4], seed=3))
+    plan = [1, 1, 5, 4]                     # single launches, then two graph lengths
+    ref = run(gl, f0, "cached", plan)
+    assert not gl.nontemporal_stores
+    nt = run(gl, f0, "nontemporal", plan)
+    assert gl.nontemporal_stores
+    assert torch.equal(nt, ref)
+    assert torch.isfinite(ref).all()
+
+
+def test_mode_change_between_graph_replays():
+    """The cached step graphs are keyed on the store kind: switching modes between replays on the same
+    buffers keeps the results equal to single launches."""
+    print("[case] stores graph replays", flush=True)
+    gl = make("prod2d_f64")
+    f0 = gl.init(*fields(2, CASES["prod2d_f64"][4], seed=4))
+    ga, gb = f0.clone(), gl.new_state()
+    ea, eb = f0.clone(), gl.new_state()
+    for rep, mode in enumerate(["cached", "nontemporal", "cached", "auto", "nontemporal"]):
+        gl.store_mode = mode
+        r = gl.step(ga, gb, 4)
+        ga, gb = r, (gb if r is ga else ga)
+        for _ in range(4):
+            r = gl.step(ea, eb, 1)
+            ea, eb = r, (eb if r is ea else ea)
+        gl.sync()
+        assert torch.equal(ga, ea), rep
+
+
+def test_nontemporal_stores_oracle_parity():
+    """Ragged 2D product-rule lattice, FP64, seven steps with non-temporal stores against the oracle."""
+    print("[case] stores oracle parity", flush=True)
+    gl = make("prod2d_f64")
+    ext = CASES["prod2d_f64"][4]
+    n, T, u = fields(2, ext, seed=5)
+    gl.store_mode = "nontemporal"
+    res = gl.step(gl.init(n, T, u), gl.new_state(), 7)
+    gl.sync()
+    ol = OL.Lattice(qd.product_2d(1.0, 3), 0.9, ext)
+    fs = ol.collide(ol.init(n, T, u))
+    for _ in range(7):
+        fs = ol.collide(ol.stream(fs))
+    err = ((res.cpu() - fs).abs().max() / fs.abs().max()).item()
+    assert err < 1e-12
+
+
+@pytest.mark.parametrize("d,ext,storage,want", [
+    (2, (512, 512), "f64", False),          # 2 x 32 x 8 B x 2^18 = 128 MiB
+    (2, (1024, 1024), "f64", True),         # 512 MiB
+    (2, (1024, 1024), "f32dev", False),     # 256 MiB
+    (2, (1536, 1024), "f32dev", False),     # 384 MiB: not above
+    (2, (1552, 1024), "f32dev", True),      # 388 MiB, rows of 6208 B
+    (2, (1030, 1030), "f64", False),        # 518 MiB, but rows of 8240 B
+    (2, (1000, 1000), "f64", True),         # rows of 8000 B
+    (3, (32, 32, 32), "f64", False),        # 2 x 104 x 8 B x 2^15 = 52 MiB
+    (3, (128, 128, 128), "f32dev", True),   # 1.6 GiB
+])
+def test_automatic_choice_follows_footprint(d, ext, storage, want):
+    from paper_1909_04502_amd import rlbm as R
+    gl = R.Lattice(d=d, zeta=1.0, order=3, extent=ext, storage=storage, tau=0.9)
+    q, s = gl.Q, (8 if storage == "f64" else 4)
+    sites = int(np.prod(ext))
+    assert gl.store_mode == "auto"
+    assert gl.nontemporal_stores == (2 * q * s * sites > 384 * 2 ** 20 and ext[0] * s % 64 == 0) == want
+    gl.store_mode = "cached"
+    assert not gl.nontemporal_stores
+    gl.store_mode = "nontemporal"
+    assert gl.nontemporal_stores
+    with pytest.raises(KeyError):
+        gl.store_mode = "bogus"
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32dev"])
+def test_batch_nontemporal_stores_bit_identical(storage):
+    """The batched step (one persistent launch over several 2D product-rule lattices, with walls and a
+    force on one member) gives the same state with both store kinds, eagerly and through its graph."""
+    from paper_1909_04502_amd import rlbm as R
+    import workloads as W
+    print(f"[case] batch stores {storage}", flush=True)
+    specs = [{"extent": (64, 48), "zeta": 1.0, "tau": 0.8},
+             {"extent": (33, 65), "zeta": 5.0, "tau": 0.9, "bc": ("periodic", "open")},
+             {"extent": (19, 12), "zeta": 2.5, "tau": 1.1, "bc": ("wall", "periodic"), "force": (0.0, 3e-4)}]
+    b = R.Batch(specs, order=3, storage=storage)
+    ns, Ts, us = [], [], []
+    for i, sp in enumerate(specs):
+        n, T, u = W.taylor_green_2d(*sp["extent"], 0.08, density_sigma=1e-3, seed=20 + i)
+        ns.append(n), Ts.append(T), us.append(u)
+    f0 = b.init(ns, Ts, us)
+    assert b.store_mode == "auto" and not b.nontemporal_stores
+    out = {}
+    for mode in ("cached", "nontemporal"):
+        b.store_mode = mode
+        for graph in (False, True):
+            a, c = f0.clone(), b.new_state()
+            r = b.step(a, c, 5, graph=graph)
+            b.sync()
+            out[(mode, graph)] = r.clone()
+    assert b.nontemporal_stores
+    ref = out[("cached", False)]
+    assert torch.isfinite(ref).all()
+    for k, v in out.items():
+        assert torch.equal(v, ref), k
