@@ -367,7 +367,7 @@ static hipError_t launch_t(const LaunchArgs &a) {
   constexpr bool kStream = ST::ONLAT && ST::SHIFT && ST::D == 3 && sizeof(S) == 8;
   switch (a.op) {
     case OP_STEP: {
-      // one instantiation per (occupancy target 0 or 2, force/walls, store kind)
+      // one instantiation per (occupancy target 0, 2 or 4, force/walls, store kind)
       auto go = [&](auto occ, auto ext, auto nt) {
         constexpr int O = decltype(occ)::value;
         constexpr bool E = decltype(ext)::value, T = decltype(nt)::value;
@@ -380,6 +380,7 @@ static hipError_t launch_t(const LaunchArgs &a) {
       };
       using O0 = std::integral_constant<int, 0>;
       using O2 = std::integral_constant<int, 2>;
+      using O4 = std::integral_constant<int, 4>;
       using F = std::false_type;
       using T = std::true_type;
       const bool ext = a.ext && !kStream;
@@ -389,6 +390,9 @@ static hipError_t launch_t(const LaunchArgs &a) {
       } else if (vr.occ == 2) {
         if (a.nt) go(O2{}, F{}, T{});
         else go(O2{}, F{}, F{});
+      } else if (vr.occ == 4) {
+        if (a.nt) go(O4{}, F{}, T{});
+        else go(O4{}, F{}, F{});
       } else {
         if (a.nt) go(O0{}, F{}, T{});
         else go(O0{}, F{}, F{});
