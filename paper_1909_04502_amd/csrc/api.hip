@@ -215,9 +215,11 @@ rlbm_status rlbm_create(const rlbm_config *cfg, rlbm_lattice **out) {
   h->cfg = *cfg;
   h->stencil = stencil_of(m);
   // default launch shapes (from sweeps of every variant on MI355X):
-  //  * 3D product rules: float deviations keep ~100 populations in registers at occupancy 2
-  //    (untiled 64 x 4); in double the occupancy-2 build spills to scratch, so the unconstrained
-  //    build (468 registers, one wave per SIMD) in untiled 64 x 4 is 1.6x faster;
+  //  * 3D product rules: float deviations keep ~100 populations in registers at occupancy 2,
+  //    64 x 4 tiles in (y, z) patches per XCD (as fast as the untiled order, and half the
+  //    re-reads from beyond the L2: 1.19x the algorithmic bytes instead of 2.35x); in double
+  //    the occupancy-2 build spills to scratch, so the unconstrained build (468 registers, one
+  //    wave per SIMD) in untiled 64 x 4 is 1.6x faster;
   //  * the 3D massive rule: 64 x 2 XCD-ordered tiles (double, streaming kernel) or 64 x 1 patches
   //    (float);
   //  * 2D product rules in double: rows of 64 sites;
@@ -225,7 +227,7 @@ rlbm_status rlbm_create(const rlbm_config *cfg, rlbm_lattice **out) {
   //    update fits in 128 registers (order 2, and order 3 in float deviations), which take the
   //    occupancy-4 build: four waves per SIMD instead of three, 7-27 % faster
   if (m.d == 3 && m.kind == RLBM_QUAD_MASSIVE_ONLATTICE) h->variant = cfg->storage == RLBM_F64 ? 4 : 8;
-  else if (m.d == 3) h->variant = cfg->storage == RLBM_F64 ? 0 : 2;
+  else if (m.d == 3) h->variant = cfg->storage == RLBM_F64 ? 0 : 3;
   else if (m.kind == RLBM_QUAD_PRODUCT && cfg->storage == RLBM_F64) h->variant = 5;
   else if (m.kind == RLBM_QUAD_MASSIVE_ONLATTICE && (m.order == 2 || cfg->storage != RLBM_F64)) h->variant = 10;
   else if (m.kind != RLBM_QUAD_PRODUCT) h->variant = 3;
