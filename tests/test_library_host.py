@@ -100,6 +100,20 @@ def test_batch_create_validates_before_touching_the_device(rlbm_lib):
     assert rlbm_lib.rlbm_batch_variant_count() == 12
 
 
+def test_launch_and_store_mode_entry_points_reject_bad_arguments(rlbm_lib):
+    """Null handles and out-of-range modes are argument errors, answered without a device."""
+    from paper_1909_04502_amd import rlbm as R
+    m, nt = ctypes.c_int32(-1), ctypes.c_int32(-1)
+    assert rlbm_lib.rlbm_variant_count() == 11
+    for mode in (0, 1, 2, 3, -1):
+        assert rlbm_lib.rlbm_set_store_mode(None, mode) == R.ERR_INVALID_ARG
+        assert rlbm_lib.rlbm_batch_set_store_mode(None, mode) == R.ERR_INVALID_ARG
+    assert rlbm_lib.rlbm_get_store_mode(None, ctypes.byref(m), ctypes.byref(nt)) == R.ERR_INVALID_ARG
+    assert rlbm_lib.rlbm_batch_get_store_mode(None, ctypes.byref(m), ctypes.byref(nt)) == R.ERR_INVALID_ARG
+    assert rlbm_lib.rlbm_set_variant(None, 0) == R.ERR_INVALID_ARG
+    assert m.value == -1 and nt.value == -1
+
+
 @pytest.mark.parametrize("d,order,zetas", [(2, 3, (0.0, 0.01, 1.0, 5.0, 15.0)), (2, 2, (0.0, 30.0)),
                                           (3, 3, (0.0, 0.01, 0.3, 1.0, 5.0, 10.0)), (3, 2, (0.05, 30.0))])
 def test_tables_build_over_the_zeta_range(rlbm_lib, d, order, zetas):
