@@ -6,6 +6,9 @@ and the 256^3 shock-tube workload checked site by site on a sample (each
 sampled site's 3 x 3 x 3 upstream neighbourhood is streamed and collided by
 the oracle) plus global invariants on a periodic 64^3 grid.
 """
+import json
+import os
+
 import numpy as np
 import pytest
 import torch
@@ -214,3 +217,46 @@ def test_full_size_shock_tube_sampled():
     err = rel(got, want)
     print("full-size 3d sampled error", err, flush=True)
     assert err < F32_TOL
+
+
+def test_c3_full_length_float_deviations_against_fp64():
+    """The C3 shock tube over its full 2000 steps (256^3, zeta = 1, N = 3, open x): the FP64 run against
+    the oracle's own 2000 steps on the equivalent 256 x 1 x 1 lattice (tests/golden/make_c3_profile.py),
+    the float-deviation run against the FP64 run, both on the x-profiles of n, eps, T and U^x, and
+    the symmetries of the set-up: the state depends on x only,
+    so every (y, z) column equals the first one (each site's update is the same arithmetic on the
+    same inputs) and U^y = U^z = 0 up to round-off.  tau = 0.8: at the configuration's tau = 0.6 the
+    scheme itself (the FP64 oracle on the equivalent 256 x 1 x 1 lattice) turns non-physical at
+    step 113, populations going negative at the discontinuity from step 2."""
+    from paper_1909_04502_amd import rlbm as R
+    ext = (256, 256, 256)
+    bc = ("open", "periodic", "periodic")
+    steps = 2000
+    n, T, u = (torch.tensor(a) for a in riemann(ext))
+    prof = {}
+    for storage, sym_tol in (("f64", 1e-12), ("f32dev", 1e-5)):
+        print(f"[case] C3 full length {storage}", flush=True)
+        gl = R.Lattice(d=3, zeta=1.0, order=3, extent=ext, bc=bc, storage=storage, tau=0.8)
+        fa = gl.init(n, T, u)
+        res = gl.step(fa, gl.new_state(), steps)
+        mac = gl.moments(res)
+        gl.sync()
+        for k in ("n", "eps", "T"):
+            assert (mac[k] - mac[k][:1, :1, :]).abs().max().item() == 0.0, (storage, k)
+        assert (mac["U"] - mac["U"][:, :1, :1, :]).abs().max().item() == 0.0, storage
+        assert mac["U"][2:].abs().max().item() < sym_tol, storage
+        prof[storage] = {k: mac[k][0, 0].cpu() for k in ("n", "eps", "T")}
+        prof[storage]["Ux"] = mac["U"][1, 0, 0].cpu()
+        del gl, fa, res, mac
+        torch.cuda.empty_cache()
+    # the FP64 run against the oracle's own 2000 steps (tests/golden/make_c3_profile.py)
+    gold = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "c3_tau08_2000_profile.json")))
+    assert gold["steps"] == steps and gold["nx"] == ext[0]
+    ferr = {k: rel(prof["f64"][k], torch.tensor(gold[k], dtype=torch.float64)) for k in ("n", "eps", "T", "Ux")}
+    print("C3 2000-step FP64 vs oracle", ferr, flush=True)
+    # the two paths' round-off accumulates over 2000 steps: 1.1e-12 measured (n), 2.6e-13 (T)
+    assert max(ferr.values()) < 1e-11
+    errs = {k: rel(prof["f32dev"][k], prof["f64"][k]) for k in ("n", "eps", "T", "Ux")}
+    print("C3 2000-step float deviations vs FP64", errs, flush=True)
+    # measured: n 1.5e-4, eps 1.8e-4, T 3.5e-5, U^x 2.5e-4 (max-normalised)
+    assert max(errs.values()) < 1e-3
