@@ -100,6 +100,28 @@ def test_step_parity(name):
             assert rel(mom["U"][a], next_ref["U"][a]) < FP64_TOL
 
 
+def test_c1_full_length_against_oracle():
+    """C1 over its full 100 steps: 64 x 64, the printed massless rule (zeta = 0, N = 2, Q = 28),
+    tau = 0.9, Taylor-Green u0 = 0.01 with 1e-6 population noise (seed 1).  The populations and the
+    moments after 100 steps against the oracle's own 100 steps (whose Taylor-Green decay rate the
+    oracle tests pin to Chapman-Enskog); the two paths' round-off accumulates over the run."""
+    print("[case] C1 full length", flush=True)
+    gl, ol, (n, T, u, xi, amp) = setup_case("c1_ur_64")
+    nsteps = 100
+    res = gl.step(gl.init(n, T, u, xi, amp), gl.new_state(), nsteps)
+    mom = gl.moments(res)
+    gl.sync()
+    fs = ol.collide(ol.init(n, T, u, xi, amp))
+    for _ in range(nsteps):
+        fs = ol.collide(ol.stream(fs))
+    ref = ol.macro(ol.stream(fs))
+    err = {"f": rel(res, fs)}
+    err.update({k: rel(mom[k], ref[k]) for k in ("n", "eps", "T")})
+    err["U"] = rel(mom["U"][1:], ref["U"][1:])
+    print("C1 100-step errors", err, flush=True)
+    assert max(err.values()) < 1e-11
+
+
 @pytest.mark.parametrize("name", ["c2_ragged", "n2_open"])
 def test_f32_deviation_storage(name):
     """Float deviations from f^ref with double eigenproblem / EOS: macro fields within 1e-5 after 40 steps."""
