@@ -531,6 +531,8 @@ def main():
     }
     if tune is not None:
         out["autotune"] = {"variant": lat.variant, "ms_per_step": [round(x, 5) for x in tune]}
+    out["roofline"]["launch_variant"] = lat.variant
+    out["roofline"]["stores"] = "nontemporal" if lat.nontemporal_stores else "cached"
     del lat, fa, fb
     torch.cuda.empty_cache()
     if not args.no_variants:
