@@ -487,16 +487,23 @@ def cpu_baseline(seconds):
         f = ol.collide(ol.stream(f))
         steps += 1
     dt = time.perf_counter() - t0
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            model = next((ln.split(":", 1)[1].strip() for ln in fh if ln.startswith("model name")), model)
+    except OSError:
+        pass
     return {"value": L * L * steps / dt / 1e6, "unit": "MLUPS", "cores": torch.get_num_threads(),
             "kind": "oracle",
-            "sample": f"{steps} steps of a {L}x{L} lattice of the same workload ({dt:.1f} s, torch float64 on CPU)"}
+            "sample": f"{steps} steps of a {L}x{L} lattice of the same workload ({dt:.1f} s, torch float64 on CPU)",
+            "cpu": model, "host_cpus": os.cpu_count()}
 
 
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py: this build measures one GPU only (asked for --gpus {args.gpus}); "
-              "the path is a single-GPU lattice update", file=sys.stderr)
+        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}): the lattice update runs "
+              "on a single GPU", file=sys.stderr)
         sys.exit(2)
     import torch
     torch.cuda.set_device(0)

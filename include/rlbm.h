@@ -80,7 +80,7 @@ extern "C" {
 typedef enum {
   RLBM_OK = 0,
   RLBM_ERR_INVALID_ARG = 1,   /* bad pointer, size, or parameter */
-  RLBM_ERR_UNSUPPORTED = 2,   /* valid request outside what this build implements */
+  RLBM_ERR_UNSUPPORTED = 2,   /* valid request outside what the library implements */
   RLBM_ERR_QUADRATURE = 3,    /* quadrature construction or verification failed */
   RLBM_ERR_DEVICE = 4,        /* a HIP runtime call failed */
   RLBM_ERR_NONPHYSICAL = 5    /* a kernel met a non-physical state (see above) */

@@ -15,7 +15,7 @@ def pytest_configure(config):
 
 def pytest_collection_modifyitems(config, items):
     # GPU tests run only where a GPU is present; on a CPU-only machine they are skipped
-    # with a reason (the driver selects them with -m gpu on the GPU machine).
+    # with a reason (select them with -m gpu on a machine with an MI355X).
     try:
         import torch
         have_gpu = torch.cuda.is_available()
