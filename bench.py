@@ -472,21 +472,43 @@ def forcing_leg(L, warmup, steps):
 
 
 def cpu_baseline(seconds):
-    """The FP64 oracle (as it stands) on a 128 x 128 lattice of the same workload, on this host's cores."""
+    """The FP64 oracle (as it stands) on a 128 x 128 lattice of the same workload, on this host's cores.
+    The same leg states the error of the GPU path on that sample: the FP64 and float-deviation
+    libraries' populations and moments after the oracle's first 10 steps, max-normalised."""
     import torch
     import workloads as W
     from oracle import lattice as OL
     from oracle import quadrature as qd
-    L = 128
-    n, T, u = W.taylor_green_2d(L, L, 0.1, density_sigma=1e-3, seed=2)
+    from paper_1909_04502_amd import rlbm as R
+    L, KERR = 128, 10
+    n, T, u = (torch.tensor(a) for a in W.taylor_green_2d(L, L, 0.1, density_sigma=1e-3, seed=2))
     ol = OL.Lattice(qd.product_2d(1.0, 3), 0.8, (L, L))
-    f = ol.collide(ol.init(torch.tensor(n), torch.tensor(T), torch.tensor(u)))
+    f = ol.collide(ol.init(n, T, u))
+    for _ in range(KERR):                       # untimed: the reference for the error statement
+        f = ol.collide(ol.stream(f))
+    ref = (f.clone(), ol.macro(ol.stream(f)))
     steps = 0
     t0 = time.perf_counter()
     while time.perf_counter() - t0 < seconds or steps < 2:
         f = ol.collide(ol.stream(f))
         steps += 1
     dt = time.perf_counter() - t0
+    errors = {"steps": KERR, "lattice": f"{L}x{L}"}
+    for storage in ("f64", "f32dev"):
+        lat = R.Lattice(d=2, zeta=1.0, order=3, extent=(L, L), tau=0.8, storage=storage)
+        res = lat.step(lat.init(n, T, u), lat.new_state(), KERR)
+        mom = lat.moments(res)
+        lat.sync()
+
+        def rel(a, b):
+            a = a.detach().cpu().to(torch.float64)
+            return float((a - b).abs().max() / b.abs().max())
+        e = {k: rel(mom[k], ref[1][k]) for k in ("n", "eps", "T")}
+        e["U"] = rel(mom["U"][1:], ref[1]["U"][1:])
+        if storage == "f64":
+            e["f"] = rel(res, ref[0])
+        errors[storage] = {k: float(f"{v:.2e}") for k, v in e.items()}
+        del lat, res
     model = "unknown"
     try:
         with open("/proc/cpuinfo") as fh:
@@ -496,7 +518,7 @@ def cpu_baseline(seconds):
     return {"value": L * L * steps / dt / 1e6, "unit": "MLUPS", "cores": torch.get_num_threads(),
             "kind": "oracle",
             "sample": f"{steps} steps of a {L}x{L} lattice of the same workload ({dt:.1f} s, torch float64 on CPU)",
-            "cpu": model, "host_cpus": os.cpu_count()}
+            "cpu": model, "host_cpus": os.cpu_count(), "gpu_error_vs_oracle": errors}
 
 
 def main():
