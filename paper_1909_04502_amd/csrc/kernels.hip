@@ -251,7 +251,7 @@ k_step_stream(const Tables *__restrict__ tb, const S *__restrict__ fin, S *__res
   const double tau = site_tau<S>(tb, tau_field, site);
   constexpr int kStreamKeep = 48;
   S keep[kStreamKeep];
-  const Macro<ST::D> mac = massive_update<ST, N, S, DEV, true, false>(
+  const Macro<ST::D> mac = massive_update<ST, N, S, DEV, true, false, false>(
       tb, tau, -1.0,
       [&](int i) {
         const S v = load(fin, i);
