@@ -225,11 +225,14 @@ rlbm_status rlbm_create(const rlbm_config *cfg, rlbm_lattice **out) {
   //  * 2D product rules in double: rows of 64 sites;
   //  * 2D on-lattice rules: 64 x 4 tiles of the occupancy-2 build, except the massive rules whose
   //    update fits in 128 registers (order 2, and order 3 in float deviations), which take the
-  //    occupancy-4 build: four waves per SIMD instead of three, 7-27 % faster
+  //    occupancy-4 build: four waves per SIMD instead of three, 7-27 % faster; and small lattices
+  //    of the massless rules (at most 65,536 sites, such as 64 x 64), which take rows of 64 sites
+  //    so that four times as many blocks spread over the CUs (about 9 % faster at 64 x 64)
   if (m.d == 3 && m.kind == RLBM_QUAD_MASSIVE_ONLATTICE) h->variant = cfg->storage == RLBM_F64 ? 4 : 8;
   else if (m.d == 3) h->variant = cfg->storage == RLBM_F64 ? 0 : 3;
   else if (m.kind == RLBM_QUAD_PRODUCT && cfg->storage == RLBM_F64) h->variant = 5;
   else if (m.kind == RLBM_QUAD_MASSIVE_ONLATTICE && (m.order == 2 || cfg->storage != RLBM_F64)) h->variant = 10;
+  else if (m.kind == RLBM_QUAD_UR_ONLATTICE && sites <= 65536) h->variant = 5;
   else if (m.kind != RLBM_QUAD_PRODUCT) h->variant = 3;
   h->sites = sites;
   std::string err;
