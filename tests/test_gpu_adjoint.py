@@ -5,7 +5,8 @@
 * one adjoint step against central differences of one forward step
   (<J v, w> = <v, J^T w>);
 * central differences of the GPU forward (h = 1e-4) along seeded directions;
-* the float-deviation storage gradient against the double one.
+* the float-deviation storage gradient against the double one;
+* one reverse step at C5's full size (512 x 512), sampled sites against the oracle's VJP.
 """
 import numpy as np
 import pytest
@@ -131,3 +132,54 @@ def test_reverse_mode_rejects_unsupported_lattices():
     with pytest.raises(R.RLBMError) as e:
         lat.adjoint_step(B, B.clone())
     assert e.value.status == R.ERR_UNSUPPORTED
+
+
+def test_full_size_reverse_step_sampled():
+    """C5's reverse step at full size, in the launch configuration the bench times: 512 x 512, float
+    deviations, a tau field (0.8 +- 0.2, seed 4), zeta = 1, N = 3, from the state after 5 forward
+    steps and a seeded lam_{t+1}.  lam_t and the dL/dtau increment at 256 sampled sites against the
+    oracle: F_t(x) = S(B)(x) from B's 3 x 3 periodic neighbourhood, mu(x) = (S^T lam_{t+1})(x) from
+    lam_{t+1}'s (the transposed pull reaches one site the other way, so a 3 x 3 window does not
+    alias), and lam_t(x), dL/dtau(x) as the VJP of the oracle's collision at F_t(x) by autograd."""
+    from paper_1909_04502_amd import rlbm as R
+    print("[case] full-size reverse step", flush=True)
+    L = 512
+    n, T, u, tau, _ = problem(L, L)
+    lat = R.Lattice(d=2, zeta=1.0, order=3, extent=(L, L), storage="f32dev", tau=0.8, tau_field=tau.clone())
+    fa = lat.init(n, T, u)
+    B = lat.step(fa, lat.new_state(), 5)
+    g = np.random.default_rng(9)
+    lam_next = torch.tensor(g.normal(size=tuple(B.shape)) * 1e-3, dtype=B.dtype, device="cuda")
+    dtau = torch.zeros((L, L), dtype=torch.float64, device="cuda")
+    lam = lat.adjoint_step(B, lam_next, dtau=dtau)
+    lat.sync()
+    q = qd.product_2d(1.0, 3)
+    one = torch.ones(1, 1, dtype=torch.float64)
+    fref = OL.Lattice(q, 0.8, (1, 1)).equilibrium(one, one, torch.tensor([1.0, 0.0, 0.0],
+                                                                       dtype=torch.float64)[:, None, None])[:, 0, 0]
+    tau32 = tau.to(torch.float32).to(torch.float64)          # the field the library holds
+    K = 256
+    ys, xs = g.integers(0, L, K), g.integers(0, L, K)
+    ol3 = OL.Lattice(q, 0.8, (3, 3))
+    Bc, lamc = B.cpu().to(torch.float64), lam_next.cpu().to(torch.float64)
+    got_lam = lam.cpu().to(torch.float64)[:, ys, xs]
+    got_dtau = dtau.cpu()[ys, xs]
+    want_lam = torch.empty_like(got_lam)
+    want_dtau = torch.empty_like(got_dtau)
+    for k in range(K):
+        iy = torch.tensor([(ys[k] + d) % L for d in (-1, 0, 1)])
+        ix = torch.tensor([(xs[k] + d) % L for d in (-1, 0, 1)])
+        Bw = Bc[:, iy][:, :, ix] + fref[:, None, None]
+        Fc = ol3.stream(Bw)[:, 1:2, 1:2].clone().requires_grad_(True)
+        G = torch.zeros((q.Q, 3, 3), dtype=torch.float64, requires_grad=True)
+        (ol3.stream(G) * lamc[:, iy][:, :, ix]).sum().backward()
+        mu = G.grad[:, 1:2, 1:2]
+        tc = tau32[ys[k]:ys[k] + 1, xs[k]:xs[k] + 1].clone().requires_grad_(True)
+        ol1 = OL.Lattice(q, 0.8, (1, 1))
+        (OG.collide_diff(ol1, Fc, tc) * mu).sum().backward()
+        want_lam[:, k] = Fc.grad[:, 0, 0]
+        want_dtau[k] = tc.grad[0, 0]
+    el, ed = rel(got_lam, want_lam), rel(got_dtau, want_dtau)
+    print("full-size reverse step errors: lam", el, "dtau", ed, flush=True)
+    # measured: lam 7.8e-8, dL/dtau 4.2e-6 (a sum over the populations of float products)
+    assert el < 1e-5 and ed < 1e-5
