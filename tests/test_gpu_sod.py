@@ -12,7 +12,9 @@ sites per step and dt = 0.01 fm/c (300 steps to t = 3.0 fm/c); hbar c / T0 = 197
 viscosity eta = (3/4) P (tau - 1/2) dt, eta/s fixed gives tau = 1/2 + tau_T / T with
 tau_T = (eta/s) * 3 / (3/4) * (0.49332 fm / 0.01 fm).
 """
+import json
 import math
+import os
 
 import numpy as np
 import pytest
@@ -124,3 +126,12 @@ def test_sod_inviscid_against_app_d():
     # T 3.1e-3, beta 2.5e-3, plateau speed 2e-4
     assert err["n"] < 5e-3 and err["P"] < 4e-3 and err["T"] < 4e-3 and err["beta"] < 4e-3
     assert err_plateau < 1e-3
+    # the oracle's own 300 steps of the same set-up (tests/golden/make_sod_profile.py), every 8th site
+    gold = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "sod_eta002_300_profile.json")))
+    assert gold["steps"] == steps and gold["nx"] == nx and abs(gold["tau_T"] - tau_T_of(0.002)) < 1e-15
+    sites = np.array(gold["sites"])
+    EE = mac["eps"][0, : nx // 2].cpu().numpy()
+    got = {"n": nn[sites], "eps": EE[sites], "T": TT[sites], "beta": beta[sites]}
+    perr = {k: float(np.max(np.abs(got[k] - np.array(gold[k]))) / np.max(np.abs(gold[k]))) for k in got}
+    print("against the oracle's 300 steps", perr, flush=True)
+    assert max(perr.values()) < 1e-11
