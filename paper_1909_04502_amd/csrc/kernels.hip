@@ -58,13 +58,17 @@ __device__ __forceinline__ void write_fields(const FieldPtrs &fp, int64_t site, 
 }
 
 __device__ __forceinline__ void flag_error(int *err) {
-  // all writers store the same value: a benign race
-  *(volatile int *)err = 1;
+  // all writers store the same value: a benign race, and a plain store (a volatile one would make
+  // the wave wait for every load it has in flight)
+  *err = 1;
 }
 
 template <typename S>
 __device__ __forceinline__ double site_tau(const Tables *__restrict__ tb, const void *tau_field, int64_t site) {
-  if (tau_field == nullptr) return tb->tau;
+  // the lattice's tau through a scalar load, chosen by value (a per-site load through a pointer
+  // picked between the field and the table would be a vector load the wave waits for)
+  const double tau = tb->tau;
+  if (tau_field == nullptr) return tau;
   return (double)((const S *)tau_field)[site];
 }
 
@@ -157,8 +161,8 @@ __device__ __forceinline__ void store_site(S *__restrict__ fout, int64_t sites, 
   for (int i = 0; i < ST::Q; ++i) put_pop<NT>(fout, sites, site_off, i, f[i]);
 }
 
-// Site of this thread.  Blocks form a 1D grid over tiles of blockDim.x x
-// blockDim.y x blockDim.z sites.  The hardware deals consecutive blocks
+// Site of this thread.  Blocks form a 1D grid over tiles of tl.bx x tl.by x
+// tl.bz sites.  The hardware deals consecutive blocks
 // round-robin to the 8 XCDs, each with its own L2.  Tile orders:
 //   xcd == 0: x fastest, then y, then z, as dealt;
 //   xcd == 1: each XCD receives a contiguous range of that order (a band of
@@ -171,14 +175,24 @@ __device__ __forceinline__ void store_site(S *__restrict__ fout, int64_t sites, 
 //             8) * tiles-per-patch blocks; those past the lattice return.
 constexpr int kPatch = 8;
 
-__device__ __forceinline__ bool site_coords(const Tables *__restrict__ tb, int xcd, int &x, int &y, int &z) {
-  const uint32_t gx = (tb->nx + blockDim.x - 1) / blockDim.x;
-  const uint32_t gy = (tb->ny + blockDim.y - 1) / blockDim.y;
-  const uint32_t nb = gridDim.x;
+// The launch shape as kernel arguments (scalar registers): blockDim and gridDim would be read from
+// the dispatch packet by vector loads that every wave waits for before its first tap load.
+struct Tiling {
+  int bx, by, bz;   // block shape
+  int nb;           // blocks in the grid
+  int order;        // tile order (0, 1, 2 as above)
+};
+
+__device__ __forceinline__ bool site_coords(const Tables *__restrict__ tb, const Tiling &tl, int &x, int &y, int &z) {
+  const uint32_t bx = tl.bx, by = tl.by, bz = tl.bz;
+  const uint32_t gx = (tb->nx + bx - 1) / bx;
+  const uint32_t gy = (tb->ny + by - 1) / by;
+  const uint32_t nb = tl.nb;
+  const int xcd = tl.order;
   uint32_t t = blockIdx.x;
   uint32_t tx, ty, tz;
   if (xcd == 2) {
-    const uint32_t py = max(1u, kPatch / blockDim.y), pz = max(1u, kPatch / blockDim.z);   // tile rows per patch
+    const uint32_t py = max(1u, kPatch / by), pz = max(1u, kPatch / bz);   // tile rows per patch
     const uint32_t npy = (gy + py - 1) / py;
     const uint32_t per = gx * py * pz;                                     // tiles per patch
     const uint32_t k = t % 8, l = t / 8;
@@ -195,18 +209,18 @@ __device__ __forceinline__ bool site_coords(const Tables *__restrict__ tb, int x
     ty = (t / gx) % gy;
     tz = t / (gx * gy);
   }
-  x = tx * blockDim.x + threadIdx.x;
-  y = ty * blockDim.y + threadIdx.y;
-  z = tz * blockDim.z + threadIdx.z;
+  x = tx * bx + threadIdx.x;
+  y = ty * by + threadIdx.y;
+  z = tz * bz + threadIdx.z;
   return x < tb->nx && y < tb->ny && z < tb->nz;
 }
 
 template <class ST, int N, typename S, bool DEV, int OCC, bool EXT, bool NT>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(OCC > 0 ? OCC : 1, 8))) k_step(const Tables *__restrict__ tb, const S *__restrict__ fin,
                                               S *__restrict__ fout, const void *__restrict__ tau_field,
-                                              FieldPtrs last, int *err, int xcd) {
+                                              FieldPtrs last, int *err, Tiling tl) {
   int x, y, z;
-  if (!site_coords(tb, xcd, x, y, z)) return;
+  if (!site_coords(tb, tl, x, y, z)) return;
   const int64_t sites = tb->sites;
   const int64_t site = ((int64_t)z * tb->ny + y) * tb->nx + x;
   S f[ST::Q];
@@ -231,9 +245,9 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(OCC > 
 template <class ST, int N, typename S, bool DEV, int OCC, bool NT>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(OCC > 0 ? OCC : 1, 8)))
 k_step_stream(const Tables *__restrict__ tb, const S *__restrict__ fin, S *__restrict__ fout,
-              const void *__restrict__ tau_field, FieldPtrs last, int *err, int xcd) {
+              const void *__restrict__ tau_field, FieldPtrs last, int *err, Tiling tl) {
   int x, y, z;
-  if (!site_coords(tb, xcd, x, y, z)) return;
+  if (!site_coords(tb, tl, x, y, z)) return;
   const int64_t sites = tb->sites;
   const int64_t site = ((int64_t)z * tb->ny + y) * tb->nx + x;
   constexpr int R = ST::RMAX;
@@ -266,9 +280,9 @@ k_step_stream(const Tables *__restrict__ tb, const S *__restrict__ fin, S *__res
 
 template <class ST, int N, typename S, bool DEV>
 __global__ void __launch_bounds__(256) k_moments(const Tables *__restrict__ tb, const S *__restrict__ fin,
-                                                 FieldPtrs out, int *err) {
+                                                 FieldPtrs out, int *err, Tiling tl) {
   int x, y, z;
-  if (!site_coords(tb, 0, x, y, z)) return;
+  if (!site_coords(tb, tl, x, y, z)) return;
   const int64_t sites = tb->sites;
   const int64_t site = ((int64_t)z * tb->ny + y) * tb->nx + x;
   S f[ST::Q];
@@ -283,11 +297,12 @@ template <class ST, int N, typename S, bool DEV>
 __global__ void __launch_bounds__(256) k_init(const Tables *__restrict__ tb, const double *__restrict__ n0,
                                               const double *__restrict__ T0, const double *__restrict__ u0,
                                               const double *__restrict__ noise, double amp, S *__restrict__ fout,
-                                              const void *__restrict__ tau_field, FieldPtrs fields0, int *err) {
+                                              const void *__restrict__ tau_field, FieldPtrs fields0, int *err,
+                                              Tiling tl) {
   constexpr int D = ST::D, Q = ST::Q, NP = Q / 2;
   using B = BasisDef<D, N>;
   int x, y, z;
-  if (!site_coords(tb, 0, x, y, z)) return;
+  if (!site_coords(tb, tl, x, y, z)) return;
   const int64_t sites = tb->sites;
   const int64_t site = ((int64_t)z * tb->ny + y) * tb->nx + x;
   double U[D + 1], uu = 0.0;
@@ -362,6 +377,7 @@ static hipError_t launch_t(const LaunchArgs &a) {
     nb = 8 * ((npatch + 7) / 8) * gx * py * pz;
   }
   dim3 grid((unsigned)nb, 1, 1);
+  const Tiling tl{vr.bx, by, bz, (int)nb, order};
   // the 143 doubles of the 3D massive rule overflow the registers (scratch spills): stream them;
   // 143 floats fit, and there the single load is faster
   constexpr bool kStream = ST::ONLAT && ST::SHIFT && ST::D == 3 && sizeof(S) == 8;
@@ -373,10 +389,10 @@ static hipError_t launch_t(const LaunchArgs &a) {
         constexpr bool E = decltype(ext)::value, T = decltype(nt)::value;
         if constexpr (kStream)
           hipLaunchKernelGGL((k_step_stream<ST, N, S, DEV, O, T>), grid, block, 0, a.stream, a.tb,
-                             (const S *)a.fin, (S *)a.fout, a.tau_field, a.fields, a.err, order);
+                             (const S *)a.fin, (S *)a.fout, a.tau_field, a.fields, a.err, tl);
         else
           hipLaunchKernelGGL((k_step<ST, N, S, DEV, O, E, T>), grid, block, 0, a.stream, a.tb, (const S *)a.fin,
-                             (S *)a.fout, a.tau_field, a.fields, a.err, order);
+                             (S *)a.fout, a.tau_field, a.fields, a.err, tl);
       };
       using O0 = std::integral_constant<int, 0>;
       using O2 = std::integral_constant<int, 2>;
@@ -401,11 +417,11 @@ static hipError_t launch_t(const LaunchArgs &a) {
     }
     case OP_MOMENTS:
       hipLaunchKernelGGL((k_moments<ST, N, S, DEV>), grid, block, 0, a.stream, a.tb, (const S *)a.fin, a.fields,
-                         a.err);
+                         a.err, tl);
       break;
     case OP_INIT:
       hipLaunchKernelGGL((k_init<ST, N, S, DEV>), grid, block, 0, a.stream, a.tb, a.n0, a.T0, a.u0, a.noise,
-                         a.amp, (S *)a.fout, a.tau_field, a.fields, a.err);
+                         a.amp, (S *)a.fout, a.tau_field, a.fields, a.err, tl);
       break;
     default:
       return hipErrorInvalidValue;
