@@ -23,11 +23,9 @@ template <class ST, int N, typename S, bool DEV, int BX, int BY, bool EXT, bool 
 __global__ void __launch_bounds__(BX * BY) k_step_batch(const Tables *__restrict__ tabs,
                                                         const int64_t *__restrict__ elem_off,
                                                         const int2 *__restrict__ tiles, int ntiles,
-                                                        const S *__restrict__ fin, S *__restrict__ fout, int *err,
-                                                        int nblocks) {
-  // XCD k (blocks with blockIdx.x % 8 == k) walks tiles [k*chunk, (k+1)*chunk); the grid size comes
-  // as an argument (gridDim would be a vector load from the dispatch packet)
-  const int per_xcd = nblocks / 8;
+                                                        const S *__restrict__ fin, S *__restrict__ fout, int *err) {
+  // XCD k (blocks with blockIdx.x % 8 == k) walks tiles [k*chunk, (k+1)*chunk)
+  const int per_xcd = gridDim.x / 8;
   const int k = blockIdx.x % 8, b = blockIdx.x / 8;
   const int chunk = (ntiles + 7) / 8;
   const int lo = k * chunk, hi = min(ntiles, lo + chunk);
@@ -53,7 +51,7 @@ __global__ void __launch_bounds__(BX * BY) k_step_batch(const Tables *__restrict
     S f[ST::Q];
     pull_prod<ST, S, false>(tb, fi, sites, o, f);
     const Macro<ST::D> mac = collide_prod<ST, N, S, DEV, true, EXT>(tb, f, tb->tau, EXT ? site_wall(tb, x, y, 0) : -1.0);
-    if (!mac.ok) *err = 1;   // all writers store the same value
+    if (!mac.ok) *(volatile int *)err = 1;
     const uint32_t so = (uint32_t)site * (uint32_t)sizeof(S);
 #pragma unroll
     for (int i = 0; i < ST::Q; ++i) put_pop<NT>(fo, sites, so, i, f[i]);
@@ -66,19 +64,19 @@ static hipError_t launch_batch_t(const BatchArgs &a) {
   switch (a.tile) {
     case 0:
       hipLaunchKernelGGL((k_step_batch<ST, N, S, DEV, 64, 4, EXT, NT>), dim3(nb), dim3(64, 4), 0, a.stream, a.tabs,
-                         a.elem_off, a.tiles, a.ntiles, (const S *)a.fin, (S *)a.fout, a.err, nb);
+                         a.elem_off, a.tiles, a.ntiles, (const S *)a.fin, (S *)a.fout, a.err);
       break;
     case 1:
       hipLaunchKernelGGL((k_step_batch<ST, N, S, DEV, 64, 2, EXT, NT>), dim3(nb), dim3(64, 2), 0, a.stream, a.tabs,
-                         a.elem_off, a.tiles, a.ntiles, (const S *)a.fin, (S *)a.fout, a.err, nb);
+                         a.elem_off, a.tiles, a.ntiles, (const S *)a.fin, (S *)a.fout, a.err);
       break;
     case 2:
       hipLaunchKernelGGL((k_step_batch<ST, N, S, DEV, 128, 2, EXT, NT>), dim3(nb), dim3(128, 2), 0, a.stream, a.tabs,
-                         a.elem_off, a.tiles, a.ntiles, (const S *)a.fin, (S *)a.fout, a.err, nb);
+                         a.elem_off, a.tiles, a.ntiles, (const S *)a.fin, (S *)a.fout, a.err);
       break;
     default:
       hipLaunchKernelGGL((k_step_batch<ST, N, S, DEV, 256, 1, EXT, NT>), dim3(nb), dim3(256, 1), 0, a.stream, a.tabs,
-                         a.elem_off, a.tiles, a.ntiles, (const S *)a.fin, (S *)a.fout, a.err, nb);
+                         a.elem_off, a.tiles, a.ntiles, (const S *)a.fin, (S *)a.fout, a.err);
       break;
   }
   return hipGetLastError();
