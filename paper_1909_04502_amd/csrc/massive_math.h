@@ -269,9 +269,20 @@ __device__ __forceinline__ Macro<ST::D> massive_update(const Tables *__restrict_
     }
   };
   if constexpr (REST && REVERSE) relax_rest();
+  // each group's populations are fetched before any of it is relaxed: in the streaming kernel its
+  // re-loads are then in flight together instead of one pair per memory round trip (a store between
+  // two re-loads makes the wave wait for every access it has in flight)
+  constexpr int GMAX = [] {
+    int mx = 0;
+    for (int g = 0; g < NG; ++g) mx = ST::gcount(g) > mx ? ST::gcount(g) : mx;
+    return mx;
+  }();
 #pragma unroll
   for (int gg = 0; gg < NG; ++gg) {
     const int g = REVERSE ? NG - 1 - gg : gg;
+    A fg[GMAX];
+#pragma unroll
+    for (int j = 0; j < ST::gcount(g); ++j) fg[j] = refetch(ST::gfirst(g) + j);
     A ce[20];
 #pragma unroll
     for (int q = 0; q < AT.n; ++q) {
@@ -303,7 +314,7 @@ __device__ __forceinline__ Macro<ST::D> massive_update(const Tables *__restrict_
         else if (c != 0) b += (A)c * ub[a];
       }
       const A om0 = a0 - b, om1 = a0 + b;
-      const A f0 = refetch(i), f1 = refetch(i + 1);
+      const A f0 = fg[i - ST::gfirst(g)], f1 = fg[i + 1 - ST::gfirst(g)];
       put(i, f0 + om0 * ((E + O) - f0));
       put(i + 1, f1 + om1 * ((E - O) - f1));
     }
