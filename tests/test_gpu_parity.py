@@ -122,6 +122,33 @@ def test_c1_full_length_against_oracle():
     assert max(err.values()) < 1e-11
 
 
+def test_c2_full_length_sampled_against_oracle():
+    """The headline workload over its full 1000 steps: 1024 x 1024, zeta = 1, N = 3 product rule,
+    FP64, tau = 0.8, Taylor-Green u0 = 0.1 with density noise 1e-3 (seed 2), in the default launch
+    configuration; n, eps, T and U at 512 seeded sites against the oracle's own 1000 steps
+    (tests/golden/make_c2_samples.py); the two paths' round-off accumulates over the run."""
+    import json
+    import os
+    from paper_1909_04502_amd import rlbm as R
+    print("[case] C2 full length", flush=True)
+    path = os.path.join(os.path.dirname(__file__), "golden", "c2_1000_samples.json")
+    if not os.path.exists(path):
+        pytest.skip("tests/golden/c2_1000_samples.json not generated (tests/golden/make_c2_samples.py)")
+    gold = json.load(open(path))
+    L, steps = gold["L"], gold["steps"]
+    n, T, u = (torch.tensor(a) for a in W.taylor_green_2d(L, L, 0.1, density_sigma=1e-3, seed=2))
+    lat = R.Lattice(d=2, zeta=1.0, order=3, extent=(L, L), tau=0.8)
+    res = lat.step(lat.init(n, T, u), lat.new_state(), steps)
+    mom = lat.moments(res)
+    lat.sync()
+    ys, xs = torch.tensor(gold["ys"]), torch.tensor(gold["xs"])
+    err = {k: rel(mom[k].cpu()[ys, xs], torch.tensor(gold[k], dtype=torch.float64)) for k in ("n", "eps", "T")}
+    err["U"] = rel(mom["U"].cpu()[1:, ys, xs], torch.tensor(gold["U"], dtype=torch.float64)[1:])
+    print("C2 1000-step errors", err, flush=True)
+    # measured: n 1.1e-13, eps 6.0e-14, T 1.4e-13, U 1.4e-12 (the velocity is ~0.1 of U^0)
+    assert max(err.values()) < 1e-11
+
+
 @pytest.mark.parametrize("name", ["c2_ragged", "n2_open"])
 def test_f32_deviation_storage(name):
     """Float deviations from f^ref with double eigenproblem / EOS: macro fields within 1e-5 after 40 steps."""
