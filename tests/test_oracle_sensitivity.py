@@ -1,24 +1,44 @@
 """The oracle's pins catch plausible mistakes in the oracle itself (CPU only).
 
 Each case plants one slip in the oracle for the duration of the test (a dropped factor, a
-raised index, a flipped sign or direction, a truncated basis, a swapped table column) and
+raised index, a flipped sign or direction, an exponent or factorial off by one, a truncated
+basis, a swapped table column) and
 checks that at least one of the independent pins of the other ``test_oracle_*`` modules then
 fails.  A pin that still passed with the slip planted would not be pinning that part of the
 oracle.  The pins are the same functions the suite runs unmodified; nothing here touches the
 HIP library.
 """
 
+import inspect
+import sys
+import textwrap
+
 import numpy as np
 import pytest
 import torch
 
+import test_oracle_grad as PG
 import test_oracle_quadrature as PQ
+import test_oracle_sod as PD
 import test_oracle_special as PS
 import test_oracle_step as PT
 from oracle import basis as bs
+from oracle import grad as og
 from oracle import lattice as L
 from oracle import mj
 from oracle import quadrature as qd
+from oracle import sod
+
+
+def _edit(mp, owner, name, old, new):
+    """Replace ``owner.name`` by a copy compiled from its own source with the text ``old`` (which
+    must occur exactly once) replaced by ``new``; the copy resolves globals as the original does."""
+    fn = getattr(owner, name)
+    src = textwrap.dedent(inspect.getsource(fn))
+    assert src.count(old) == 1, (name, old)
+    ns = dict(vars(sys.modules[fn.__module__]))
+    exec(compile(src.replace(old, new), f"<{name} with a planted slip>", "exec"), ns)
+    mp.setattr(owner, name, ns[name])
 
 
 def _euclidean_metric(method):
@@ -108,6 +128,54 @@ def plant_ur_weight_columns_swapped(mp):
     mp.setattr(qd, "UR2D_W_50", qd.UR2D_W_34)
 
 
+def plant_interpolation_weights_swapped(mp):
+    # streaming: the weights of the two bracketing sites exchanged (frac <-> 1 - frac)
+    _edit(mp, L.Lattice, "stream", "wgt *= frac[ax] if corner[ax] else 1.0 - frac[ax]",
+          "wgt *= 1.0 - frac[ax] if corner[ax] else frac[ax]")
+
+
+def plant_open_axis_wraps(mp):
+    # an open axis read as periodic (upstream coordinates wrapped instead of clamped)
+    _edit(mp, L.Lattice, "_gather", 'if self.bc[ax] == "periodic":', 'if self.bc[ax] != "wall":')
+
+
+def plant_sphere_average_off_by_one(mp):
+    # the sphere averages behind the 3D direction weights with (a+b+c-1)!! in the denominator
+    _edit(mp, qd, "sphere_average", "dfact(a + b + c + 1)", "dfact(a + b + c - 1)")
+
+
+def plant_massive_energy_power(mp):
+    # Sec. 5.3: the moment system of the weights with the power of p^0 one too high
+    _edit(mp, qd, "massive_group_weights", "A[r, g] = p0 ** row[0] *", "A[r, g] = p0 ** (row[0] + 1) *")
+
+
+def plant_sod_fan_exponent(mp):
+    # App. D: the rarefaction's pressure exponent without its factor 2
+    _edit(mp, sod, "plateau_pressure", "k = 2.0 * math.sqrt(d) / (d + 1)", "k = math.sqrt(d) / (d + 1)")
+
+
+def plant_sod_fan_density(mp):
+    # App. D: the density in the fan with the exponent sqrt(d) instead of sqrt(d)/2
+    _edit(mp, sod, "solution", "n[fan] = nL * ratio ** (sd / 2.0)", "n[fan] = nL * ratio ** sd")
+
+
+def plant_adjoint_eigen_jacobian_sign(mp):
+    # reverse mode: a sign slip in the Jacobian of the Landau eigenproblem
+    _edit(mp, og, "landau_diff", "J[:, :D, D] = -u0", "J[:, :D, D] = u0")
+
+
+def plant_adjoint_eos_newton_sign(mp):
+    # reverse mode: the EOS inversion's Newton correction added instead of subtracted
+    _edit(mp, og, "temperature_diff", "return T0 - (eT.detach() - e) / slope",
+          "return T0 + (eT.detach() - e) / slope")
+
+
+def plant_ce_shear_wrong_dimension(mp):
+    # Sec. 4.1 / App. C: the Chapman-Enskog shear ratio of the (d+1)-dimensional gas
+    orig = mj.ce_shear_ratio
+    mp.setattr(mj, "ce_shear_ratio", lambda zeta, d: orig(zeta, d + 1))
+
+
 # (slip, pins any one of which must fail with it planted)
 CASES = {
     "landau_without_metric": (plant_landau_without_metric,
@@ -132,6 +200,24 @@ CASES = {
                           [(PQ.test_product_2d_exact_to_degree_7, (1.0,))]),
     "ur_weight_columns_swapped": (plant_ur_weight_columns_swapped,
                                   [(PQ.test_ur_rule_exact_to_degree_4_only, ())]),
+    "interpolation_weights_swapped": (plant_interpolation_weights_swapped,
+                                      [(PT.test_interpolated_streaming_conserves_each_population, ("p2m1",))]),
+    "open_axis_wraps": (plant_open_axis_wraps,
+                        [(PT.test_open_axis_budget_of_an_integer_shift, ())]),
+    "sphere_average_off_by_one": (plant_sphere_average_off_by_one,
+                                  [(PQ.test_product_3d_exact_to_degree_7, (1.0,))]),
+    "massive_energy_power": (plant_massive_energy_power,
+                                 [(PQ.test_massive_solver_reproduces_printed_weights_and_window, ())]),
+    "sod_fan_exponent": (plant_sod_fan_exponent,
+                         [(PD.test_shock_jump_conditions, (2,)), (PD.test_rarefaction_fan, (2,))]),
+    "sod_fan_density": (plant_sod_fan_density,
+                        [(PD.test_rarefaction_fan, (2,)), (PD.test_global_conservation, (2,))]),
+    "adjoint_eigen_jacobian_sign": (plant_adjoint_eigen_jacobian_sign,
+                                    [(PG.test_gradient_matches_central_differences, (1,))]),
+    "adjoint_eos_newton_sign": (plant_adjoint_eos_newton_sign,
+                                [(PG.test_gradient_matches_central_differences, (1,))]),
+    "ce_shear_wrong_dimension": (plant_ce_shear_wrong_dimension,
+                                 [(PS.test_ce_shear_limits_and_table2, ())]),
 }
 
 

@@ -48,7 +48,7 @@ def test_rarefaction_fan(d):
     # the fan is a left-moving characteristic family: x/t = (beta - c_s)/(1 - beta c_s), c_s = 1/sqrt(d)
     assert np.allclose(x / t, (f["beta"] - 1 / sd) / (1 - f["beta"] / sd), rtol=1e-12, atol=1e-14)
     # its tail joins the plateau (this checks the root P_C)
-    tail = sod.solution(d, PL, nL, PR, nR, np.array([c["w_T"] * t * (1 - 1e-12)]), t)
+    tail = sod.solution(d, PL, nL, PR, nR, np.array([(c["w_T"] - 1e-12) * t]), t)     # just inside the fan
     assert abs(tail["P"][0] - c["PC"]) < 1e-10 and abs(tail["beta"][0] - c["beta_C"]) < 1e-10
     assert abs(tail["n"][0] - c["n_I"]) < 1e-10
 

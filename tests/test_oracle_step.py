@@ -111,6 +111,31 @@ def test_integer_streaming_is_a_shift():
         assert torch.equal(out[i], torch.roll(g[i], shifts=(dy, dx), dims=(0, 1)))
 
 
+def test_open_axis_budget_of_an_integer_shift():
+    """Zero-gradient open x axis (upstream coordinates clamp to the nearest plane), periodic y.
+    A population moving k > 0 sites along +x loses the k planes that leave through the far face
+    and gains k copies of the near-face plane (the mirror image for k < 0); the y shift only
+    permutes rows.  Checked as a budget of plane sums, not by re-deriving the gather."""
+    q = qd.ur_onlattice_2d()
+    nx, ny = 16, 12
+    lat = L.Lattice(q, 0.9, (nx, ny), bc=("open", "periodic"))
+    g = torch.tensor(np.random.default_rng(4).uniform(size=(q.Q, ny, nx)))
+    out = lat.stream(g)
+    moved = 0
+    for i in range(q.Q):
+        k = int(q.disp[i, 0])
+        col = g[i].sum(0)                                  # plane sums, one per x
+        if k > 0:
+            want = k * col[0] - col[nx - k:].sum()
+        elif k < 0:
+            want = -k * col[-1] - col[:-k].sum()
+        else:
+            want = torch.zeros((), dtype=torch.float64)
+        moved += k != 0
+        assert abs((out[i].sum() - g[i].sum()) - want) < 1e-12 * g[i].sum()
+    assert moved > 0
+
+
 @pytest.mark.parametrize("rule", ["p2m1", "p3m1"])
 def test_interpolated_streaming_conserves_each_population(rule):
     q = RULES[rule]()
