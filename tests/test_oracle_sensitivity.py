@@ -139,6 +139,27 @@ def plant_open_axis_wraps(mp):
     _edit(mp, L.Lattice, "_gather", 'if self.bc[ax] == "periodic":', 'if self.bc[ax] != "wall":')
 
 
+def plant_mj_alternating_sign_dropped(mp):
+    # App. B.1: the (-1)^k of the pairing sum dropped
+    _edit(mp, mj, "mj_tensor_moment", "total = total + (-1) ** k * a_ratio(r - k, zeta, d) * term",
+          "total = total + a_ratio(r - k, zeta, d) * term")
+
+
+def plant_mj_temperature_power(mp):
+    # App. B.1: the rank-r moment scaled by T^r instead of T^(r-1)
+    _edit(mp, mj, "mj_tensor_moment", "return n * T ** (r - 1) * total", "return n * T ** r * total")
+
+
+def plant_wall_plane_off_by_one(mp):
+    # Sec. 7.2: the far wall placed one plane inside the lattice
+    _edit(mp, L.Lattice, "wall_mask", "idx[dim] = grid_shape[dim] - 1", "idx[dim] = grid_shape[dim] - 2")
+
+
+def plant_product_momentum_slip(mp):
+    # the product rule's |p| = sqrt(x^2 + 2 m x) with the factor 2 dropped
+    _edit(mp, qd, "product_2d", "math.sqrt(x[j] * x[j] + 2.0 * m * x[j])", "math.sqrt(x[j] * x[j] + m * x[j])")
+
+
 def plant_sphere_average_off_by_one(mp):
     # the sphere averages behind the 3D direction weights with (a+b+c-1)!! in the denominator
     _edit(mp, qd, "sphere_average", "dfact(a + b + c + 1)", "dfact(a + b + c - 1)")
@@ -202,6 +223,14 @@ CASES = {
                                   [(PQ.test_ur_rule_exact_to_degree_4_only, ())]),
     "interpolation_weights_swapped": (plant_interpolation_weights_swapped,
                                       [(PT.test_interpolated_streaming_conserves_each_population, ("p2m1",))]),
+    "mj_alternating_sign_dropped": (plant_mj_alternating_sign_dropped,
+                                    [(PS.test_mj_moments_brute_force, (2, 1.0, 1.3, (0.3, -0.2)))]),
+    "mj_temperature_power": (plant_mj_temperature_power,
+                             [(PS.test_mj_moments_brute_force, (2, 1.0, 1.3, (0.3, -0.2)))]),
+    "wall_plane_off_by_one": (plant_wall_plane_off_by_one,
+                              [(PT.test_force_accelerates_along_g_and_walls_hold_rest, ())]),
+    "product_momentum_slip": (plant_product_momentum_slip,
+                              [(PQ.test_product_2d_exact_to_degree_7, (1.0,))]),
     "open_axis_wraps": (plant_open_axis_wraps,
                         [(PT.test_open_axis_budget_of_an_integer_shift, ())]),
     "sphere_average_off_by_one": (plant_sphere_average_off_by_one,
