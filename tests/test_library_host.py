@@ -76,6 +76,28 @@ def test_create_validates_before_touching_the_device(rlbm_lib):
     assert rlbm_lib.rlbm_step(None, None, None, 1, None, None) == R.ERR_INVALID_ARG
 
 
+def test_create_rejects_sizes_beyond_the_limits(rlbm_lib):
+    """Extents above 2^20, 3D depths above 65,535 and population planes of 4 GiB or more (the
+    kernels address a plane with 32-bit byte offsets) are refused before any allocation."""
+    from paper_1909_04502_amd import rlbm as R
+    cfg = R.Config()
+    cfg.model = R.Model(d=2, order=3, kind=1, pad_=0, zeta=1.0)
+    cfg.tau = 0.8
+    h = ctypes.c_void_p()
+    cfg.extent[0], cfg.extent[1], cfg.extent[2] = (1 << 20) + 1, 8, 1
+    assert rlbm_lib.rlbm_create(ctypes.byref(cfg), ctypes.byref(h)) == R.ERR_INVALID_ARG
+    cfg.extent[0], cfg.extent[1] = 1 << 16, 1 << 13           # 2^29 sites: an FP64 plane of 4 GiB
+    assert rlbm_lib.rlbm_create(ctypes.byref(cfg), ctypes.byref(h)) == R.ERR_UNSUPPORTED
+    cfg.extent[1] = 1 << 14                                   # float deviations: 2^30 sites x 4 B
+    cfg.storage, cfg.n_ref = R.STORAGE["f32dev"], 1.0
+    assert rlbm_lib.rlbm_create(ctypes.byref(cfg), ctypes.byref(h)) == R.ERR_UNSUPPORTED
+    cfg.storage = 0
+    cfg.model = R.Model(d=3, order=3, kind=1, pad_=0, zeta=1.0)
+    cfg.extent[0], cfg.extent[1], cfg.extent[2] = 4, 4, 65536
+    assert rlbm_lib.rlbm_create(ctypes.byref(cfg), ctypes.byref(h)) == R.ERR_UNSUPPORTED
+    assert not h.value
+
+
 def test_batch_create_validates_before_touching_the_device(rlbm_lib):
     """Mixed orders, storages, 3D or product/UR mixes and tau fields are refused up front."""
     from paper_1909_04502_amd import rlbm as R
