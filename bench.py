@@ -110,23 +110,38 @@ def measured_traffic(name):
     return rec["traffic_bytes"]
 
 
-def copy_bandwidth(nbytes, reps=20):
-    """Device-to-device copy of nbytes (read + write), the measured bandwidth reference."""
+def copy_bandwidth(nbytes, planes=32, reps=20):
+    """Device-to-device copies of nbytes (read + write bytes per second), the measured bandwidth
+    references: torch's copy_, and the library's rlbm_copy_planes with the step kernel's access
+    pattern (one site per thread, `planes` double planes) and as a flat 16-byte-vector copy, each with
+    cached and non-temporal stores."""
     import torch
+    from paper_1909_04502_amd import rlbm as R
     a = torch.empty(nbytes // 8, dtype=torch.float64, device="cuda").fill_(1.0)
     b = torch.empty_like(a)
-    for _ in range(3):
-        b.copy_(a)
-    torch.cuda.synchronize()
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    e0.record()
-    for _ in range(reps):
-        b.copy_(a)
-    e1.record()
-    torch.cuda.synchronize()
-    t = e0.elapsed_time(e1) / reps * 1e-3
-    return 2 * nbytes / t / 1e9
+    stream = torch.cuda.current_stream()
+    kinds = {"torch_copy": lambda: b.copy_(a)}
+    for mode in ("site", "flat"):
+        for nt in (False, True):
+            kinds[f"{mode}{'_nt' if nt else ''}"] = (lambda m=mode, t=nt: R.copy_planes(a, b, planes, m, t))
+    out = {}
+    for name, fn in kinds.items():
+        for _ in range(3):
+            fn()
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        t = e0.elapsed_time(e1) / reps * 1e-3
+        out[name] = round(2 * nbytes / t / 1e9, 1)
+    assert torch.equal(a, b)
+    del a, b
+    torch.cuda.empty_cache()
+    return out
 
 
 def batched(count, warmup, steps, storage="f64"):
@@ -231,22 +246,25 @@ def adjoint_leg(L, warmup, steps):
     nrun = 2000
     _, _, ut = W.taylor_green_2d(L, L, 0.08, phase=(0.3, -0.2))
     ut = torch.tensor(ut, device="cuda")
-    taug = tau.clone().cuda().requires_grad_(True)
-    u0g = torch.tensor(u).cuda().requires_grad_(True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    U = A.run(lat, taug, u0g, torch.tensor(n), torch.tensor(T), nrun, every=45)
-    loss = A.velocity_loss(U, ut)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    loss.backward()
-    torch.cuda.synchronize()
-    t2 = time.perf_counter()
+    n_t, T_t = torch.tensor(n), torch.tensor(T)
+    for rep in range(2):                 # the first run captures the segment graphs; the second is timed
+        taug = tau.clone().cuda().requires_grad_(True)
+        u0g = torch.tensor(u).cuda().requires_grad_(True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        U = A.run(lat, taug, u0g, n_t, T_t, nrun, every=45)
+        loss = A.velocity_loss(U, ut)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        loss.backward()
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
     out = {"workload": f"{L}x{L} zeta=1 N=3 f32dev with tau field", "forward_ms": round(t_fwd * 1e3, 5),
            "run_steps": nrun, "run_checkpoint_every": 45,
            "run_forward_ms_per_step": round((t1 - t0) / nrun * 1e3, 5),
            "run_backward_ms_per_step": round((t2 - t1) / nrun * 1e3, 5),
            "run_backward_over_forward": round((t2 - t1) / (t1 - t0), 3),
+           "run_forward_over_step_kernel": round((t1 - t0) / nrun / t_fwd, 3),
            "adjoint_ms": round(t_adj * 1e3, 5), "adjoint_over_forward": round(t_adj / t_fwd, 3),
            "adjoint_MLUPS": round(sites / t_adj / 1e6, 2), "adjoint_achieved_GBs": round(ab / t_adj / 1e9, 1),
            "adjoint_frac": round(ab / t_adj / 1e9 / HBM_PEAK_GBS, 4)}
@@ -256,14 +274,16 @@ def adjoint_leg(L, warmup, steps):
 
 
 def shock_tube_3d(L, warmup, steps, autotune=True):
-    """3D shock tube: zeta = 1, N = 3, Q = 104, L^3 with open x and periodic y, z, tau = 0.6, left state
-    n = 8/3, T = 1.5 for x < L/2, right n = 1, T = 1, u = 0; float-deviation storage (832 B per site)."""
+    """3D shock tube: zeta = 1, N = 3, Q = 104, L^3 with open x and periodic y, z, left state n = 8/3,
+    T = 1.5 for x < L/2, right n = 1, T = 1, u = 0; float-deviation storage (832 B per site).  Timed at
+    tau = 0.8, the set-up the 2000-step parity run validates: at tau = 0.6 the scheme itself (the FP64
+    oracle on the same set-up) turns non-physical at step 113; the step costs the same at any tau."""
     import torch
     import workloads as W
     from paper_1909_04502_amd import rlbm as R
     n, T, u = W.riemann_3d(L, L, L, L // 2, 8.0 / 3.0, 1.5, 1.0, 1.0)
     lat = R.Lattice(d=3, zeta=1.0, order=3, extent=(L, L, L), bc=("open", "periodic", "periodic"),
-                    storage="f32dev", tau=0.6)
+                    storage="f32dev", tau=0.8)
     tune = lat.autotune(steps=3) if autotune else None
     fa = lat.init(torch.tensor(n), torch.tensor(T), torch.tensor(u))
     del n, T, u
@@ -271,7 +291,8 @@ def shock_tube_3d(L, warmup, steps, autotune=True):
     t = time_steps(lat, fa, fb, warmup, steps)
     sites = L ** 3
     b = 2 * lat.Q * 4 * sites
-    out = {"workload": f"3D shock tube {L}^3, zeta=1 N=3 Q={lat.Q}, open x, tau=0.6, f32dev",
+    out = {"workload": f"3D shock tube {L}^3, zeta=1 N=3 Q={lat.Q}, open x, tau=0.8 (the validated set-up; "
+                       "tau=0.6 turns non-physical at step 113 in the FP64 oracle itself), f32dev",
            "MLUPS": round(sites / t / 1e6, 2), "ms_per_step": round(t * 1e3, 4),
            "achieved_GBs": round(b / t / 1e9, 1), "frac": round(b / t / 1e9 / HBM_PEAK_GBS, 4),
            "variant": lat.variant, "autotune_ms": [round(x, 4) for x in tune] if tune else None}
@@ -487,12 +508,20 @@ def cpu_baseline(seconds):
     for _ in range(KERR):                       # untimed: the reference for the error statement
         f = ol.collide(ol.stream(f))
     ref = (f.clone(), ol.macro(ol.stream(f)))
-    steps = 0
-    t0 = time.perf_counter()
-    while time.perf_counter() - t0 < seconds or steps < 2:
-        f = ol.collide(ol.stream(f))
-        steps += 1
-    dt = time.perf_counter() - t0
+    def timed(budget, f):
+        steps = 0
+        t0 = time.perf_counter()
+        while time.perf_counter() - t0 < budget or steps < 2:
+            f = ol.collide(ol.stream(f))
+            steps += 1
+        return steps, time.perf_counter() - t0, f
+    threads = torch.get_num_threads()
+    steps, dt, f = timed(seconds, f)
+    torch.set_num_threads(1)
+    try:
+        steps1, dt1, _ = timed(seconds / 3.0, f)
+    finally:
+        torch.set_num_threads(threads)
     errors = {"steps": KERR, "lattice": f"{L}x{L}"}
     for storage in ("f64", "f32dev"):
         lat = R.Lattice(d=2, zeta=1.0, order=3, extent=(L, L), tau=0.8, storage=storage)
@@ -515,9 +544,11 @@ def cpu_baseline(seconds):
             model = next((ln.split(":", 1)[1].strip() for ln in fh if ln.startswith("model name")), model)
     except OSError:
         pass
-    return {"value": L * L * steps / dt / 1e6, "unit": "MLUPS", "cores": torch.get_num_threads(),
+    return {"value": L * L * steps / dt / 1e6, "unit": "MLUPS", "cores": threads,
             "kind": "oracle",
             "sample": f"{steps} steps of a {L}x{L} lattice of the same workload ({dt:.1f} s, torch float64 on CPU)",
+            "one_core": {"value": L * L * steps1 / dt1 / 1e6, "unit": "MLUPS", "cores": 1,
+                         "sample": f"{steps1} steps of the same {L}x{L} lattice ({dt1:.1f} s)"},
             "cpu": model, "host_cpus": os.cpu_count(), "gpu_error_vs_oracle": errors}
 
 
@@ -597,9 +628,11 @@ def main():
     if not args.no_forcing:
         out["forcing_walls"] = forcing_leg(L, args.warmup, args.steps)
     if not args.no_copy:
-        cb = copy_bandwidth(Q * 8 * sites)
-        out["roofline"]["copy_GBs"] = round(cb, 1)
-        out["roofline"]["frac_of_copy"] = round(achieved / cb, 4)
+        cb = copy_bandwidth(Q * 8 * sites, planes=Q)
+        best = max(cb.values())
+        out["roofline"]["copy_GBs"] = cb
+        out["roofline"]["copy_ceiling_GBs"] = best
+        out["roofline"]["frac_of_copy"] = round(achieved / best, 4)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.cpu_seconds)
     print(json.dumps(out), flush=True)

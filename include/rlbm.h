@@ -90,8 +90,8 @@ typedef enum { RLBM_F64 = 0, RLBM_F32_DEV = 1 } rlbm_storage;
 /* RLBM_WALL: reads clamp as RLBM_OPEN, and the first and last plane of the
  * axis are no-slip walls whose collision is replaced by the local equilibrium
  * at zero flow speed (the site's own n and T, or a prescribed T:
- * rlbm_config.wall_T; the walls of the forcing validation, Sec. 7.2, and the
- * plates of the thermal-conductivity measurement, Sec. 7.1).  Product and
+ * rlbm_config.wall_T; the walls of the forcing validation, Sec. 8.1, and the
+ * plates of the thermal-conductivity measurement, Sec. 7.2).  Product and
  * massive rules (not the 3D massive rule in double storage). */
 typedef enum { RLBM_PERIODIC = 0, RLBM_OPEN = 1, RLBM_WALL = 2 } rlbm_bc;
 typedef enum {
@@ -140,7 +140,7 @@ typedef struct {
                         * RLBM_ERR_UNSUPPORTED for product rules. */
   double wall_T[3][2]; /* RLBM_WALL axes: the temperature imposed on the first [a][0] and last
                         * [a][1] plane (the heated and cooled plates of the thermal-conductivity
-                        * measurement, Sec. 7.1); 0 = the site's own temperature.  The wall
+                        * measurement, Sec. 7.2); 0 = the site's own temperature.  The wall
                         * site keeps its own n.  >= 0; non-zero only on wall axes. */
 } rlbm_config;
 
@@ -321,6 +321,20 @@ rlbm_status rlbm_get_store_mode(const rlbm_lattice *h, int32_t *mode, int32_t *n
  * and every member's rows must be multiples of 64 bytes. */
 rlbm_status rlbm_batch_set_store_mode(rlbm_batch *b, int32_t mode);
 rlbm_status rlbm_batch_get_store_mode(const rlbm_batch *b, int32_t *mode, int32_t *nontemporal);
+
+/* ---------------------------------------------------------- measurement
+ *
+ * The memory ceiling the step kernels are measured against (not part of the
+ * method).  Copies `planes` population planes of `sites` elements of
+ * elem_bytes (4 or 8) from src to dst, device buffers of the caller that must
+ * not overlap.  mode 0 ("site"): one thread per site loads its element of
+ * every plane, then stores them, the access pattern of the fused update
+ * (planes 32 or 104, else RLBM_ERR_UNSUPPORTED); mode 1 ("flat"): the same
+ * bytes as 16-byte vectors (16-byte aligned buffers and size).  nontemporal
+ * = 1 writes with non-temporal stores as rlbm_set_store_mode does.
+ * Asynchronous on `stream`. */
+rlbm_status rlbm_copy_planes(const void *src, void *dst, int64_t sites, int32_t planes, int32_t elem_bytes,
+                             int32_t mode, int32_t nontemporal, hipStream_t stream);
 
 #ifdef __cplusplus
 }

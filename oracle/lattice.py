@@ -35,9 +35,9 @@ Boundaries: periodic, or "open" = zero-gradient: a read outside the grid
 takes the value of the nearest boundary plane, or "wall": the open read plus
 no-slip walls on the first and last plane of the axis, where the collision is
 replaced by the local equilibrium at zero flow speed (n and T of the site,
-U = (1, 0, ...)), as in the forcing validation of Sec. 7.2; a wall plane may
+U = (1, 0, ...)), as in the forcing validation of Sec. 8.1; a wall plane may
 instead hold a prescribed temperature (the heated and cooled plates of the
-thermal-conductivity measurement, Sec. 7.1), keeping the site's own n.
+thermal-conductivity measurement, Sec. 7.2), keeping the site's own n.
 """
 from __future__ import annotations
 

@@ -25,6 +25,10 @@ Rules:
   w_{2j} = (8.889e-2, 3.481e-2, 4.219e-4) to the (+-3,+-4) group, the only
   assignment with sum_i w_i = 1; the order-3 list is read the same way (again
   the only normalised assignment).
+* ``ur_onlattice_3d``: the printed (3+1)-d massless rule of order 3 (App. H.1, the rule of the 3D
+  Sod tube of Sec. 8.2): groups (+-4,+-4,+-3)_FS, (+-5,+-4,0)_FS, (+-6,+-2,+-1)_FS (|n_i|^2 = 41),
+  four shells; the printed weights read shell-major with the groups in the listed order within a
+  shell (the only normalised assignment that is exact to degree 6).
 * ``product_2d`` / ``product_3d``: off-lattice product rules.  The paper names
   off-lattice schemes but does not build them (Sec. 5.3, last paragraphs;
   Sec. 7.3 closing remark); this is the reading used here.  In d = 2,
@@ -75,6 +79,17 @@ UR2D_W_50 = (0.0, 0.0, 0.0017535654166088)                                  # (+
 UR2D3_SHELLS = (0.3225476896193923, 1.7457611011583465, 4.5366202969211279, 9.3950709123011331)
 UR2D3_W_50 = (0.0, 0.0410206173754781, 0.0044457884155769, 0.0000616926157132)
 UR2D3_W_34 = (0.0753942630427042, 0.0241670278669858, 0.0026380943565871, 0.0000365655303385)
+
+# Printed (3+1)-d ultra-relativistic order-3 rule (App. H.1): the full-symmetric groups of (4,4,3),
+# (5,4,0) and (6,2,1), every vector of length sqrt(41) (v0 = 1/sqrt(41), Sec. 8.2), on four energy
+# shells (the generalized Gauss-Laguerre nodes with alpha = 1: d^3p/p^0 = |p| d|p| dOmega); the
+# printed list read shell-major with the groups in the listed order within each shell.
+UR3D3_GROUPS = ((4, 4, 3), (5, 4, 0), (6, 2, 1))
+UR3D3_SHELLS = (0.7432919279814314, 2.5716350076462784, 5.7311787516890996, 10.953894312683190)
+UR3D3_W = ((0.0, 0.0, 0.0093098040253911),
+           (0.0085195569675087, 0.0, 0.0056909667738262),
+           (0.0013041770173120, 0.0, 0.0008932820065742),
+           (0.0000029126213348, 0.0000338363537565, 0.0000090390475856))   # [shell][group]
 
 DIRS_UR2D = [(3, 4), (-3, -4), (-3, 4), (3, -4), (4, 3), (-4, -3), (-4, 3), (4, -3),
              (5, 0), (-5, 0), (0, 5), (0, -5)]
@@ -129,6 +144,27 @@ def ur_onlattice_2d(order: int = 2) -> Quadrature:
             w.append(wj)
             disp.append((float(nx), float(ny)))
     return Quadrature(2, 0.0, order, np.array(p), np.array(w), np.array(disp), True)
+
+
+def ur_onlattice_3d(order: int = 3) -> Quadrature:
+    """Printed massless (3+1)-d rule of order 3 (App. H.1): 288 non-zero populations, integer
+    displacements n_i of length sqrt(41) (speed of light, v0 = 1/sqrt(41)), p_i = p^0_j (1, n_i/|n_i|).
+    Population order: shell-major; within a shell the groups with non-zero weight in the listed order,
+    each group in ``fs_group`` order (antipodes adjacent)."""
+    if order != 3:
+        raise ValueError("the (3+1)-d printed massless rule is built for order 3")
+    p, w, disp = [], [], []
+    for j, p0 in enumerate(UR3D3_SHELLS):
+        for g, gen in enumerate(UR3D3_GROUPS):
+            wj = UR3D3_W[j][g]
+            if wj == 0.0:
+                continue
+            for n in fs_group(gen):
+                norm = math.sqrt(sum(c * c for c in n))          # sqrt(41) for every vector
+                p.append((p0,) + tuple(p0 * c / norm for c in n))
+                w.append(wj)
+                disp.append(tuple(float(c) for c in n))
+    return Quadrature(3, 0.0, order, np.array(p), np.array(w), np.array(disp), True)
 
 
 def product_2d(m: float, order: int) -> Quadrature:

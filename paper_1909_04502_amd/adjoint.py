@@ -7,7 +7,10 @@ then segment by segment (last first) the states of the segment are
 recomputed from its checkpoint and lam_t = rlbm_adjoint_step(B_{t-1},
 lam_{t+1}) runs down to the segment start; finally rlbm_init_vjp gives
 dL/du0.  dL/dtau(x) is accumulated by every reverse kernel.  Memory: the
-checkpoints plus one segment of states.
+checkpoints plus one segment of states.  The tau field of the forward run is
+kept and restored into the lattice before the backward recomputes, so other
+runs on the same lattice between a forward and its backward do not change
+the gradient.
 """
 from __future__ import annotations
 
@@ -23,8 +26,10 @@ class _Run(torch.autograd.Function):
             raise ValueError("the lattice must be created with a tau_field tensor")
         lat.tau_field.copy_(tau_field.detach().to(lat.tau_field.dtype))
         u0d = u0.detach().to(torch.float64)
-        cur = lat.init(n0, T0, u0d, noise, amp)
-        nxt = lat.new_state()
+        # the segments run in a buffer pair kept by the lattice: the library caches the launch
+        # graph of a multi-step call per buffer pair, so every run replays the same graphs
+        cur, nxt = _work_pair(lat)
+        lat.init(n0, T0, u0d, noise, amp, out=cur)
         ckpt = {0: cur.clone()}
         t = 0
         while t < nsteps:                                  # one library call per checkpoint segment
@@ -35,9 +40,12 @@ class _Run(torch.autograd.Function):
             t += k
             if t < nsteps:
                 ckpt[t] = cur.clone()
-        final = cur
+        final = cur.clone()
         fields = lat.moments(final)
         ctx.lat, ctx.ckpt, ctx.final = lat, ckpt, final
+        # the kernels read tau through the lattice's own buffer, which another run on the same
+        # lattice may overwrite before this backward: keep this run's copy to restore there
+        ctx.tau_saved = lat.tau_field.clone()
         ctx.args = (n0, T0, u0d, noise, amp, nsteps, every)
         ctx.tau_dtype = tau_field.dtype
         return fields["U"]
@@ -46,21 +54,32 @@ class _Run(torch.autograd.Function):
     def backward(ctx, gU):
         lat = ctx.lat
         n0, T0, u0d, noise, amp, nsteps, every = ctx.args
+        lat.tau_field.copy_(ctx.tau_saved)
         lam = lat.moments_vjp(ctx.final, gU=gU.contiguous())
+        lam_spare = torch.empty_like(lam)
         dtau = torch.zeros(lat.grid_shape, dtype=torch.float64, device="cuda")
+        seg = [lat.new_state() for _ in range(max(0, min(every, nsteps) - 1))]
         for s in sorted(ctx.ckpt, reverse=True):
             e = min(s + every, nsteps)
             states = [ctx.ckpt[s]]
-            for _ in range(s + 1, e):                      # B_{s+1} .. B_{e-1}
-                nxt = lat.new_state()
-                lat.step(states[-1], nxt, 1)
-                states.append(nxt)
+            for k in range(s + 1, e):                      # B_{s+1} .. B_{e-1}
+                lat.step(states[-1], seg[k - s - 1], 1)
+                states.append(seg[k - s - 1])
             for t in range(e, s, -1):                      # lam_t from B_{t-1} and lam_{t+1}
-                lam = lat.adjoint_step(states[t - 1 - s], lam, dtau=dtau)
+                out = lat.adjoint_step(states[t - 1 - s], lam, lam=lam_spare, dtau=dtau)
+                lam_spare, lam = lam, out
             del states
         du0 = lat.init_vjp(n0, T0, u0d, lam, noise, amp, dtau=dtau)
         lat.sync()
         return dtau.to(ctx.tau_dtype), du0, None, None, None, None, None, None, None
+
+
+def _work_pair(lat: Lattice):
+    pair = getattr(lat, "_run_pair", None)
+    if pair is None:
+        pair = (lat.new_state(), lat.new_state())
+        lat._run_pair = pair
+    return pair
 
 
 def run(lat: Lattice, tau_field, u0, n0, T0, nsteps: int, every: int = 45, noise=None, amp: float = 0.0):

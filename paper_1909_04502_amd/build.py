@@ -9,10 +9,11 @@ import os
 import shutil
 import subprocess
 import sys
+from concurrent.futures import ThreadPoolExecutor
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-SOURCES = ["csrc/api.hip", "csrc/kernels.hip", "csrc/adjoint.hip", "csrc/batch.hip", "csrc/precompute.cpp",
-           "csrc/massive.cpp"]
+SOURCES = ["csrc/kernels.hip", "csrc/api.hip", "csrc/adjoint.hip", "csrc/batch.hip", "csrc/bandwidth.hip",
+           "csrc/precompute.cpp", "csrc/massive.cpp"]
 LIB = os.path.join(HERE, "librlbm.so")
 
 FLAGS = [
@@ -45,11 +46,12 @@ def _run(cmd, verbose):
         print(err, file=sys.stderr)
 
 
-def build(verbose: bool = False) -> str:
-    """Compile every source to an object file under _build/, then link librlbm.so."""
+def build(verbose: bool = False, jobs: int = 0) -> str:
+    """Compile every source to an object file under _build/ (in parallel, at most `jobs` at once;
+    0 = one per source up to the CPU count), then link librlbm.so."""
     bdir = os.path.join(HERE, "_build")
     os.makedirs(bdir, exist_ok=True)
-    objs = []
+    cmds, objs = [], []
     for src in SOURCES:
         obj = os.path.join(bdir, os.path.basename(src) + ".o")
         path = os.path.join(HERE, src)
@@ -58,8 +60,12 @@ def build(verbose: bool = False) -> str:
         else:   # host-only C++ (no device code)
             cmd = [hipcc(), "-O3", "-std=c++17", "-fPIC", "-x", "c++", "-D__HIP_PLATFORM_AMD__",
                    "-I/opt/rocm/include", "-c", path, "-o", obj]
-        _run(cmd, verbose)
+        cmds.append(cmd)
         objs.append(obj)
+    workers = jobs if jobs > 0 else max(1, min(len(cmds), os.cpu_count() or 1))
+    with ThreadPoolExecutor(max_workers=workers) as ex:
+        for fut in [ex.submit(_run, c, verbose) for c in cmds]:
+            fut.result()
     tmp = LIB + ".tmp"
     _run([hipcc(), "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs, verbose)
     os.replace(tmp, LIB)

@@ -198,8 +198,9 @@ rlbm_status rlbm_create(const rlbm_config *cfg, rlbm_lattice **out) {
   if (!std::isfinite(cfg->tau_T)) return fail(RLBM_ERR_INVALID_ARG, "tau_T must be finite");
   if (cfg->tau_T != 0.0 && m.kind == RLBM_QUAD_PRODUCT)
     return fail(RLBM_ERR_UNSUPPORTED, "the temperature-dependent tau is built for the on-lattice rules");
-  if (m.kind == RLBM_QUAD_MASSIVE_ONLATTICE && (cfg->force[0] != 0.0 || cfg->force[1] != 0.0 || cfg->force[2] != 0.0))
-    return fail(RLBM_ERR_UNSUPPORTED, "the external force is built for product rules");
+  if (m.kind == RLBM_QUAD_MASSIVE_ONLATTICE && m.d == 3 && cfg->storage == RLBM_F64 &&
+      (cfg->force[0] != 0.0 || cfg->force[1] != 0.0 || cfg->force[2] != 0.0))
+    return fail(RLBM_ERR_UNSUPPORTED, "external force: the streaming kernel of the 3D massive rule has none");
   if (cfg->storage != RLBM_F64 && cfg->storage != RLBM_F32_DEV) return fail(RLBM_ERR_INVALID_ARG, "bad storage");
   if (!(cfg->tau > 0.0) || !std::isfinite(cfg->tau)) return fail(RLBM_ERR_INVALID_ARG, "tau must be > 0");
   if (cfg->storage == RLBM_F32_DEV && !(cfg->n_ref > 0.0)) return fail(RLBM_ERR_INVALID_ARG, "n_ref must be > 0");
@@ -263,7 +264,7 @@ rlbm_status rlbm_create(const rlbm_config *cfg, rlbm_lattice **out) {
     for (int a = 0; a < 3; ++a)
       for (int e = 0; e < 2; ++e) t->wallT[a][e] = a < m.d ? cfg->wall_T[a][e] : 0.0;
     // the force term carries the mass: nothing to add for zeta = 0
-    t->has_force = (m.zeta > 0.0 && m.kind == RLBM_QUAD_PRODUCT &&
+    t->has_force = (m.zeta > 0.0 && m.kind != RLBM_QUAD_UR_ONLATTICE &&
                     (t->g[0] != 0.0 || t->g[1] != 0.0 || t->g[2] != 0.0)) ? 1 : 0;
   }
   if (rc) {
@@ -507,6 +508,11 @@ static hipError_t batch_build_tiles(rlbm_batch *b) {
     const int n = ((nx + bx - 1) / bx) * ((ny + by - 1) / by);
     for (int t = 0; t < n; ++t) tl.push_back(make_int2((int)l, t));
   }
+  // the cached graph's kernel arguments name the old tile list: drop it before that list is freed
+  if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
+  b->gexec = nullptr;
+  b->g_fa = b->g_fb = nullptr;
+  b->g_n = b->g_variant = b->g_nt = -1;
   if (b->d_tiles) (void)hipFree(b->d_tiles);
   b->d_tiles = nullptr;
   b->ntiles = (int)tl.size();

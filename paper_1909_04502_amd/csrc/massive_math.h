@@ -18,7 +18,10 @@
 //    = sum_e n_i^e [w_g v_g^|e| (a'_(0,e) + (p0_g - m) a'_(1,e))]: per group
 //    one coefficient per angular monomial e, per population integer powers
 //    n_i^e; the rest population keeps only the constant monomial, w_r a'_(0,0);
-//  * relaxation Omega_i = (U^0 - v0 n_i . U)/tau.
+//  * relaxation Omega_i = (U^0 - v0 n_i . U)/tau;
+//  * external force (Sec. 5.4, scheme B, EXT builds): the update adds
+//    (m/T) ((g . v_i) U^0 - g . U) f^eq_i with v_i = v0 n_i, so per population
+//    one integer dot product g . n_i on top of the relaxation.
 #pragma once
 #include "prod_math.h"
 
@@ -261,11 +264,30 @@ __device__ __forceinline__ Macro<ST::D> massive_update(const Tables *__restrict_
   A ub[D];
 #pragma unroll
   for (int a = 0; a < D; ++a) ub[a] = (A)(tb->v0 * mac.U[a + 1] * itau);
+  // ---- step 6, external force (Sec. 5.4, scheme B): + (m/T) ((g . v_i) U^0 - g . U) f^eq_i ----
+  const bool force = EXT && tb->has_force && !wall;
+  A cF = 0, gU = 0, gv[D];
+#pragma unroll
+  for (int a = 0; a < D; ++a) gv[a] = 0;
+  if (force) {
+    cF = (A)(tb->m / mac.T);
+    double acc = 0.0;
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+      acc += tb->g[a] * mac.U[a + 1];
+      gv[a] = (A)(tb->v0 * tb->g[a] * mac.U[0]);   // (g . v_i) U^0 = sum_a n_i^a gv[a]
+    }
+    gU = (A)acc;
+  }
+  // full equilibrium of population i from its deviation part (float-deviation storage)
+  auto feq_full = [&](int i, A e) { return DEV ? e + tab<A>(tb->fref[i], tb->freff[i]) : e; };
   auto relax_rest = [&]() {
     if constexpr (REST) {
       const A E = ap[0] * tab<A>(tb->wrest, tb->wrestf);   // the constant monomial is basis entry 0
       const A fr = refetch(Q - 1);
-      put(Q - 1, fr + a0 * (E - fr));
+      A out = fr + a0 * (E - fr);
+      if (force) out -= cF * gU * feq_full(Q - 1, E);
+      put(Q - 1, out);
     }
   };
   if constexpr (REST && REVERSE) relax_rest();
@@ -315,8 +337,22 @@ __device__ __forceinline__ Macro<ST::D> massive_update(const Tables *__restrict_
       }
       const A om0 = a0 - b, om1 = a0 + b;
       const A f0 = fg[i - ST::gfirst(g)], f1 = fg[i + 1 - ST::gfirst(g)];
-      put(i, f0 + om0 * ((E + O) - f0));
-      put(i + 1, f1 + om1 * ((E - O) - f1));
+      A out0 = f0 + om0 * ((E + O) - f0);
+      A out1 = f1 + om1 * ((E - O) - f1);
+      if (force) {
+        A gn = 0;   // (g . v_i) U^0 of the pair's first member; the second has the opposite sign
+#pragma unroll
+        for (int a = 0; a < D; ++a) {
+          const int c = ST::dir(i, a);
+          if (c == 1) gn += gv[a];
+          else if (c == -1) gn -= gv[a];
+          else if (c != 0) gn += (A)c * gv[a];
+        }
+        out0 += cF * (gn - gU) * feq_full(i, E + O);
+        out1 += cF * (-gn - gU) * feq_full(i + 1, E - O);
+      }
+      put(i, out0);
+      put(i + 1, out1);
     }
   }
   if constexpr (REST && !REVERSE) relax_rest();

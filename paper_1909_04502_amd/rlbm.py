@@ -144,6 +144,8 @@ def lib():
     L.rlbm_batch_get_store_mode.argtypes = [c_void_p, POINTER(c_int32), POINTER(c_int32)]
     L.rlbm_batch_autotune.restype = st
     L.rlbm_batch_autotune.argtypes = [c_void_p, c_void_p, c_void_p, c_int32, c_void_p, c_void_p]
+    L.rlbm_copy_planes.restype = st
+    L.rlbm_copy_planes.argtypes = [c_void_p, c_void_p, c_int64, c_int32, c_int32, c_int32, c_int32, c_void_p]
     _lib = L
     _check_single_hip_runtime()
     return L
@@ -181,6 +183,16 @@ def massive_window(zeta: float, order: int, d: int = 2):
     lo, hi = c_double(0.0), c_double(0.0)
     _check(L.rlbm_massive_window(ctypes.byref(m), ctypes.byref(lo), ctypes.byref(hi)))
     return lo.value, hi.value
+
+
+def copy_planes(src, dst, planes: int, mode: str = "site", nontemporal: bool = False):
+    """dst <- src with rlbm_copy_planes: "site" copies `planes` SoA planes one site per thread (the
+    step kernels' access pattern), "flat" as 16-byte vectors.  Both tensors on the device, same size."""
+    assert src.is_cuda and dst.is_cuda and src.numel() == dst.numel() and src.dtype == dst.dtype
+    es = src.element_size()
+    sites = src.numel() // planes
+    _check(lib().rlbm_copy_planes(_ptr(src), _ptr(dst), int(sites), int(planes), int(es),
+                                  {"site": 0, "flat": 1}[mode], int(bool(nontemporal)), _stream()))
 
 
 def _stream():

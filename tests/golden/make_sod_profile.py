@@ -2,7 +2,7 @@
 half of the ultra-relativistic Sod tube after 300 steps, computed by the FP64 oracle alone: the
 printed order-3 massless rule (App. H.2), 6400 x 5 sites with the mirror image of the left state
 (T_L = 1, n_L = 1 for the first 1600 sites, P_L / P_R = 5.43, T_R = 0.475), tau = 1/2 + tau_T / T
-for eta/s = 0.002 (Sec. 7, the inviscid test).  Run from the repository root:
+for eta/s = 0.002 (Sec. 8.2, the inviscid test).  Run from the repository root:
     python tests/golden/make_sod_profile.py
 It takes under a minute on the CPU."""
 import json
@@ -37,7 +37,7 @@ def main():
         fs = ol.collide(ol.stream(fs))
     mac = ol.macro(ol.stream(fs))          # the moments call's fields for f*_STEPS
     sites = list(range(0, NX // 2, EVERY))
-    out = {"citation": "Sec. 7 (ultra-relativistic Sod tube, inviscid test, eta/s = 0.002) with the "
+    out = {"citation": "Sec. 8.2 (ultra-relativistic Sod tube, inviscid test, eta/s = 0.002) with the "
                        "printed order-3 massless rule of App. H.2; FP64 oracle only",
            "nx": NX, "ny": NY, "split": SPLIT, "steps": STEPS, "tau_T": tau_T, "sites": sites,
            "n": mac["n"][0, sites].tolist(), "eps": mac["eps"][0, sites].tolist(),

@@ -62,6 +62,33 @@ def test_gradient_matches_oracle(nsteps, every):
     assert rel(gu0, gu00) < 1e-10
 
 
+def test_interleaved_runs_keep_their_own_tau():
+    """Two differentiable runs on one lattice with different tau fields, then the backward of the
+    first: its gradient equals that of a lone forward and backward (the second run overwrites the
+    lattice's tau buffer and its work buffers in between)."""
+    from paper_1909_04502_amd import adjoint as A
+    from paper_1909_04502_amd import rlbm as R
+    print("[case] interleaved runs", flush=True)
+    nx, ny, nsteps, every = 24, 20, 6, 4
+    n, T, u, tau, ut = problem(nx, ny)
+    _, _, _, tau2, _ = problem(nx, ny, seed=11)
+    lat = R.Lattice(d=2, zeta=1.0, order=3, extent=(nx, ny), tau=0.8, tau_field=tau.clone())
+    grads = []
+    for interleave in (False, True):
+        taug = tau.clone().cuda().requires_grad_(True)
+        u0g = u.clone().cuda().requires_grad_(True)
+        L1 = A.velocity_loss(A.run(lat, taug, u0g, n, T, nsteps, every=every), ut.cuda())
+        if interleave:
+            t2 = tau2.clone().cuda().requires_grad_(True)
+            u2 = (0.5 * u).clone().cuda().requires_grad_(True)
+            L2 = A.velocity_loss(A.run(lat, t2, u2, n, T, nsteps, every=every), ut.cuda())
+            assert abs(L2.item() - L1.item()) > 1e-9 * abs(L1.item())
+        L1.backward()
+        grads.append((L1.item(), taug.grad.detach().clone(), u0g.grad.detach().clone()))
+    assert grads[0][0] == grads[1][0]
+    assert rel(grads[1][1], grads[0][1]) == 0.0 and rel(grads[1][2], grads[0][2]) == 0.0
+
+
 def test_single_adjoint_step_dot_product():
     """<w, (step(B + h v) - step(B - h v)) / 2h> == <v, adjoint(B, w)> (S^T and J_C^T together)."""
     from paper_1909_04502_amd import rlbm as R

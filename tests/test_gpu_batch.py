@@ -143,3 +143,28 @@ def test_batch_workload_sampled():
         solo = m.step(b.view(f0, int(l)).clone(), m.new_state(), 3)
         m.sync()
         assert rel(b.view(res, int(l)), solo) < 1e-14, int(l)
+
+
+def test_graph_cache_survives_tile_rebuild():
+    """A graph step, then a variant with another tile shape and autotuning (both rebuild the tile
+    list the captured kernels read), then a graph step on the same buffers and step count: the
+    cached graph must be dropped with the old tile list, and every result equals eager launches."""
+    print("[case] batch graph after tile rebuild", flush=True)
+    b, ns, Ts, us = make(SPECS)
+    f0 = b.init(ns, Ts, us)
+    v0 = b.variant
+    ea, eb = f0.clone(), b.new_state()
+    ga, gb = f0.clone(), b.new_state()
+    r_e = b.step(ea, eb, 2, graph=False)
+    r_g = b.step(ga, gb, 2, graph=True)
+    b.sync()
+    assert rel(r_g, r_e) == 0.0
+    b.variant = (v0 + 1) % 4 + 4 * (v0 // 4)        # another tile shape, same grid size
+    b.step(f0.clone(), b.new_state(), 2, graph=True)
+    ta, tb = f0.clone(), b.new_state()
+    b.autotune(ta, tb, steps=2)                      # walks every variant
+    b.variant = v0
+    r_e = b.step(ea, eb, 2, graph=False)
+    r_g = b.step(ga, gb, 2, graph=True)             # the key of the first graph again
+    b.sync()
+    assert rel(r_g, r_e) == 0.0

@@ -1,9 +1,9 @@
-"""External force (Sec. 5.4, scheme B) and no-slip equilibrium walls (Sec. 7.2) on the GPU.
+"""External force (Sec. 5.4, scheme B) and no-slip equilibrium walls (Sec. 8.1) on the GPU.
 
 * parity of the HIP path with the FP64 oracle (periodic and walled lattices, 2D and
   3D, both storages);
 * a batch member with a force evolves as it does alone;
-* Poiseuille flow between the walls (the forcing validation of Sec. 7.2): the
+* Poiseuille flow between the walls (the forcing validation of Sec. 8.1): the
   steady profile is a parabola whose curvature gives an effective viscosity
   eta_eff = n m g / (2 A); its slope in tau must be the Chapman-Enskog
   f_CE(zeta) P of App. C (the interpolation adds a tau-independent numerical
@@ -36,19 +36,31 @@ CASES = {
     "f2_walls_n2": (2, 0.5, 2, (16, 9), ("periodic", "wall"), 0.9, (1e-4, 0.0), "f64"),
     "f2_f32dev": (2, 1.0, 3, (40, 24), ("wall", "periodic"), 0.8, (0.0, 2e-4), "f32dev"),
     "f3_walls": (3, 1.0, 3, (9, 7, 6), ("wall", "periodic", "periodic"), 0.7, (0.0, 2e-4, 1e-4), "f64"),
+    # the massive on-lattice rules (Sec. 5.3) with the force: the set-up of the forcing validation
+    "m2_walls": (2, 5.0, 3, (19, 8), ("wall", "periodic"), 0.9, (0.0, 3e-4), "f64", "massive_onlattice"),
+    "m2_periodic_n2": (2, 3.0, 2, (12, 10), ("periodic", "periodic"), 1.2, (2e-4, -1e-4), "f64",
+                       "massive_onlattice"),
+    "m2_f32dev": (2, 5.0, 3, (19, 8), ("wall", "periodic"), 0.9, (0.0, 3e-4), "f32dev", "massive_onlattice"),
+    "m3_f32dev": (3, 5.0, 3, (8, 7, 6), ("wall", "periodic", "periodic"), 0.8, (0.0, 2e-4, 1e-4), "f32dev",
+                  "massive_onlattice"),
 }
 
 
 def setup(name):
     from paper_1909_04502_amd import rlbm as R
-    d, zeta, order, ext, bc, tau, force, storage = CASES[name]
+    d, zeta, order, ext, bc, tau, force, storage = CASES[name][:8]
+    kind = CASES[name][8] if len(CASES[name]) > 8 else "product"
     shape = tuple(reversed(ext))
     g = np.random.default_rng(7)
     n = 1.0 + 0.02 * g.standard_normal(shape)
     T = 1.0 + 0.05 * g.uniform(-1, 1, shape)
     u = 0.05 * g.uniform(-1, 1, (d,) + shape)
-    gl = R.Lattice(d=d, zeta=zeta, order=order, extent=ext, bc=bc, storage=storage, tau=tau, force=force)
-    quad = qd.product_2d(zeta, order) if d == 2 else qd.product_3d(zeta, order)
+    gl = R.Lattice(d=d, zeta=zeta, order=order, kind=kind, extent=ext, bc=bc, storage=storage, tau=tau,
+                   force=force)
+    if kind == "massive_onlattice":
+        quad = qd.massive_onlattice(d, zeta, order, v0=gl.v0)
+    else:
+        quad = qd.product_2d(zeta, order) if d == 2 else qd.product_3d(zeta, order)
     ol = OL.Lattice(quad, tau, ext, bc=bc, force=force)
     return gl, ol, [torch.tensor(a) for a in (n, T, u)], storage
 

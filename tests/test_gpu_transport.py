@@ -1,4 +1,4 @@
-"""Transport-coefficient calibrations (Sec. 7.1) on the GPU with the paper's on-lattice massive stencil
+"""Transport-coefficient calibrations (Secs. 7.2 and 7.3) on the GPU with the paper's on-lattice massive stencil
 (the 45-vector (2+1)-d rule at m~ = 5, exact streaming), and parity of the walls at prescribed
 temperatures that the thermal-conductivity set-up needs.
 

@@ -203,7 +203,8 @@ def test_library_massive_rule_rejections(rlbm_lib):
 
 def test_create_validates_massive_lattices(rlbm_lib):
     """Checks that run before any device call: a periodic extent shorter than the longest integer
-    displacement (the pull would wrap more than once) and a force on a massive on-lattice rule."""
+    displacement (the pull would wrap more than once) and a force on the 3D massive rule in double
+    storage (its streaming kernel has no force term; the 2D massive rules take one)."""
     from paper_1909_04502_amd import rlbm as R
     cfg = R.Config()
     cfg.model = R.Model(d=2, order=3, kind=R.KIND["massive_onlattice"], pad_=0, zeta=5.0, v0=0.0)
@@ -211,7 +212,8 @@ def test_create_validates_massive_lattices(rlbm_lib):
     cfg.tau = 0.8
     h = ctypes.c_void_p()
     assert rlbm_lib.rlbm_create(ctypes.byref(cfg), ctypes.byref(h)) == R.ERR_INVALID_ARG
-    cfg.extent[0] = 8
+    cfg.model = R.Model(d=3, order=3, kind=R.KIND["massive_onlattice"], pad_=0, zeta=5.0, v0=0.0)
+    cfg.extent[0], cfg.extent[1], cfg.extent[2] = 8, 8, 8
     cfg.force[0] = 1e-5
     assert rlbm_lib.rlbm_create(ctypes.byref(cfg), ctypes.byref(h)) == R.ERR_UNSUPPORTED
     ur = R.Config()

@@ -331,3 +331,46 @@ def test_printed_ur_order3_rule():
     assert max_moment_error(q.p, q.w, 0.0, 2, 7) > 1e-6
     assert np.all(np.abs(np.hypot(q.disp[:, 0], q.disp[:, 1]) - 5.0) == 0)
     assert np.allclose(q.p[0:44:2, 1:], -q.p[1:44:2, 1:])
+
+
+def test_printed_ur_3d_order3_rule():
+    """App. H.1, (3+1)-d order 3: the shells are the 4-point generalized Gauss-Laguerre nodes
+    (alpha = 1, from d^3p/p^0 = |p| d|p| dOmega), the twelve printed weights read shell-major with the
+    groups in the listed order normalise and integrate every rest-frame moment to degree 2N = 6 (the
+    per-shell sums are the normalised Gauss weights); every other group order within a shell, and
+    the group-major order, fails one of these; degree 7 is not exact."""
+    from scipy.special import roots_genlaguerre
+    tab = json.load(open(os.path.join(GOLDEN, "ur_3d_order3_table.json")))
+    wl = tab["weights_as_printed"]
+    x, W = roots_genlaguerre(4, 1)
+    assert np.allclose(tab["shells"], x, rtol=1e-14)
+    sizes = [len(qd.fs_group(g)) for g in tab["stencil_groups"]]
+    assert sizes == [24, 24, 48]
+    q = qd.ur_onlattice_3d(3)
+    assert q.Q == 48 + 72 + 72 + 96 and q.order == 3
+    assert q.w.sum() == pytest.approx(1.0, abs=1e-13)
+    for j in range(4):
+        shell = sum(sizes[g] * wl[3 * j + g] for g in range(3))
+        assert shell == pytest.approx(W[j] / W.sum(), rel=1e-12)
+    for deg in range(7):
+        assert max_moment_error(q.p, q.w, 0.0, 3, deg) < 1e-11, deg
+    assert max_moment_error(q.p, q.w, 0.0, 3, 7) > 1e-3
+    # other readings of the list
+    for perm in itertools.permutations(range(3)):
+        if perm == (0, 1, 2):
+            continue
+        tot = sum(sizes[g] * wl[3 * j + slot] for j in range(4) for slot, g in enumerate(perm))
+        if abs(tot - 1.0) < 1e-12:          # normalised but not exact
+            ws = np.array([wl[3 * j + perm.index(g)] for j in range(4) for g in range(3)
+                           if wl[3 * j + perm.index(g)] != 0 for _ in range(sizes[g])])
+            pts = np.array([(tab["shells"][j],) + tuple(tab["shells"][j] * c / math.sqrt(41) for c in n)
+                            for j in range(4) for g in range(3) if wl[3 * j + perm.index(g)] != 0
+                            for n in qd.fs_group(tab["stencil_groups"][g])])
+            assert max(max_moment_error(pts, ws, 0.0, 3, d) for d in range(7)) > 1e-3, perm
+    group_major = sum(sizes[g] * wl[4 * g + j] for g in range(3) for j in range(4))
+    assert abs(group_major - 1.0) > 0.1
+    # on-lattice, massless, antipodes adjacent
+    assert np.all(q.disp == np.round(q.disp))
+    assert np.allclose((q.disp ** 2).sum(1), 41.0)
+    assert np.allclose(q.p[:, 0], np.sqrt((q.p[:, 1:] ** 2).sum(1)), rtol=1e-15)
+    assert np.allclose(q.p[0::2, 1:], -q.p[1::2, 1:])

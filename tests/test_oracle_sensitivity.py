@@ -151,7 +151,7 @@ def plant_mj_temperature_power(mp):
 
 
 def plant_wall_plane_off_by_one(mp):
-    # Sec. 7.2: the far wall placed one plane inside the lattice
+    # Sec. 8.1: the far wall placed one plane inside the lattice
     _edit(mp, L.Lattice, "wall_mask", "idx[dim] = grid_shape[dim] - 1", "idx[dim] = grid_shape[dim] - 2")
 
 

@@ -122,9 +122,12 @@ def _brute_3d(idx, T, U, m):
 
 
 @pytest.mark.parametrize("d,m,T,u", [(2, 1.0, 1.3, (0.3, -0.2)), (2, 0.0, 0.8, (-0.25, 0.4)),
-                                     (3, 1.0, 1.2, (0.2, -0.1, 0.3))])
+                                     (3, 1.0, 1.2, (0.2, -0.1, 0.3)), (3, 0.0, 0.9, (-0.3, 0.25, 0.1)),
+                                     (3, 5.0, 1.0, (0.1, 0.35, -0.2))])
 def test_mj_moments_brute_force(d, m, T, u):
-    """App. B closed forms vs direct integration, all index tuples up to degree 3.
+    """App. B closed forms vs direct integration, all index tuples up to degree 3 (in d = 3 too: the
+    degree-3 moments of a moving state are what the order-3 equilibrium of the (3+1)-d rules
+    projects).
 
     The density normalisation is taken from the integral itself: n = U_a int f^eq p^a
     with f^eq = B exp(-U.p/T), so nothing of App. B enters the expectation.
@@ -140,8 +143,7 @@ def test_mj_moments_brute_force(d, m, T, u):
     Ut = torch.tensor(U)
     Tt = torch.tensor(T, dtype=torch.float64)
     nt = torch.tensor(n_target, dtype=torch.float64)
-    degs = (0, 1, 2, 3) if d == 2 else (0, 1, 2)
-    for deg in degs:
+    for deg in (0, 1, 2, 3):
         for idx in itertools.combinations_with_replacement(range(d + 1), deg):
             ref = B * brute(idx, T, U, m)
             got = float(mj.mj_tensor_moment(idx, nt, Tt, Ut, m, d))

@@ -255,7 +255,7 @@ def test_taylor_green_viscosity_slope_off_lattice():
 
 
 # ---------------------------------------------------------------------------
-# External force (Sec. 5.4, scheme B) and no-slip walls (Sec. 7.2)
+# External force (Sec. 5.4, scheme B) and no-slip walls (Sec. 8.1)
 # ---------------------------------------------------------------------------
 @pytest.mark.parametrize("rule", ["p2m1", "p2m5", "p3m1"])
 def test_force_term_moments(rule):

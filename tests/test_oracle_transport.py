@@ -1,4 +1,4 @@
-"""The oracle's RLBM against the Chapman-Enskog transport coefficients of App. C (Sec. 7.1
+"""The oracle's RLBM against the Chapman-Enskog transport coefficients of App. C (Secs. 7.2 and 7.3
 calibrations), with the paper's on-lattice massive stencil (45 vectors, m~ = 5, exact streaming).
 
 * Thermal conductivity: a rod between plates held at T = 1.005 and 0.995 (walls at rest, own n),
