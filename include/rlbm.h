@@ -39,6 +39,11 @@
  *     (3,4) (-3,-4) (-3,4) (3,-4) (4,3) (-4,-3) (-4,3) (4,-3) (5,0) (-5,0) (0,5) (0,-5)
  *   on three (order 2) or four (order 3) shells, zero-weight populations
  *   dropped (28 / 44 populations);
+ *   for the printed (3+1)-d massless rule (App. H.1) the groups (4,4,3)_FS,
+ *   (5,4,0)_FS, (6,2,1)_FS on four shells, shell-major, within a shell the
+ *   groups in that order with zero-weight groups dropped ((6,2,1) on shell 0;
+ *   (4,4,3), (6,2,1) on shells 1 and 2; all three on shell 3: 288
+ *   populations), each group's members ordered as for the massive rules;
  *   for the massive on-lattice rules the generating vectors of the groups
  *     order 2: (1,0) (1,1) (2,1) (2,2) (3,1)
  *     order 3: (1,0) (1,1) (2,0) (2,1) (2,2) (3,0) (3,2) (3,3) (4,0)
@@ -95,8 +100,10 @@ typedef enum { RLBM_F64 = 0, RLBM_F32_DEV = 1 } rlbm_storage;
  * massive rules (not the 3D massive rule in double storage). */
 typedef enum { RLBM_PERIODIC = 0, RLBM_OPEN = 1, RLBM_WALL = 2 } rlbm_bc;
 typedef enum {
-  RLBM_QUAD_UR_ONLATTICE = 0, /* printed massless (2+1)-d rules of order 2 and 3 (App. H.2), integer
-                               * streaming (zeta = 0) */
+  RLBM_QUAD_UR_ONLATTICE = 0, /* printed massless rules, integer streaming (zeta = 0): (2+1)-d of
+                               * order 2 and 3 (App. H.2; 28 / 44 populations) and (3+1)-d of order
+                               * 3 (App. H.1; 288 populations, the rule of the 3D Sod tube of
+                               * Sec. 8.2) */
   RLBM_QUAD_PRODUCT = 1,      /* off-lattice product rule: shells x directions, interpolated streaming */
   RLBM_QUAD_MASSIVE_ONLATTICE = 2 /* massive (2+1)-d on-lattice rule (Sec. 5.3): integer vectors n_i in
                                    * full-symmetric groups, p_i = p^0_i (1, v0 n_i) with p^0_i =
@@ -151,7 +158,9 @@ typedef struct {
   int64_t state_bytes; /* bytes of one population buffer */
   int32_t elem_bytes;  /* 8 (F64) or 4 (F32_DEV) */
   int32_t on_lattice;  /* 1 if displacements are integers */
-  double v0;           /* RLBM_QUAD_MASSIVE_ONLATTICE: the v0 in use; 0 otherwise */
+  double v0;           /* on-lattice rules: the lattice-speed parameter in use (massive rules: inside
+                        * the window; the printed massless rules: 1/5 in 2D, 1/sqrt(41) in 3D);
+                        * 0 for product rules */
 } rlbm_info;
 
 typedef struct rlbm_lattice rlbm_lattice;   /* opaque */
@@ -214,7 +223,9 @@ rlbm_status rlbm_init(rlbm_lattice *h, const double *n0, const double *T0, const
  * the pre-collision state of the final step's time level.  With nsteps >= 4 and
  * last == NULL the launches are captured once into a HIP graph (kept by the
  * handle for the same buffers, step count and launch variant) that is replayed
- * on `stream`; a handle serves one stream at a time. */
+ * on `stream`; a handle serves one stream at a time.  A run of more than 256
+ * steps replays the graph of 256 steps (an even count: the state is back in
+ * f_a after each replay) and ends with the remaining 1 .. 256 steps. */
 rlbm_status rlbm_step(rlbm_lattice *h, void *f_a, void *f_b, int32_t nsteps,
                       const rlbm_fields *last, hipStream_t stream);
 
@@ -270,7 +281,8 @@ rlbm_status rlbm_batch_init(rlbm_batch *b, const double *n0, const double *T0, c
                             hipStream_t stream);
 /* nsteps steps of every lattice, ping-ponging as rlbm_step.  With use_graph != 0
  * the launches are captured once into a HIP graph (cached for the same
- * buffers, step count and variant) and the graph is replayed on `stream`. */
+ * buffers, step count and variant) and the graph is replayed on `stream`;
+ * more than 256 steps replay the graph of 256 steps, as rlbm_step does. */
 rlbm_status rlbm_batch_step(rlbm_batch *b, void *f_a, void *f_b, int32_t nsteps, int32_t use_graph,
                             hipStream_t stream);
 rlbm_status rlbm_batch_moments(rlbm_batch *b, const void *f, const rlbm_fields *out, hipStream_t stream);

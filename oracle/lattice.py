@@ -243,6 +243,34 @@ class Lattice:
             out[i] = acc
         return out
 
+    # -- the lattice's own shear viscosity ----------------------------------
+    def shear_coefficient(self) -> float:
+        """c_eta with eta = c_eta P (tau - 1/2): the first-order (Chapman-Enskog) shear stress of this
+        discrete update in the rest frame at n = T = 1.
+
+        The relaxation of Sec. 6.2 (step 8) leaves, to first order in the gradients, the non-equilibrium
+        part f1_i = -tau' p_i^a d_a f^eq_i / (p_i . U); for a shear flow u_x(y) it is
+        -tau' (p_i^y / p_i^0) (d f^eq_i / d u_x) d_y u_x, and pi^xy = sum_i f1_i p_i^x p_i^y, so
+            c_eta = sum_i (d f^eq_i / d u_x) p_i^x (p_i^y)^2 / p_i^0 / (n T),
+        with tau' = tau - 1/2 on the lattice (the step's dt/2 shift).  The derivative is that of this
+        rule's projected equilibrium (step 5), by autograd.  For the continuum Maxwell-Juettner
+        distribution (d f / d u_x = f p^x / T at rest) the same sum is the App. C coefficient f_CE;
+        a rule that cannot integrate the non-polynomial p^x^2 p^y^2 / p^0 moment of f^eq exactly has
+        its own value.  This is the coefficient of the xy shear (a flow u_x(y), as in Poiseuille flow);
+        a rule whose fourth-rank moments are not isotropic has another one for the normal-stress
+        strain d_x u_x - d_y u_y of the Taylor-Green vortex.
+        """
+        ux = torch.zeros((), dtype=torch.float64, requires_grad=True)
+        g = 1.0 / torch.sqrt(1.0 - ux * ux)
+        U = torch.stack([g, g * ux] + [torch.zeros((), dtype=torch.float64)] * (self.d - 1))
+        shape = (1,) * self.d
+        one = torch.ones(shape, dtype=torch.float64)
+        feq = self.equilibrium(one, one, U.reshape((-1,) + shape)).reshape(self.quad.Q)
+        p = self.p
+        weight = p[:, 1] * p[:, 2] ** 2 / p[:, 0]
+        (dfeq,) = torch.autograd.grad((feq * weight).sum(), ux)
+        return float(dfeq)
+
     # -- whole step ---------------------------------------------------------
     def step(self, f):
         """Collide, then stream (Sec. 6.2, step 8)."""

@@ -36,6 +36,7 @@ struct rlbm_lattice {
 };
 
 constexpr int32_t kGraphMinSteps = 4;   // rlbm_step replays a cached graph from this many steps on
+constexpr int32_t kGraphChunk = 256;    // and captures at most this many (even) steps in one graph
 
 struct rlbm_batch {
   std::vector<rlbm_lattice *> lats;
@@ -66,7 +67,7 @@ rlbm_status fail(rlbm_status s, const std::string &msg) {
 }
 
 int stencil_of(const rlbm_model &m) {
-  if (m.kind == RLBM_QUAD_UR_ONLATTICE) return rlbm::ST_UR2D;
+  if (m.kind == RLBM_QUAD_UR_ONLATTICE) return m.d == 2 ? rlbm::ST_UR2D : rlbm::ST_UR3D;
   if (m.kind == RLBM_QUAD_MASSIVE_ONLATTICE) return m.d == 2 ? rlbm::ST_MASSIVE2D : rlbm::ST_MASSIVE3D;
   return m.d == 2 ? rlbm::ST_PROD2D : rlbm::ST_PROD3D;
 }
@@ -194,7 +195,6 @@ rlbm_status rlbm_create(const rlbm_config *cfg, rlbm_lattice **out) {
     }
     if (!std::isfinite(cfg->force[a])) return fail(RLBM_ERR_INVALID_ARG, "force must be finite");
   }
-  if (m.d == 3 && m.kind == RLBM_QUAD_UR_ONLATTICE) return fail(RLBM_ERR_UNSUPPORTED, "the printed massless rule is 2D");
   if (!std::isfinite(cfg->tau_T)) return fail(RLBM_ERR_INVALID_ARG, "tau_T must be finite");
   if (cfg->tau_T != 0.0 && m.kind == RLBM_QUAD_PRODUCT)
     return fail(RLBM_ERR_UNSUPPORTED, "the temperature-dependent tau is built for the on-lattice rules");
@@ -230,6 +230,7 @@ rlbm_status rlbm_create(const rlbm_config *cfg, rlbm_lattice **out) {
   //    of the massless rules (at most 65,536 sites, such as 64 x 64), which take rows of 64 sites
   //    so that four times as many blocks spread over the CUs (about 9 % faster at 64 x 64)
   if (m.d == 3 && m.kind == RLBM_QUAD_MASSIVE_ONLATTICE) h->variant = cfg->storage == RLBM_F64 ? 4 : 8;
+  else if (m.d == 3 && m.kind == RLBM_QUAD_UR_ONLATTICE) h->variant = 4;   // streaming kernel, as the 3D massive rule
   else if (m.d == 3) h->variant = cfg->storage == RLBM_F64 ? 0 : 3;
   else if (m.kind == RLBM_QUAD_PRODUCT && cfg->storage == RLBM_F64) h->variant = 5;
   else if (m.kind == RLBM_QUAD_MASSIVE_ONLATTICE && (m.order == 2 || cfg->storage != RLBM_F64)) h->variant = 10;
@@ -346,6 +347,17 @@ rlbm_status rlbm_step(rlbm_lattice *h, void *f_a, void *f_b, int32_t nsteps, con
   const int64_t bytes = (int64_t)(h->cfg.storage == RLBM_F64 ? 8 : 4) * h->quad.Q * h->sites;
   const char *pa = (const char *)f_a, *pb = (const char *)f_b;
   if (pa < pb + bytes && pb < pa + bytes) return fail(RLBM_ERR_INVALID_ARG, "f_a and f_b overlap");
+  if (nsteps > kGraphChunk) {
+    // long runs replay one cached graph of an even number of steps (the state returns to f_a after
+    // each replay) instead of capturing every launch of the run into one graph; the last 1 ..
+    // kGraphChunk steps (and the fields of the final one) follow as an ordinary call
+    int32_t rest = nsteps;
+    for (; rest > kGraphChunk; rest -= kGraphChunk) {
+      const rlbm_status st = rlbm_step(h, f_a, f_b, kGraphChunk, nullptr, stream);
+      if (st != RLBM_OK) return st;
+    }
+    return rlbm_step(h, f_a, f_b, rest, last, stream);
+  }
   if (nsteps >= kGraphMinSteps && last == nullptr) {
     // many steps without field output: a cached HIP graph of the launches (no per-launch host cost)
     hipError_t he = hipSuccess;
@@ -666,6 +678,15 @@ rlbm_status rlbm_batch_step(rlbm_batch *b, void *f_a, void *f_b, int32_t nsteps,
   const char *pa = (const char *)f_a, *pb = (const char *)f_b;
   if (pa < pb + bytes && pb < pa + bytes) return fail(RLBM_ERR_INVALID_ARG, "f_a and f_b overlap");
   if (nsteps == 0) return RLBM_OK;
+  if (use_graph && nsteps > kGraphChunk) {   // as rlbm_step: replays of one even-length graph
+    int32_t rest = nsteps;
+    for (; rest > kGraphChunk; rest -= kGraphChunk) {
+      const rlbm_status st = rlbm_batch_step(b, f_a, f_b, kGraphChunk, 1, stream);
+      if (st != RLBM_OK) return st;
+    }
+    // the batch caches one graph: the remainder runs eagerly rather than replace the chunk's graph
+    return rlbm_batch_step(b, f_a, f_b, rest, rest == kGraphChunk ? 1 : 0, stream);
+  }
   hipError_t he = hipSuccess;
   if (!use_graph) {
     he = batch_enqueue(b, f_a, f_b, nsteps, stream);

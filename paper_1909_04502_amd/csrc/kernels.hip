@@ -278,6 +278,81 @@ k_step_stream(const Tables *__restrict__ tb, const S *__restrict__ fin, S *__res
   if (last.any) write_fields<ST::D>(last, site, sites, mac);
 }
 
+// The moments and the initial state for stencils too large to hold in registers (the 288-vector
+// (3+1)-d massless rule): the same arithmetic as k_moments and k_init, with every population loaded
+// (or, at the initial state, evaluated from its projection row) when the update asks for it.
+template <class ST, int N, typename S, bool DEV>
+__global__ void __launch_bounds__(256) k_moments_stream(const Tables *__restrict__ tb, const S *__restrict__ fin,
+                                                        FieldPtrs out, int *err, Tiling tl) {
+  int x, y, z;
+  if (!site_coords(tb, tl, x, y, z)) return;
+  const int64_t sites = tb->sites;
+  const int64_t site = ((int64_t)z * tb->ny + y) * tb->nx + x;
+  constexpr int R = ST::RMAX;
+  uint32_t ox[2 * R + 1], oy[2 * R + 1], oz[2 * R + 1];
+  onlat_offsets<ST, S>(tb, x, y, z, ox, oy, oz);
+  auto load = [&](int i) {
+    return *(const S *)((const char *)(fin + (int64_t)i * sites) + ox[R - ST::dir(i, 0)] + oy[R - ST::dir(i, 1)] +
+                        oz[R - dir_z<ST>(i)]);
+  };
+  const Macro<ST::D> mac = massive_update<ST, N, S, DEV, false, false, false>(
+      tb, 1.0, -1.0, load, load, [&](int, S) {});
+  if (!mac.ok) flag_error(err);
+  write_fields<ST::D>(out, site, sites, mac);
+}
+
+template <class ST, int N, typename S, bool DEV>
+__global__ void __launch_bounds__(256) k_init_stream(const Tables *__restrict__ tb, const double *__restrict__ n0,
+                                                     const double *__restrict__ T0, const double *__restrict__ u0,
+                                                     const double *__restrict__ noise, double amp,
+                                                     S *__restrict__ fout, const void *__restrict__ tau_field,
+                                                     FieldPtrs fields0, int *err, Tiling tl) {
+  constexpr int D = ST::D, Q = ST::Q;
+  static_assert(D == 3, "streaming init: the (3+1)-d rule");
+  using B = BasisDef<D, N>;
+  int x, y, z;
+  if (!site_coords(tb, tl, x, y, z)) return;
+  const int64_t sites = tb->sites;
+  const int64_t site = ((int64_t)z * tb->ny + y) * tb->nx + x;
+  double U[D + 1], uu = 0.0;
+#pragma unroll
+  for (int a = 0; a < D; ++a) {
+    U[a + 1] = u0[a * sites + site];
+    uu += U[a + 1] * U[a + 1];
+  }
+  const double g = 1.0 / sqrt(1.0 - uu);
+  U[0] = g;
+#pragma unroll
+  for (int a = 1; a <= D; ++a) U[a] *= g;
+  const double n = n0[site], T = T0[site];
+  bool inr = true;
+  const double r = tb->m == 0.0 ? 0.0 : cheb_r(tb, tb->m / T, inr);
+  if (!inr || !(uu < 1.0) || !(n > 0.0) || !(T > 0.0)) flag_error(err);
+  const Ratios rr = ratios_3d(tb->m / T, r);
+  double M[B::NM];
+  basis_moments<D, N>(n, T, U, rr, M);
+  if constexpr (ST::SHIFT) shift_basis_moments<D, N>(tb->m, M);
+  // f_i(x, 0) = f^eq_i (1 + amp xi_i) from the projection rows, in storage form
+  auto feq = [&](int i) {
+    const int pr = i >> 1;
+    double E = 0.0, O = 0.0;
+#pragma unroll
+    for (int k = 0; k < B::NE; ++k) E += tb->Re[pr][k] * M[k];
+#pragma unroll
+    for (int k = 0; k < B::NO; ++k) O += tb->Ro[pr][k] * M[B::NE + k];
+    double v = (i & 1) ? E - O : E + O;
+    if (noise != nullptr) v *= 1.0 + amp * noise[(int64_t)i * sites + site];
+    return DEV ? (S)(v - tb->fref[i]) : (S)v;
+  };
+  static_assert((Q & 1) == 0, "streaming init: stencils without a rest population");
+  const double tau = site_tau<S>(tb, tau_field, site);
+  const uint32_t site_off = (uint32_t)site * (uint32_t)sizeof(S);
+  const Macro<D> mac = massive_update<ST, N, S, DEV, true, false, false>(
+      tb, tau, -1.0, feq, feq, [&](int i, S v) { put_pop<false>(fout, sites, site_off, i, v); });
+  if (!mac.ok) flag_error(err);
+  if (fields0.any) write_fields<D>(fields0, site, sites, mac);
+}
+
 template <class ST, int N, typename S, bool DEV>
 __global__ void __launch_bounds__(256) k_moments(const Tables *__restrict__ tb, const S *__restrict__ fin,
                                                  FieldPtrs out, int *err, Tiling tl) {
@@ -380,7 +455,10 @@ static hipError_t launch_t(const LaunchArgs &a) {
   const Tiling tl{vr.bx, by, bz, (int)nb, order};
   // the 143 doubles of the 3D massive rule overflow the registers (scratch spills): stream them;
   // 143 floats fit, and there the single load is faster
-  constexpr bool kStream = ST::ONLAT && ST::SHIFT && ST::D == 3 && sizeof(S) == 8;
+  constexpr bool kStream = (ST::ONLAT && ST::SHIFT && ST::D == 3 && sizeof(S) == 8) || ST::Q > 144;
+  // the 288 populations of the (3+1)-d massless rule do not fit in registers in either storage: its
+  // moments and initial state take the streaming forms too
+  constexpr bool kStreamAll = ST::Q > 144;
   switch (a.op) {
     case OP_STEP: {
       // one instantiation per (occupancy target 0, 2 or 4, force/walls, store kind)
@@ -400,7 +478,12 @@ static hipError_t launch_t(const LaunchArgs &a) {
       using F = std::false_type;
       using T = std::true_type;
       const bool ext = a.ext && !kStream;
-      if (ext) {
+      if constexpr (kStreamAll) {
+        // one build (no occupancy target) for the 288-vector rule: every other build multiplies its
+        // compile time and none is faster for a kernel that streams its populations
+        if (a.nt) go(O0{}, F{}, T{});
+        else go(O0{}, F{}, F{});
+      } else if (ext) {
         if (a.nt) go(O0{}, T{}, T{});
         else go(O0{}, T{}, F{});
       } else if (vr.occ == 2) {
@@ -416,12 +499,20 @@ static hipError_t launch_t(const LaunchArgs &a) {
       break;
     }
     case OP_MOMENTS:
-      hipLaunchKernelGGL((k_moments<ST, N, S, DEV>), grid, block, 0, a.stream, a.tb, (const S *)a.fin, a.fields,
-                         a.err, tl);
+      if constexpr (kStreamAll)
+        hipLaunchKernelGGL((k_moments_stream<ST, N, S, DEV>), grid, block, 0, a.stream, a.tb, (const S *)a.fin,
+                           a.fields, a.err, tl);
+      else
+        hipLaunchKernelGGL((k_moments<ST, N, S, DEV>), grid, block, 0, a.stream, a.tb, (const S *)a.fin, a.fields,
+                           a.err, tl);
       break;
     case OP_INIT:
-      hipLaunchKernelGGL((k_init<ST, N, S, DEV>), grid, block, 0, a.stream, a.tb, a.n0, a.T0, a.u0, a.noise,
-                         a.amp, (S *)a.fout, a.tau_field, a.fields, a.err, tl);
+      if constexpr (kStreamAll)
+        hipLaunchKernelGGL((k_init_stream<ST, N, S, DEV>), grid, block, 0, a.stream, a.tb, a.n0, a.T0, a.u0,
+                           a.noise, a.amp, (S *)a.fout, a.tau_field, a.fields, a.err, tl);
+      else
+        hipLaunchKernelGGL((k_init<ST, N, S, DEV>), grid, block, 0, a.stream, a.tb, a.n0, a.T0, a.u0, a.noise,
+                           a.amp, (S *)a.fout, a.tau_field, a.fields, a.err, tl);
       break;
     default:
       return hipErrorInvalidValue;
@@ -445,6 +536,7 @@ hipError_t launch(const LaunchArgs &a) {
     return launch_storage<Stencil<ST_MASSIVE2D, 3>, 3>(a);
   }
   if (a.stencil == ST_MASSIVE3D) return launch_storage<Stencil<ST_MASSIVE3D, 3>, 3>(a);
+  if (a.stencil == ST_UR3D) return launch_storage<Stencil<ST_UR3D, 4>, 3>(a);
   if (a.stencil == ST_PROD2D) {
     if (a.order == 2) return launch_storage<Stencil<ST_PROD2D, 3>, 2>(a);
     return launch_storage<Stencil<ST_PROD2D, 4>, 3>(a);

@@ -147,6 +147,16 @@ static const double kUR3Shells[4] = {0.3225476896193923, 1.7457611011583465, 4.5
 static const double kUR3W34[4] = {0.0753942630427042, 0.0241670278669858, 0.0026380943565871, 0.0000365655303385};
 static const double kUR3W50[4] = {0.0, 0.0410206173754781, 0.0044457884155769, 0.0000616926157132};
 
+// Printed (3+1)-d massless order-3 rule (App. H.1): generalized Gauss-Laguerre (alpha = 1) shells and
+// the twelve printed weights, read shell-major with the groups (4,4,3), (5,4,0), (6,2,1) in that order
+// within a shell.
+static const double kUR3DShells[4] = {0.7432919279814314, 2.5716350076462784, 5.7311787516890996,
+                                      10.953894312683190};
+static const double kUR3DW[4][3] = {{0.0, 0.0, 0.0093098040253911},
+                                    {0.0085195569675087, 0.0, 0.0056909667738262},
+                                    {0.0013041770173120, 0.0, 0.0008932820065742},
+                                    {0.0000029126213348, 0.0000338363537565, 0.0000090390475856}};
+
 int build_quadrature(int d, double m, int order, int kind, double v0, QuadHost &q, std::string &err) {
   if (kind == RLBM_QUAD_MASSIVE_ONLATTICE) return build_massive(d, m, order, v0, q, err);
   q = QuadHost();
@@ -154,11 +164,37 @@ int build_quadrature(int d, double m, int order, int kind, double v0, QuadHost &
   q.m = m;
   q.order = order;
   q.kind = kind;
-  if (kind == RLBM_QUAD_UR_ONLATTICE) {
-    if (d != 2 || (order != 2 && order != 3) || m != 0.0) {
-      err = "the printed on-lattice rules are massless (zeta = 0), d = 2, order N = 2 or 3";
+  if (kind == RLBM_QUAD_UR_ONLATTICE && d == 3) {
+    if (order != 3 || m != 0.0) {
+      err = "the printed (3+1)-d on-lattice rule is massless (zeta = 0) of order N = 3";
       return RLBM_ERR_UNSUPPORTED;
     }
+    q.nshell = 4;
+    q.ndir = kUR3DQ;
+    q.Q = kUR3DQ;
+    q.v0 = 1.0 / std::sqrt((double)kUR3DNorm2);
+    for (int g = 0; g < kUR3DGroups; ++g) {
+      const double p0 = kUR3DShells[kUR3DShellOf[g]], wg = kUR3DW[kUR3DShellOf[g]][kUR3DGenOf[g]];
+      if (wg == 0.0) {
+        err = "internal: zero-weight group in the printed rule";
+        return RLBM_ERR_QUADRATURE;
+      }
+      q.gfirst.push_back(kUR3DDirs.first[g]);
+      for (int i = kUR3DDirs.first[g]; i < kUR3DDirs.first[g] + kUR3DDirs.count[g]; ++i) {
+        const int *n = kUR3DDirs.v[i];
+        q.p.insert(q.p.end(), {p0, p0 * q.v0 * n[0], p0 * q.v0 * n[1], p0 * q.v0 * n[2]});
+        q.w.push_back(wg);
+        q.disp.insert(q.disp.end(), {(double)n[0], (double)n[1], (double)n[2]});
+      }
+    }
+    return 0;
+  }
+  if (kind == RLBM_QUAD_UR_ONLATTICE) {
+    if (d != 2 || (order != 2 && order != 3) || m != 0.0) {
+      err = "the printed on-lattice rules are massless (zeta = 0): d = 2 with order N = 2 or 3, d = 3 with N = 3";
+      return RLBM_ERR_UNSUPPORTED;
+    }
+    q.v0 = 0.2;
     q.nshell = order == 2 ? 3 : 4;
     q.ndir = 12;
     q.Q = order == 2 ? kUR2DQ : kUR3Q;
@@ -671,7 +707,7 @@ int build_tables(const QuadHost &q, double tau, double n_ref, int storage, const
   if (!q.gfirst.empty()) {
     // group factors: p = (p0, v n) with v = v0 p0 for every member n of a group (v0 = 1/|n| = 1/5
     // for the printed massless rules)
-    const double v0 = q.kind == RLBM_QUAD_UR_ONLATTICE ? 0.2 : q.v0;
+    const double v0 = q.v0;
     if ((int)q.gfirst.size() > kMaxMassiveGroups) {
       err = "internal: too many groups";
       return RLBM_ERR_UNSUPPORTED;

