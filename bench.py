@@ -144,7 +144,7 @@ def copy_bandwidth(nbytes, planes=32, reps=20):
     return out
 
 
-def batched(count, warmup, steps, storage="f64"):
+def batched(count, warmup, steps, storage="f64", physics=False):
     """Many lattices (sides 64..512, tau in [0.6, 2], zeta in [0, 5], seed 4; Taylor-Green u0 = 0.05):
     one persistent launch per step (graph-replayed) against one launch per lattice per step."""
     import torch
@@ -189,6 +189,16 @@ def batched(count, warmup, steps, storage="f64"):
     torch.cuda.synchronize()
     t_solo = e0.elapsed_time(e1) / ps * 1e-3
     b.sync()
+    # the configuration's whole run: 500 steps in one call (replays of the cached 256-step graph)
+    run_steps = 500
+    b.step(fa, fb, run_steps)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    b.step(fa, fb, run_steps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    t_run = e0.elapsed_time(e1) / run_steps * 1e-3
+    b.sync()
     sites = b.total_sites
     Q = b.Q
     t = res["graph"]
@@ -199,10 +209,63 @@ def batched(count, warmup, steps, storage="f64"):
            "achieved_GBs": round(2 * Q * es * sites / t / 1e9, 1),
            "frac": round(2 * Q * es * sites / t / 1e9 / HBM_PEAK_GBS, 4),
            "variant": b.variant, "autotune_ms": [round(x, 4) for x in tune],
+           "run_500_steps_ms_per_step": round(t_run * 1e3, 4), "run_500_steps_MLUPS": round(sites / t_run / 1e6, 2),
            "workload": f"{count} lattices, sides U{{64..512}}, tau U[0.6,2], zeta U[0,5] (seed 4), N=3, {storage}"}
+    if physics:
+        out["shear_viscosity_fit"] = batch_viscosity_fit(b, specs)
     del b, fa, fb, views
     torch.cuda.empty_cache()
     return out
+
+
+def batch_viscosity_fit(b, specs, steps=500, every=25, first=50):
+    """The batched configuration's physics (untimed): a fresh Taylor-Green start run for its 500 steps,
+    the amplitude of each lattice's mode (u_x projected on cos x sin y) every 25 steps, the decay rate
+    gamma fitted from step 50 on, eta/P = gamma G_2(zeta) / (2 k^2) with G_2 = (zeta^2 + 3 zeta + 3) /
+    (zeta + 1), and per zeta bin of width 1 the least-squares slope of eta/P against tau (with an
+    intercept linear in zeta: interpolated streaming adds a tau-independent viscosity).  The tests
+    compare each bin's slope with the Chapman-Enskog coefficient."""
+    import numpy as np
+    import torch
+    import workloads as W
+    ns, Ts, us = [], [], []
+    for i, sp in enumerate(specs):
+        n, T, u = W.taylor_green_2d(*sp["extent"], 0.05, density_sigma=1e-3, seed=100 + i)
+        ns.append(n), Ts.append(T), us.append(u)
+    fa = b.init(ns, Ts, us)
+    fb = b.new_state()
+    del ns, Ts, us
+    modes = []
+    for sp in specs:
+        x = 2 * np.pi * np.arange(sp["extent"][0]) / sp["extent"][0]
+        X, Y = np.meshgrid(x, x)
+        modes.append(torch.tensor(np.cos(X) * np.sin(Y), device="cuda"))
+    times = list(range(0, steps + 1, every))
+    amps = np.zeros((len(specs), len(times)))
+    for ti, t in enumerate(times):
+        if t:
+            r = b.step(fa, fb, every)
+            if r is fb:
+                fa, fb = fb, fa
+        mom = b.moments(fa)
+        amps[:, ti] = torch.stack([((m["U"][1] / m["U"][0]) * md).sum() / (md * md).sum()
+                                   for m, md in zip(mom, modes)]).cpu().numpy()
+    b.sync()
+    sel = [i for i, t in enumerate(times) if t >= first]
+    tt = np.array([times[i] for i in sel])
+    tau = np.array([sp["tau"] for sp in specs])
+    zeta = np.array([sp["zeta"] for sp in specs])
+    gam = np.array([-np.polyfit(tt, np.log(np.abs(amps[l, sel])), 1)[0] for l in range(len(specs))])
+    k = 2 * np.pi / np.array([sp["extent"][0] for sp in specs])
+    y = gam * (zeta * zeta + 3 * zeta + 3) / (zeta + 1) / (2 * k * k)
+    bins = []
+    for lo in range(5):
+        m = (zeta >= lo) & (zeta < lo + 1)
+        A = np.stack([tau[m] - 0.5, np.ones(m.sum()), zeta[m] - zeta[m].mean()], 1)
+        coef, *_ = np.linalg.lstsq(A, y[m], rcond=None)
+        bins.append({"zeta_bin": [lo, lo + 1], "lattices": int(m.sum()), "mean_zeta": round(float(zeta[m].mean()), 4),
+                     "eta_over_P_slope": round(float(coef[0]), 5)})
+    return {"steps": steps, "fit_from_step": first, "per_zeta_bin": bins}
 
 
 def adjoint_leg(L, warmup, steps):
@@ -391,6 +454,29 @@ def sod_leg(warmup, steps):
     t = e0.elapsed_time(e1) * 1e-3
     lat.sync()
     out["sod_6400x5"] = {"steps": nsteps, "ms_total": round(t * 1e3, 3), "MLUPS": round(nx * ny * nsteps / t / 1e6, 1)}
+    del lat, fa, fb
+    # the same tube in (3+1) dimensions: the printed order-3 rule of App. H.1 (288 populations), light
+    # crossing sqrt(41) sites per step (234 steps to t = 3.0 fm/c), open y and z (one row)
+    import math
+    nsteps3 = 234
+    n3 = torch.tensor(np.where(left, 1.0, nR)[None, None, :])
+    T3 = torch.tensor(np.where(left, 1.0, TR)[None, None, :])
+    u3 = torch.zeros((3, 1, 1, nx), dtype=torch.float64)
+    tau_T3 = 0.002 * 4 / 0.8 * (197.327 / 400.0) / (math.sqrt(41.0) * 0.002)
+    lat = R.Lattice(d=3, zeta=0.0, order=3, kind="ur_onlattice", extent=(nx, 1, 1), bc=("periodic", "open", "open"),
+                    tau=0.5, tau_T=tau_T3)
+    fa = lat.init(n3, T3, u3)
+    fb = lat.new_state()
+    lat.step(fa, fb, 2)
+    torch.cuda.synchronize()
+    e0.record()
+    lat.step(fa, fb, nsteps3)
+    e1.record()
+    torch.cuda.synchronize()
+    t3 = e0.elapsed_time(e1) * 1e-3
+    lat.sync()
+    out["sod3d_6400x1x1"] = {"Q": lat.Q, "steps": nsteps3, "ms_total": round(t3 * 1e3, 3),
+                             "MLUPS": round(nx * nsteps3 / t3 / 1e6, 1)}
     del lat, fa, fb
     L = 1024
     n, T, u = W.taylor_green_2d(L, L, 0.01, seed=2)
@@ -614,7 +700,7 @@ def main():
     if not args.no_batch:
         out["batched"] = batched(args.batch_count, max(2, args.warmup // 4), max(4, args.steps // 10))
         out["batched_f32dev"] = batched(args.batch_count, max(2, args.warmup // 4), max(4, args.steps // 10),
-                                        "f32dev")
+                                        "f32dev", physics=True)
     if not args.no_onlattice:
         want = (lambda name: args.only in (None, name))
         if want("onlattice_ur"):

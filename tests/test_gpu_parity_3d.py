@@ -260,3 +260,43 @@ def test_c3_full_length_float_deviations_against_fp64():
     print("C3 2000-step float deviations vs FP64", errs, flush=True)
     # measured: n 1.5e-4, eps 1.8e-4, T 3.5e-5, U^x 2.5e-4 (max-normalised)
     assert max(errs.values()) < 1e-3
+
+
+@pytest.mark.parametrize("zeta,kind", [(0.5, "product"), (1.0, "product"), (5.0, "product"),
+                                       (5.0, "massive_onlattice")])
+def test_3d_equation_of_state_over_its_range(zeta, kind):
+    """The 3D equation of state runs through two Chebyshev series built per lattice on T in [1/4, 4]
+    (K1/K2 in log z, and the inverse T(eps/n)).  Temperatures swept across that whole range (with
+    density and flow varying too): the initial state, its fields and two steps against the oracle,
+    whose temperature is the bisection root of the exact equation of state."""
+    from paper_1909_04502_amd import rlbm as R
+    print(f"[case] 3D EOS range zeta={zeta} {kind}", flush=True)
+    nx, ny, nz = 24, 6, 5
+    x = np.arange(nx)[None, None, :]
+    T = np.broadcast_to(0.27 * (3.7 / 0.27) ** (x / (nx - 1)), (nz, ny, nx)).copy()   # 0.27 .. 3.7
+    n = np.broadcast_to(1.0 + 0.3 * np.sin(2 * np.pi * x / nx), (nz, ny, nx)).copy()
+    u = np.zeros((3, nz, ny, nx))
+    u[1] = 0.05 * np.cos(2 * np.pi * np.arange(ny) / ny)[None, :, None]
+    bc = ("open", "periodic", "periodic")
+    if kind == "product":
+        q = qd.product_3d(zeta, 3)
+        gl = R.Lattice(d=3, zeta=zeta, order=3, extent=(nx, ny, nz), bc=bc, tau=0.9)
+    else:
+        q = qd.massive_onlattice(3, zeta, 3)
+        gl = R.Lattice(d=3, zeta=zeta, order=3, kind=kind, extent=(nx, ny, nz), bc=bc, tau=0.9, v0=q.v0)
+    ol = OL.Lattice(q, 0.9, (nx, ny, nz), bc=bc)
+    tn, tT, tu = (torch.tensor(a) for a in (n, T, u))
+    f0, fields0 = gl.init(tn, tT, tu, want_fields=True)
+    res = gl.step(f0, gl.new_state(), 2)
+    mom = gl.moments(res)
+    gl.sync()
+    fs = ol.collide(ol.init(tn, tT, tu))
+    mac0 = ol.macro(ol.init(tn, tT, tu))
+    assert rel(fields0["T"], mac0["T"]) < FP64_TOL and rel(fields0["n"], mac0["n"]) < FP64_TOL
+    assert rel(f0, fs) < FP64_TOL
+    for _ in range(2):
+        fs = ol.collide(ol.stream(fs))
+    ref = ol.macro(ol.stream(fs))
+    assert rel(res, fs) < FP64_TOL
+    for k in ("n", "eps", "T"):
+        assert rel(mom[k], ref[k]) < FP64_TOL, k

@@ -1,4 +1,5 @@
-"""Ultra-relativistic Sod shock tube with an eta/s-driven local tau (Sec. 7, App. D) on the GPU.
+"""Ultra-relativistic Sod shock tube with an eta/s-driven local tau (Sec. 8.2, App. D) on the GPU, in
+(2+1) and (3+1) dimensions.
 
 * parity of the printed (2+1)-d order-3 massless rule (App. H.2, 44 populations) with the FP64
   oracle, with and without the temperature-dependent tau(x) = tau + tau_T / T(x);
@@ -230,8 +231,9 @@ def test_sod3d_inviscid_against_app_d():
     plateau = (x > c["w_T"] * t + third) & (x < c["w_C"] * t - third)
     err_plateau = np.max(np.abs(beta[plateau] - c["beta_C"])) / c["beta_C"]
     print("3d mean abs errors", err, "plateau beta rel", err_plateau, flush=True)
-    assert err["n"] < 8e-3 and err["P"] < 8e-3 and err["T"] < 8e-3 and err["beta"] < 8e-3
-    assert err_plateau < 2e-3
+    # the oracle's run of the same set-up gives n 5.4e-3, P 3.0e-3, T 4.1e-3, beta 2.4e-3, plateau 2.2e-4
+    assert err["n"] < 7e-3 and err["P"] < 4e-3 and err["T"] < 5e-3 and err["beta"] < 3e-3
+    assert err_plateau < 1e-3
     gold = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "sod3d_eta002_234_profile.json")))
     assert gold["steps"] == STEPS3 and gold["nx"] == nx and abs(gold["tau_T"] - tau_T3_of(0.002)) < 1e-15
     sites = np.array(gold["sites"])
