@@ -336,9 +336,10 @@ def adjoint_leg(L, warmup, steps):
     return out
 
 
-def shock_tube_3d(L, warmup, steps, autotune=True):
+def shock_tube_3d(L, warmup, steps, autotune=True, storage="f32dev"):
     """3D shock tube: zeta = 1, N = 3, Q = 104, L^3 with open x and periodic y, z, left state n = 8/3,
-    T = 1.5 for x < L/2, right n = 1, T = 1, u = 0; float-deviation storage (832 B per site).  Timed at
+    T = 1.5 for x < L/2, right n = 1, T = 1, u = 0; float-deviation storage (832 B per site), updated
+    in float (f32dev) or in double (f32dev_f64).  Timed at
     tau = 0.8, the set-up the 2000-step parity run validates: at tau = 0.6 the scheme itself (the FP64
     oracle on the same set-up) turns non-physical at step 113; the step costs the same at any tau."""
     import torch
@@ -346,7 +347,7 @@ def shock_tube_3d(L, warmup, steps, autotune=True):
     from paper_1909_04502_amd import rlbm as R
     n, T, u = W.riemann_3d(L, L, L, L // 2, 8.0 / 3.0, 1.5, 1.0, 1.0)
     lat = R.Lattice(d=3, zeta=1.0, order=3, extent=(L, L, L), bc=("open", "periodic", "periodic"),
-                    storage="f32dev", tau=0.8)
+                    storage=storage, tau=0.8)
     tune = lat.autotune(steps=3) if autotune else None
     fa = lat.init(torch.tensor(n), torch.tensor(T), torch.tensor(u))
     del n, T, u
@@ -355,7 +356,7 @@ def shock_tube_3d(L, warmup, steps, autotune=True):
     sites = L ** 3
     b = 2 * lat.Q * 4 * sites
     out = {"workload": f"3D shock tube {L}^3, zeta=1 N=3 Q={lat.Q}, open x, tau=0.8 (the validated set-up; "
-                       "tau=0.6 turns non-physical at step 113 in the FP64 oracle itself), f32dev",
+                       f"tau=0.6 turns non-physical at step 113 in the FP64 oracle itself), {storage}",
            "MLUPS": round(sites / t / 1e6, 2), "ms_per_step": round(t * 1e3, 4),
            "achieved_GBs": round(b / t / 1e9, 1), "frac": round(b / t / 1e9 / HBM_PEAK_GBS, 4),
            "variant": lat.variant, "autotune_ms": [round(x, 4) for x in tune] if tune else None}
@@ -609,7 +610,7 @@ def cpu_baseline(seconds):
     finally:
         torch.set_num_threads(threads)
     errors = {"steps": KERR, "lattice": f"{L}x{L}"}
-    for storage in ("f64", "f32dev"):
+    for storage in ("f64", "f32dev", "f32dev_f64"):
         lat = R.Lattice(d=2, zeta=1.0, order=3, extent=(L, L), tau=0.8, storage=storage)
         res = lat.step(lat.init(n, T, u), lat.new_state(), KERR)
         mom = lat.moments(res)
@@ -692,11 +693,23 @@ def main():
                                       "autotune_ms": [round(x, 5) for x in tune32] if tune32 else None}}
         del lat, fa, fb
         torch.cuda.empty_cache()
+        # float storage, double arithmetic: float traffic, errors that do not grow with the run
+        lat, fa, fb, tunem = make_lattice(L, "f32dev_f64", args.autotune)
+        tm = time_steps(lat, fa, fb, args.warmup, args.steps)
+        out["variants"]["f32dev_f64"] = {"MLUPS": round(sites / tm / 1e6, 2), "ms_per_step": round(tm * 1e3, 5),
+                                         "achieved_GBs": round(b32 / tm / 1e9, 1),
+                                         "frac": round(b32 / tm / 1e9 / HBM_PEAK_GBS, 4),
+                                         "variant": lat.variant,
+                                         "autotune_ms": [round(x, 5) for x in tunem] if tunem else None}
+        del lat, fa, fb
+        torch.cuda.empty_cache()
     if not args.no_adjoint:
         out["adjoint"] = adjoint_leg(512, args.warmup, args.steps)
     if not args.no_3d:
         out["shock_tube_3d"] = shock_tube_3d(args.size_3d, max(2, args.warmup // 4), max(4, args.steps // 10),
                                              args.autotune)
+        out["shock_tube_3d_f32dev_f64"] = shock_tube_3d(args.size_3d, max(2, args.warmup // 4),
+                                                        max(4, args.steps // 10), args.autotune, "f32dev_f64")
     if not args.no_batch:
         out["batched"] = batched(args.batch_count, max(2, args.warmup // 4), max(4, args.steps // 10))
         out["batched_f32dev"] = batched(args.batch_count, max(2, args.warmup // 4), max(4, args.steps // 10),

@@ -65,6 +65,13 @@
  *                 moments accumulate the deviations in float, the
  *                 eigenproblem, equation of state and equilibrium
  *                 coefficients are computed in double.
+ *   RLBM_F32_DEV_F64  the same float deviations in memory (same traffic),
+ *                 but every step computes in double: the interpolated
+ *                 pull, the moment sums and the relaxation; only the
+ *                 store rounds to float.  Rounding in float arithmetic is
+ *                 correlated from step to step and its error grows about
+ *                 linearly with the number of steps; the rounding of the
+ *                 stores alone does not build up.  Product rules only.
  *
  * Errors
  *   Functions return rlbm_status.  Invalid arguments are reported
@@ -91,7 +98,7 @@ typedef enum {
   RLBM_ERR_NONPHYSICAL = 5    /* a kernel met a non-physical state (see above) */
 } rlbm_status;
 
-typedef enum { RLBM_F64 = 0, RLBM_F32_DEV = 1 } rlbm_storage;
+typedef enum { RLBM_F64 = 0, RLBM_F32_DEV = 1, RLBM_F32_DEV_F64 = 2 } rlbm_storage;
 /* RLBM_WALL: reads clamp as RLBM_OPEN, and the first and last plane of the
  * axis are no-slip walls whose collision is replaced by the local equilibrium
  * at zero flow speed (the site's own n and T, or a prescribed T:
@@ -132,8 +139,8 @@ typedef struct {
   int32_t bc[3];       /* rlbm_bc per axis; RLBM_OPEN = zero-gradient (reads clamp to the edge) */
   int32_t storage;     /* rlbm_storage */
   double tau;          /* relaxation time, used where tau_field is NULL; > 0.5 recommended */
-  const void *tau_field; /* device [sites] per-site tau, double (F64) or float (F32_DEV), or NULL */
-  double n_ref;        /* reference density of the F32_DEV deviations (T_ref = 1, U = 0) */
+  const void *tau_field; /* device [sites] per-site tau, double (F64) or float (float storages), or NULL */
+  double n_ref;        /* reference density of the float deviations (T_ref = 1, U = 0) */
   double force[3];     /* constant acceleration g (lattice units, first d used) of the external
                         * force of Sec. 5.4, scheme B: Minkowski force K = p^0 g, K^0 = g.p;
                         * the update subtracts F^ext_i = -(m/T) (K^a U_a / p_i^0) f^eq_i, the
@@ -156,7 +163,7 @@ typedef struct {
   int32_t n_basis;     /* dimension of the polynomial space (N+1)^2 (2D), (N+1)(N+2)(2N+3)/6 (3D) */
   int64_t sites;       /* nx * ny * nz */
   int64_t state_bytes; /* bytes of one population buffer */
-  int32_t elem_bytes;  /* 8 (F64) or 4 (F32_DEV) */
+  int32_t elem_bytes;  /* 8 (F64) or 4 (float storages) */
   int32_t on_lattice;  /* 1 if displacements are integers */
   double v0;           /* on-lattice rules: the lattice-speed parameter in use (massive rules: inside
                         * the window; the printed massless rules: 1/5 in 2D, 1/sqrt(41) in 3D);

@@ -60,7 +60,7 @@ __device__ __forceinline__ double tau_at(const Tables *__restrict__ tb, const vo
 __device__ __forceinline__ void set_err(int *err) { *err = 1; }
 
 // lam_t(x) = J_C(F_t(x))^T (S^T lam_{t+1})(x), F_t = S(B_{t-1}); dtau(x) += dL/dtau(x)
-template <class ST, int N, typename S, bool DEV>
+template <class ST, int N, typename S, bool DEV, typename A = S>
 __global__ void __launch_bounds__(256) k_adjoint(const Tables *__restrict__ tb, const S *__restrict__ Bprev,
                                                  const S *__restrict__ lam_next, S *__restrict__ lam,
                                                  const void *__restrict__ tau_field, double *__restrict__ dtau,
@@ -70,19 +70,19 @@ __global__ void __launch_bounds__(256) k_adjoint(const Tables *__restrict__ tb, 
   const int64_t sites = tb->sites;
   const int64_t site = ((int64_t)z * tb->ny + y) * tb->nx + x;
   const Offs o = offs_periodic<ST, S>(tb, x, y, z);
-  S f[ST::Q], mu[ST::Q];
-  pull_prod<ST, S, false>(tb, Bprev, sites, o, f);
-  pull_prod<ST, S, true>(tb, lam_next, sites, o, mu);
+  A f[ST::Q], mu[ST::Q];
+  pull_prod<ST, S, false, A>(tb, Bprev, sites, o, f);
+  pull_prod<ST, S, true, A>(tb, lam_next, sites, o, mu);
   double taub;
-  if (!collide_vjp<ST, N, S, DEV>(tb, f, mu, tau_at<S>(tb, tau_field, site), taub)) set_err(err);
+  if (!collide_vjp<ST, N, A, DEV>(tb, f, mu, tau_at<S>(tb, tau_field, site), taub)) set_err(err);
   const uint32_t so = (uint32_t)site * (uint32_t)sizeof(S);
 #pragma unroll
-  for (int i = 0; i < ST::Q; ++i) *(S *)((char *)(lam + (int64_t)i * sites) + so) = f[i];
+  for (int i = 0; i < ST::Q; ++i) *(S *)((char *)(lam + (int64_t)i * sites) + so) = (S)f[i];
   if (dtau != nullptr) dtau[site] += taub;
 }
 
 // lam_{T+1}(x) = J_macro(F(x))^T g(x), F = S(B); g = (dL/dn, dL/deps, dL/dT, dL/dU)
-template <class ST, int N, typename S, bool DEV>
+template <class ST, int N, typename S, bool DEV, typename A = S>
 __global__ void __launch_bounds__(256) k_moments_vjp(const Tables *__restrict__ tb, const S *__restrict__ B,
                                                      FieldPtrs g, S *__restrict__ lam, int *err) {
   constexpr int D = ST::D;
@@ -91,10 +91,10 @@ __global__ void __launch_bounds__(256) k_moments_vjp(const Tables *__restrict__ 
   const int64_t sites = tb->sites;
   const int64_t site = ((int64_t)z * tb->ny + y) * tb->nx + x;
   const Offs o = offs_periodic<ST, S>(tb, x, y, z);
-  S f[ST::Q];
-  pull_prod<ST, S, false>(tb, B, sites, o, f);
+  A f[ST::Q];
+  pull_prod<ST, S, false, A>(tb, B, sites, o, f);
   double Nv[D + 1], T[D + 1][D + 1];
-  moments_prod<ST, S, DEV>(tb, f, Nv, T);
+  moments_prod<ST, A, DEV>(tb, f, Nv, T);
   Macro<D> mac;
   mac.ok = landau_frame<D, 3>(T, mac.eps, mac.U);
   mac.n = lorentz_dot<D>(mac.U, Nv);
@@ -104,18 +104,18 @@ __global__ void __launch_bounds__(256) k_moments_vjp(const Tables *__restrict__ 
 #pragma unroll
   for (int a = 0; a <= D; ++a) Ub[a] = g.U ? g.U[a * sites + site] : 0.0;
   const double nb = g.n ? g.n[site] : 0.0, eb = g.eps ? g.eps[site] : 0.0, Tb = g.T ? g.T[site] : 0.0;
-  S out[ST::Q];
+  A out[ST::Q];
 #pragma unroll
   for (int i = 0; i < ST::Q; ++i) out[i] = 0;
-  macro_vjp<ST, S>(tb, Nv, T, mac, nb, eb, Tb, Ub, out);
+  macro_vjp<ST, A>(tb, Nv, T, mac, nb, eb, Tb, Ub, out);
   const uint32_t so = (uint32_t)site * (uint32_t)sizeof(S);
 #pragma unroll
-  for (int i = 0; i < ST::Q; ++i) *(S *)((char *)(lam + (int64_t)i * sites) + so) = out[i];
+  for (int i = 0; i < ST::Q; ++i) *(S *)((char *)(lam + (int64_t)i * sites) + so) = (S)out[i];
 }
 
 // Reverse of the initial condition B_0 = C(f_0), f_0 = f^eq(n0, T0, U(u0)) (1 + amp xi):
 // du0 (and dn0, dT0 when requested) from lam_1 = dL/dF_1; dtau(x) += dL/dtau(x).
-template <class ST, int N, typename S, bool DEV>
+template <class ST, int N, typename S, bool DEV, typename A = S>
 __global__ void __launch_bounds__(256) k_init_vjp(const Tables *__restrict__ tb, const double *__restrict__ n0,
                                                   const double *__restrict__ T0, const double *__restrict__ u0,
                                                   const double *__restrict__ noise, double amp,
@@ -148,18 +148,18 @@ __global__ void __launch_bounds__(256) k_init_vjp(const Tables *__restrict__ tb,
   basis_moments<D, N>(n, T, U, rr, M);
   double fe[Q];
   feq_prod<ST, N, double, false>(tb, M, fe);
-  S f[Q];
+  A f[Q];
 #pragma unroll
   for (int i = 0; i < Q; ++i) {
     const double sc = noise ? 1.0 + amp * noise[(int64_t)i * sites + site] : 1.0;
     const double fi = fe[i] * sc;
-    f[i] = DEV ? (S)(fi - tb->fref[i]) : (S)fi;
+    f[i] = DEV ? (A)(fi - tb->fref[i]) : (A)fi;
   }
   const Offs o = offs_periodic<ST, S>(tb, x, y, z);
-  S mu[Q];
-  pull_prod<ST, S, true>(tb, lam1, sites, o, mu);
+  A mu[Q];
+  pull_prod<ST, S, true, A>(tb, lam1, sites, o, mu);
   double taub;
-  if (!collide_vjp<ST, N, S, DEV>(tb, f, mu, tau_at<S>(tb, tau_field, site), taub)) set_err(err);
+  if (!collide_vjp<ST, N, A, DEV>(tb, f, mu, tau_at<S>(tb, tau_field, site), taub)) set_err(err);
   if (dtau != nullptr) dtau[site] += taub;
   // f now holds dL/df_0; through the noise factor to dL/df^eq
   double g[Q];
@@ -183,22 +183,22 @@ __global__ void __launch_bounds__(256) k_init_vjp(const Tables *__restrict__ tb,
   if (dT0 != nullptr) dT0[site] = Tb;
 }
 
-template <class ST, int N, typename S, bool DEV>
+template <class ST, int N, typename S, bool DEV, typename A = S>
 static hipError_t launch_adj_t(const AdjointArgs &a) {
   dim3 block(kAdjBX, kAdjBY, 1);
   const long nb = (long)((a.nx + kAdjBX - 1) / kAdjBX) * ((a.ny + kAdjBY - 1) / kAdjBY) * a.nz;
   dim3 grid((unsigned)nb, 1, 1);
   switch (a.op) {
     case ADJ_STEP:
-      hipLaunchKernelGGL((k_adjoint<ST, N, S, DEV>), grid, block, 0, a.stream, a.tb, (const S *)a.state,
+      hipLaunchKernelGGL((k_adjoint<ST, N, S, DEV, A>), grid, block, 0, a.stream, a.tb, (const S *)a.state,
                          (const S *)a.lam_in, (S *)a.lam_out, a.tau_field, a.dtau, a.err);
       break;
     case ADJ_MOMENTS:
-      hipLaunchKernelGGL((k_moments_vjp<ST, N, S, DEV>), grid, block, 0, a.stream, a.tb, (const S *)a.state,
+      hipLaunchKernelGGL((k_moments_vjp<ST, N, S, DEV, A>), grid, block, 0, a.stream, a.tb, (const S *)a.state,
                          a.grads, (S *)a.lam_out, a.err);
       break;
     case ADJ_INIT:
-      hipLaunchKernelGGL((k_init_vjp<ST, N, S, DEV>), grid, block, 0, a.stream, a.tb, a.n0, a.T0, a.u0, a.noise,
+      hipLaunchKernelGGL((k_init_vjp<ST, N, S, DEV, A>), grid, block, 0, a.stream, a.tb, a.n0, a.T0, a.u0, a.noise,
                          a.amp, (const S *)a.lam_in, a.tau_field, a.du0, a.dn0, a.dT0, a.dtau, a.err);
       break;
     default:
@@ -207,14 +207,18 @@ static hipError_t launch_adj_t(const AdjointArgs &a) {
   return hipGetLastError();
 }
 
+// storage 0: double; 1: float deviations updated in float; 2: float deviations updated in double
+template <class ST, int N>
+static hipError_t launch_adj_storage(const AdjointArgs &a) {
+  if (a.storage == 0) return launch_adj_t<ST, N, double, false>(a);
+  if (a.storage == 1) return launch_adj_t<ST, N, float, true>(a);
+  return launch_adj_t<ST, N, float, true, double>(a);
+}
+
 hipError_t launch_adjoint(const AdjointArgs &a) {
   if (a.stencil != ST_PROD2D) return hipErrorInvalidValue;
-  if (a.order == 2) {
-    if (a.storage == 0) return launch_adj_t<Stencil<ST_PROD2D, 3>, 2, double, false>(a);
-    return launch_adj_t<Stencil<ST_PROD2D, 3>, 2, float, true>(a);
-  }
-  if (a.storage == 0) return launch_adj_t<Stencil<ST_PROD2D, 4>, 3, double, false>(a);
-  return launch_adj_t<Stencil<ST_PROD2D, 4>, 3, float, true>(a);
+  if (a.order == 2) return launch_adj_storage<Stencil<ST_PROD2D, 3>, 2>(a);
+  return launch_adj_storage<Stencil<ST_PROD2D, 4>, 3>(a);
 }
 
 }  // namespace rlbm

@@ -174,9 +174,9 @@ rlbm_status rlbm_massive_window(const rlbm_model *model, double *lo, double *hi)
   return rc ? fail((rlbm_status)rc, err) : RLBM_OK;
 }
 
-rlbm_status rlbm_create(const rlbm_config *cfg, rlbm_lattice **out) {
-  if (!cfg || !out) return fail(RLBM_ERR_INVALID_ARG, "null argument");
-  *out = nullptr;
+// Validates a configuration and fills the lattice description h and its host tables t (no
+// device work; the caller owns both and frees them on failure).
+static rlbm_status prepare_lattice(const rlbm_config *cfg, rlbm_lattice *h, rlbm::Tables *t) {
   const rlbm_model &m = cfg->model;
   if (m.d != 2 && m.d != 3) return fail(RLBM_ERR_UNSUPPORTED, "d must be 2 or 3");
   for (int a = 0; a < m.d; ++a) {
@@ -201,9 +201,12 @@ rlbm_status rlbm_create(const rlbm_config *cfg, rlbm_lattice **out) {
   if (m.kind == RLBM_QUAD_MASSIVE_ONLATTICE && m.d == 3 && cfg->storage == RLBM_F64 &&
       (cfg->force[0] != 0.0 || cfg->force[1] != 0.0 || cfg->force[2] != 0.0))
     return fail(RLBM_ERR_UNSUPPORTED, "external force: the streaming kernel of the 3D massive rule has none");
-  if (cfg->storage != RLBM_F64 && cfg->storage != RLBM_F32_DEV) return fail(RLBM_ERR_INVALID_ARG, "bad storage");
+  if (cfg->storage != RLBM_F64 && cfg->storage != RLBM_F32_DEV && cfg->storage != RLBM_F32_DEV_F64)
+    return fail(RLBM_ERR_INVALID_ARG, "bad storage");
+  if (cfg->storage == RLBM_F32_DEV_F64 && m.kind != RLBM_QUAD_PRODUCT)
+    return fail(RLBM_ERR_UNSUPPORTED, "float storage with double arithmetic is built for the product rules");
   if (!(cfg->tau > 0.0) || !std::isfinite(cfg->tau)) return fail(RLBM_ERR_INVALID_ARG, "tau must be > 0");
-  if (cfg->storage == RLBM_F32_DEV && !(cfg->n_ref > 0.0)) return fail(RLBM_ERR_INVALID_ARG, "n_ref must be > 0");
+  if (cfg->storage != RLBM_F64 && !(cfg->n_ref > 0.0)) return fail(RLBM_ERR_INVALID_ARG, "n_ref must be > 0");
   const int64_t nz = m.d == 3 ? cfg->extent[2] : 1;
   const int64_t sites = cfg->extent[0] * cfg->extent[1] * nz;
   if (m.d == 3 && nz > 65535) return fail(RLBM_ERR_UNSUPPORTED, "nz > 65535");
@@ -211,19 +214,18 @@ rlbm_status rlbm_create(const rlbm_config *cfg, rlbm_lattice **out) {
   if (sites * (cfg->storage == RLBM_F64 ? 8 : 4) >= (int64_t(1) << 32))
     return fail(RLBM_ERR_UNSUPPORTED, "a population plane must stay below 4 GiB");
 
-  rlbm_lattice *h = new (std::nothrow) rlbm_lattice();
-  if (!h) return fail(RLBM_ERR_DEVICE, "out of host memory");
   h->cfg = *cfg;
   h->stencil = stencil_of(m);
   // default launch shapes (from sweeps of every variant on MI355X):
   //  * 3D product rules: float deviations keep ~100 populations in registers at occupancy 2,
   //    64 x 4 tiles in (y, z) patches per XCD (as fast as the untiled order, and half the
   //    re-reads from beyond the L2: 1.19x the algorithmic bytes instead of 2.35x); in double
-  //    the occupancy-2 build spills to scratch, so the unconstrained build (468 registers, one
-  //    wave per SIMD) in untiled 64 x 4 is 1.6x faster;
+  //    (storage or arithmetic) the occupancy-2 build spills to scratch, so the unconstrained
+  //    build (468 registers, one wave per SIMD) in untiled 64 x 4 is 1.6x faster;
   //  * the 3D massive rule: 64 x 2 XCD-ordered tiles (double, streaming kernel) or 64 x 1 patches
   //    (float);
-  //  * 2D product rules in double: rows of 64 sites;
+  //  * 2D product rules in double: rows of 64 sites; float storage with double arithmetic:
+  //    64 x 4 band tiles of the occupancy-2 build (4 % faster than rows of 64);
   //  * 2D on-lattice rules: 64 x 4 tiles of the occupancy-2 build, except the massive rules whose
   //    update fits in 128 registers (order 2, and order 3 in float deviations), which take the
   //    occupancy-4 build: four waves per SIMD instead of three, 7-27 % faster; and small lattices
@@ -231,29 +233,24 @@ rlbm_status rlbm_create(const rlbm_config *cfg, rlbm_lattice **out) {
   //    so that four times as many blocks spread over the CUs (about 9 % faster at 64 x 64)
   if (m.d == 3 && m.kind == RLBM_QUAD_MASSIVE_ONLATTICE) h->variant = cfg->storage == RLBM_F64 ? 4 : 8;
   else if (m.d == 3 && m.kind == RLBM_QUAD_UR_ONLATTICE) h->variant = 4;   // streaming kernel, as the 3D massive rule
-  else if (m.d == 3) h->variant = cfg->storage == RLBM_F64 ? 0 : 3;
+  else if (m.d == 3) h->variant = cfg->storage == RLBM_F32_DEV ? 3 : 0;
   else if (m.kind == RLBM_QUAD_PRODUCT && cfg->storage == RLBM_F64) h->variant = 5;
+  else if (m.kind == RLBM_QUAD_PRODUCT && cfg->storage == RLBM_F32_DEV_F64) h->variant = 9;
   else if (m.kind == RLBM_QUAD_MASSIVE_ONLATTICE && (m.order == 2 || cfg->storage != RLBM_F64)) h->variant = 10;
   else if (m.kind == RLBM_QUAD_UR_ONLATTICE && sites <= 65536) h->variant = 5;
   else if (m.kind != RLBM_QUAD_PRODUCT) h->variant = 3;
   h->sites = sites;
   std::string err;
   int rc = rlbm::build_quadrature(m.d, m.zeta, m.order, m.kind, m.v0, h->quad, err);
-  if (rc) {
-    delete h;
-    return fail((rlbm_status)rc, err);
-  }
+  if (rc) return fail((rlbm_status)rc, err);
   // integer streaming reads x - n_i with one periodic wrap: a periodic axis must be at least as
   // long as the longest displacement along it
   for (int i = 0; i < h->quad.Q; ++i)
     for (int a = 0; a < m.d; ++a)
-      if (cfg->bc[a] == RLBM_PERIODIC && std::fabs(h->quad.disp[i * m.d + a]) > (double)cfg->extent[a]) {
-        delete h;
+      if (cfg->bc[a] == RLBM_PERIODIC && std::fabs(h->quad.disp[i * m.d + a]) > (double)cfg->extent[a])
         return fail(RLBM_ERR_INVALID_ARG, "a periodic extent is shorter than the stencil's longest displacement");
-      }
-  rlbm::Tables *t = new rlbm::Tables;
   int bc[3] = {cfg->bc[0], cfg->bc[1], cfg->bc[2]};
-  rc = rlbm::build_tables(h->quad, cfg->tau, cfg->storage == RLBM_F32_DEV ? cfg->n_ref : 1.0, cfg->storage,
+  rc = rlbm::build_tables(h->quad, cfg->tau, cfg->storage != RLBM_F64 ? cfg->n_ref : 1.0, cfg->storage,
                           cfg->extent, bc, *t, err);
   if (!rc && m.d == 3) rc = rlbm::build_eos_fit(m.zeta, *t, err);
   if (!rc) {
@@ -268,10 +265,25 @@ rlbm_status rlbm_create(const rlbm_config *cfg, rlbm_lattice **out) {
     t->has_force = (m.zeta > 0.0 && m.kind != RLBM_QUAD_UR_ONLATTICE &&
                     (t->g[0] != 0.0 || t->g[1] != 0.0 || t->g[2] != 0.0)) ? 1 : 0;
   }
-  if (rc) {
+  if (rc) return fail((rlbm_status)rc, err);
+  return RLBM_OK;
+}
+
+rlbm_status rlbm_create(const rlbm_config *cfg, rlbm_lattice **out) {
+  if (!cfg || !out) return fail(RLBM_ERR_INVALID_ARG, "null argument");
+  *out = nullptr;
+  rlbm_lattice *h = new (std::nothrow) rlbm_lattice();
+  rlbm::Tables *t = new (std::nothrow) rlbm::Tables;
+  if (!h || !t) {
+    delete h;
+    delete t;
+    return fail(RLBM_ERR_DEVICE, "out of host memory");
+  }
+  const rlbm_status st = prepare_lattice(cfg, h, t);
+  if (st != RLBM_OK) {
     delete t;
     delete h;
-    return fail((rlbm_status)rc, err);
+    return st;
   }
   hipError_t he = hipMalloc(&h->d_tables, sizeof(rlbm::Tables));
   if (he == hipSuccess) he = hipMalloc(&h->d_err, sizeof(int));
@@ -327,9 +339,8 @@ rlbm_status rlbm_init(rlbm_lattice *h, const double *n0, const double *T0, const
   return he == hipSuccess ? RLBM_OK : fail(RLBM_ERR_DEVICE, hipGetErrorString(he));
 }
 
-static hipError_t step_launches(rlbm_lattice *h, void *f_a, void *f_b, int32_t nsteps, const rlbm_fields *last,
-                                hipStream_t stream) {
-  rlbm::LaunchArgs a = base_args(h, stream);
+// nsteps step launches alternating between f_a and f_b (a: the lattice's launch arguments)
+static hipError_t launch_steps(rlbm::LaunchArgs a, void *f_a, void *f_b, int32_t nsteps, const rlbm_fields *last) {
   a.op = rlbm::OP_STEP;
   for (int32_t s = 0; s < nsteps; ++s) {
     a.fin = (s & 1) ? f_b : f_a;
@@ -339,6 +350,11 @@ static hipError_t step_launches(rlbm_lattice *h, void *f_a, void *f_b, int32_t n
     if (he != hipSuccess) return he;
   }
   return hipSuccess;
+}
+
+static hipError_t step_launches(rlbm_lattice *h, void *f_a, void *f_b, int32_t nsteps, const rlbm_fields *last,
+                                hipStream_t stream) {
+  return launch_steps(base_args(h, stream), f_a, f_b, nsteps, last);
 }
 
 rlbm_status rlbm_step(rlbm_lattice *h, void *f_a, void *f_b, int32_t nsteps, const rlbm_fields *last,

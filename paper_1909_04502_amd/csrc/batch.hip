@@ -19,7 +19,7 @@ __device__ __forceinline__ int wrap_b(int v, int n, int open) {
   return v >= n ? v - n : v;
 }
 
-template <class ST, int N, typename S, bool DEV, int BX, int BY, bool EXT, bool NT>
+template <class ST, int N, typename S, bool DEV, int BX, int BY, bool EXT, bool NT, typename A = S>
 __global__ void __launch_bounds__(BX * BY) k_step_batch(const Tables *__restrict__ tabs,
                                                         const int64_t *__restrict__ elem_off,
                                                         const int2 *__restrict__ tiles, int ntiles,
@@ -48,56 +48,56 @@ __global__ void __launch_bounds__(BX * BY) k_step_batch(const Tables *__restrict
       o.y[dd + 1] = (uint32_t)wrap_b(y + dd, ny, tb->open[1]) * (uint32_t)nx * (uint32_t)sizeof(S);
       o.z[dd + 1] = 0u;
     }
-    S f[ST::Q];
-    pull_prod<ST, S, false>(tb, fi, sites, o, f);
-    const Macro<ST::D> mac = collide_prod<ST, N, S, DEV, true, EXT>(tb, f, tb->tau, EXT ? site_wall(tb, x, y, 0) : -1.0);
+    A f[ST::Q];
+    pull_prod<ST, S, false, A>(tb, fi, sites, o, f);
+    const Macro<ST::D> mac = collide_prod<ST, N, A, DEV, true, EXT>(tb, f, tb->tau, EXT ? site_wall(tb, x, y, 0) : -1.0);
     if (!mac.ok) *(volatile int *)err = 1;
     const uint32_t so = (uint32_t)site * (uint32_t)sizeof(S);
 #pragma unroll
-    for (int i = 0; i < ST::Q; ++i) put_pop<NT>(fo, sites, so, i, f[i]);
+    for (int i = 0; i < ST::Q; ++i) put_pop<NT>(fo, sites, so, i, (S)f[i]);
   }
 }
 
-template <class ST, int N, typename S, bool DEV, bool EXT, bool NT>
+template <class ST, int N, typename S, bool DEV, bool EXT, bool NT, typename A = S>
 static hipError_t launch_batch_t(const BatchArgs &a) {
   const int nb = a.blocks;
   switch (a.tile) {
     case 0:
-      hipLaunchKernelGGL((k_step_batch<ST, N, S, DEV, 64, 4, EXT, NT>), dim3(nb), dim3(64, 4), 0, a.stream, a.tabs,
+      hipLaunchKernelGGL((k_step_batch<ST, N, S, DEV, 64, 4, EXT, NT, A>), dim3(nb), dim3(64, 4), 0, a.stream, a.tabs,
                          a.elem_off, a.tiles, a.ntiles, (const S *)a.fin, (S *)a.fout, a.err);
       break;
     case 1:
-      hipLaunchKernelGGL((k_step_batch<ST, N, S, DEV, 64, 2, EXT, NT>), dim3(nb), dim3(64, 2), 0, a.stream, a.tabs,
+      hipLaunchKernelGGL((k_step_batch<ST, N, S, DEV, 64, 2, EXT, NT, A>), dim3(nb), dim3(64, 2), 0, a.stream, a.tabs,
                          a.elem_off, a.tiles, a.ntiles, (const S *)a.fin, (S *)a.fout, a.err);
       break;
     case 2:
-      hipLaunchKernelGGL((k_step_batch<ST, N, S, DEV, 128, 2, EXT, NT>), dim3(nb), dim3(128, 2), 0, a.stream, a.tabs,
+      hipLaunchKernelGGL((k_step_batch<ST, N, S, DEV, 128, 2, EXT, NT, A>), dim3(nb), dim3(128, 2), 0, a.stream, a.tabs,
                          a.elem_off, a.tiles, a.ntiles, (const S *)a.fin, (S *)a.fout, a.err);
       break;
     default:
-      hipLaunchKernelGGL((k_step_batch<ST, N, S, DEV, 256, 1, EXT, NT>), dim3(nb), dim3(256, 1), 0, a.stream, a.tabs,
+      hipLaunchKernelGGL((k_step_batch<ST, N, S, DEV, 256, 1, EXT, NT, A>), dim3(nb), dim3(256, 1), 0, a.stream, a.tabs,
                          a.elem_off, a.tiles, a.ntiles, (const S *)a.fin, (S *)a.fout, a.err);
       break;
   }
   return hipGetLastError();
 }
 
+// storage 0: double; 1: float deviations updated in float; 2: float deviations updated in double
+template <class ST, int N, bool EXT, bool NT>
+static hipError_t launch_batch_storage(const BatchArgs &a) {
+  if (a.storage == 0) return launch_batch_t<ST, N, double, false, EXT, NT>(a);
+  if (a.storage == 1) return launch_batch_t<ST, N, float, true, EXT, NT>(a);
+  return launch_batch_t<ST, N, float, true, EXT, NT, double>(a);
+}
+
 template <bool NT>
 static hipError_t launch_batch_ext(const BatchArgs &a) {
   if (a.ext) {
-    if (a.order == 2) {
-      if (a.storage == 0) return launch_batch_t<Stencil<ST_PROD2D, 3>, 2, double, false, true, NT>(a);
-      return launch_batch_t<Stencil<ST_PROD2D, 3>, 2, float, true, true, NT>(a);
-    }
-    if (a.storage == 0) return launch_batch_t<Stencil<ST_PROD2D, 4>, 3, double, false, true, NT>(a);
-    return launch_batch_t<Stencil<ST_PROD2D, 4>, 3, float, true, true, NT>(a);
+    if (a.order == 2) return launch_batch_storage<Stencil<ST_PROD2D, 3>, 2, true, NT>(a);
+    return launch_batch_storage<Stencil<ST_PROD2D, 4>, 3, true, NT>(a);
   }
-  if (a.order == 2) {
-    if (a.storage == 0) return launch_batch_t<Stencil<ST_PROD2D, 3>, 2, double, false, false, NT>(a);
-    return launch_batch_t<Stencil<ST_PROD2D, 3>, 2, float, true, false, NT>(a);
-  }
-  if (a.storage == 0) return launch_batch_t<Stencil<ST_PROD2D, 4>, 3, double, false, false, NT>(a);
-  return launch_batch_t<Stencil<ST_PROD2D, 4>, 3, float, true, false, NT>(a);
+  if (a.order == 2) return launch_batch_storage<Stencil<ST_PROD2D, 3>, 2, false, NT>(a);
+  return launch_batch_storage<Stencil<ST_PROD2D, 4>, 3, false, NT>(a);
 }
 
 hipError_t launch_batch(const BatchArgs &a) {

@@ -130,15 +130,17 @@ __device__ __forceinline__ void gather_onlat(const Tables *__restrict__ tb, cons
   gather_onlat_impl<ST, S, R>(fin, sites, ox, oy, oz, f, std::make_integer_sequence<int, ST::Q>{});
 }
 
-// pre-collision populations at the site
-template <class ST, typename S>
+// pre-collision populations at the site, in the arithmetic type A (the storage type S, or double
+// for float deviations updated in double: product rules)
+template <class ST, typename S, typename A = S>
 __device__ __forceinline__ void gather(const Tables *__restrict__ tb, const S *__restrict__ fin, int64_t sites, int x,
-                                       int y, int z, S (&f)[ST::Q]) {
+                                       int y, int z, A (&f)[ST::Q]) {
   if constexpr (ST::ONLAT) {
+    static_assert(sizeof(A) == sizeof(S), "on-lattice rules compute in their storage type");
     gather_onlat<ST, S>(tb, fin, sites, x, y, z, f);
   } else {
     const Offs o = make_offs<ST, S>(tb, x, y, z);
-    pull_prod<ST, S>(tb, fin, sites, o, f);
+    pull_prod<ST, S, false, A>(tb, fin, sites, o, f);
   }
 }
 
@@ -154,11 +156,12 @@ __device__ __forceinline__ Macro<ST::D> collide_site(const Tables *__restrict__ 
     return collide_prod<ST, N, S, DEV, RELAX, EXT>(tb, f, tau, wallT);
 }
 
-template <class ST, typename S, bool NT = false>
+// post-collision populations of the site, rounded to the storage type
+template <class ST, typename S, bool NT = false, typename A = S>
 __device__ __forceinline__ void store_site(S *__restrict__ fout, int64_t sites, uint32_t site_off,
-                                           const S (&f)[ST::Q]) {
+                                           const A (&f)[ST::Q]) {
 #pragma unroll
-  for (int i = 0; i < ST::Q; ++i) put_pop<NT>(fout, sites, site_off, i, f[i]);
+  for (int i = 0; i < ST::Q; ++i) put_pop<NT>(fout, sites, site_off, i, (S)f[i]);
 }
 
 // Site of this thread.  Blocks form a 1D grid over tiles of tl.bx x tl.by x
@@ -215,7 +218,7 @@ __device__ __forceinline__ bool site_coords(const Tables *__restrict__ tb, const
   return x < tb->nx && y < tb->ny && z < tb->nz;
 }
 
-template <class ST, int N, typename S, bool DEV, int OCC, bool EXT, bool NT>
+template <class ST, int N, typename S, bool DEV, int OCC, bool EXT, bool NT, typename A = S>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(OCC > 0 ? OCC : 1, 8))) k_step(const Tables *__restrict__ tb, const S *__restrict__ fin,
                                               S *__restrict__ fout, const void *__restrict__ tau_field,
                                               FieldPtrs last, int *err, Tiling tl) {
@@ -223,16 +226,16 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(OCC > 
   if (!site_coords(tb, tl, x, y, z)) return;
   const int64_t sites = tb->sites;
   const int64_t site = ((int64_t)z * tb->ny + y) * tb->nx + x;
-  S f[ST::Q];
-  gather<ST, S>(tb, fin, sites, x, y, z, f);
+  A f[ST::Q];
+  gather<ST, S, A>(tb, fin, sites, x, y, z, f);
   const double tau = site_tau<S>(tb, tau_field, site);
-  const Macro<ST::D> mac = collide_site<ST, N, S, DEV, true, EXT>(tb, f, tau, EXT ? site_wall(tb, x, y, z) : -1.0);
+  const Macro<ST::D> mac = collide_site<ST, N, A, DEV, true, EXT>(tb, f, tau, EXT ? site_wall(tb, x, y, z) : -1.0);
   if (!mac.ok) flag_error(err);
   // a fresh copy of the plane size for the store addresses: otherwise the compiler keeps the
   // load phase's plane offsets alive (in spilled scalar registers) for reuse here
   int64_t sites_st = sites;
   if constexpr (ST::D == 3) asm volatile("" : "+s"(sites_st));
-  store_site<ST, S, NT>(fout, sites_st, (uint32_t)site * (uint32_t)sizeof(S), f);
+  store_site<ST, S, NT, A>(fout, sites_st, (uint32_t)site * (uint32_t)sizeof(S), f);
   if (last.any) write_fields<ST::D>(last, site, sites, mac);
 }
 
@@ -353,22 +356,22 @@ __global__ void __launch_bounds__(256) k_init_stream(const Tables *__restrict__ 
   if (fields0.any) write_fields<D>(fields0, site, sites, mac);
 }
 
-template <class ST, int N, typename S, bool DEV>
+template <class ST, int N, typename S, bool DEV, typename A = S>
 __global__ void __launch_bounds__(256) k_moments(const Tables *__restrict__ tb, const S *__restrict__ fin,
                                                  FieldPtrs out, int *err, Tiling tl) {
   int x, y, z;
   if (!site_coords(tb, tl, x, y, z)) return;
   const int64_t sites = tb->sites;
   const int64_t site = ((int64_t)z * tb->ny + y) * tb->nx + x;
-  S f[ST::Q];
-  gather<ST, S>(tb, fin, sites, x, y, z, f);
-  const Macro<ST::D> mac = collide_site<ST, N, S, DEV, false>(tb, f, 1.0);
+  A f[ST::Q];
+  gather<ST, S, A>(tb, fin, sites, x, y, z, f);
+  const Macro<ST::D> mac = collide_site<ST, N, A, DEV, false>(tb, f, 1.0);
   if (!mac.ok) flag_error(err);
   write_fields<ST::D>(out, site, sites, mac);
 }
 
 // f(x, 0) = f^eq(n0, T0, U(u0)) (1 + amp xi), then collide; store f*(x, 0).
-template <class ST, int N, typename S, bool DEV>
+template <class ST, int N, typename S, bool DEV, typename A = S>
 __global__ void __launch_bounds__(256) k_init(const Tables *__restrict__ tb, const double *__restrict__ n0,
                                               const double *__restrict__ T0, const double *__restrict__ u0,
                                               const double *__restrict__ noise, double amp, S *__restrict__ fout,
@@ -425,20 +428,22 @@ __global__ void __launch_bounds__(256) k_init(const Tables *__restrict__ tb, con
 #pragma unroll
     for (int i = 0; i < Q; ++i) fd[i] *= 1.0 + amp * noise[(int64_t)i * sites + site];
   }
-  S f[Q];
+  // the update's form: f, or the deviations f - f^ref (in float, or in double when float deviations
+  // are updated in double)
+  A f[Q];
 #pragma unroll
-  for (int i = 0; i < Q; ++i) f[i] = DEV ? (S)(fd[i] - tb->fref[i]) : (S)fd[i];
+  for (int i = 0; i < Q; ++i) f[i] = DEV ? (A)(fd[i] - tb->fref[i]) : (A)fd[i];
   const double tau = site_tau<S>(tb, tau_field, site);
-  const Macro<D> mac = collide_site<ST, N, S, DEV, true, true>(tb, f, tau, site_wall(tb, x, y, z));
+  const Macro<D> mac = collide_site<ST, N, A, DEV, true, true>(tb, f, tau, site_wall(tb, x, y, z));
   if (!mac.ok) flag_error(err);
-  store_site<ST, S>(fout, sites, (uint32_t)site * (uint32_t)sizeof(S), f);
+  store_site<ST, S, false, A>(fout, sites, (uint32_t)site * (uint32_t)sizeof(S), f);
   if (fields0.any) write_fields<D>(fields0, site, sites, mac);
 }
 
 // ---------------------------------------------------------------------------
 // Dispatch
 // ---------------------------------------------------------------------------
-template <class ST, int N, typename S, bool DEV>
+template <class ST, int N, typename S, bool DEV, typename A = S>
 static hipError_t launch_t(const LaunchArgs &a) {
   const Variant vr = kVariants[(a.op == OP_STEP && a.variant >= 0 && a.variant < kNumVariants) ? a.variant : 0];
   const int by = ST::D == 2 ? vr.by * vr.bz : vr.by, bz = ST::D == 2 ? 1 : vr.bz;
@@ -465,12 +470,13 @@ static hipError_t launch_t(const LaunchArgs &a) {
       auto go = [&](auto occ, auto ext, auto nt) {
         constexpr int O = decltype(occ)::value;
         constexpr bool E = decltype(ext)::value, T = decltype(nt)::value;
-        if constexpr (kStream)
+        if constexpr (kStream) {
           hipLaunchKernelGGL((k_step_stream<ST, N, S, DEV, O, T>), grid, block, 0, a.stream, a.tb,
                              (const S *)a.fin, (S *)a.fout, a.tau_field, a.fields, a.err, tl);
-        else
-          hipLaunchKernelGGL((k_step<ST, N, S, DEV, O, E, T>), grid, block, 0, a.stream, a.tb, (const S *)a.fin,
+        } else {
+          hipLaunchKernelGGL((k_step<ST, N, S, DEV, O, E, T, A>), grid, block, 0, a.stream, a.tb, (const S *)a.fin,
                              (S *)a.fout, a.tau_field, a.fields, a.err, tl);
+        }
       };
       using O0 = std::integral_constant<int, 0>;
       using O2 = std::integral_constant<int, 2>;
@@ -503,7 +509,7 @@ static hipError_t launch_t(const LaunchArgs &a) {
         hipLaunchKernelGGL((k_moments_stream<ST, N, S, DEV>), grid, block, 0, a.stream, a.tb, (const S *)a.fin,
                            a.fields, a.err, tl);
       else
-        hipLaunchKernelGGL((k_moments<ST, N, S, DEV>), grid, block, 0, a.stream, a.tb, (const S *)a.fin, a.fields,
+        hipLaunchKernelGGL((k_moments<ST, N, S, DEV, A>), grid, block, 0, a.stream, a.tb, (const S *)a.fin, a.fields,
                            a.err, tl);
       break;
     case OP_INIT:
@@ -511,7 +517,7 @@ static hipError_t launch_t(const LaunchArgs &a) {
         hipLaunchKernelGGL((k_init_stream<ST, N, S, DEV>), grid, block, 0, a.stream, a.tb, a.n0, a.T0, a.u0,
                            a.noise, a.amp, (S *)a.fout, a.tau_field, a.fields, a.err, tl);
       else
-        hipLaunchKernelGGL((k_init<ST, N, S, DEV>), grid, block, 0, a.stream, a.tb, a.n0, a.T0, a.u0, a.noise,
+        hipLaunchKernelGGL((k_init<ST, N, S, DEV, A>), grid, block, 0, a.stream, a.tb, a.n0, a.T0, a.u0, a.noise,
                            a.amp, (S *)a.fout, a.tau_field, a.fields, a.err, tl);
       break;
     default:
@@ -520,10 +526,14 @@ static hipError_t launch_t(const LaunchArgs &a) {
   return hipGetLastError();
 }
 
+// storage 0: double; 1: float deviations updated in float; 2: float deviations updated in double
+// (product rules)
 template <class ST, int N>
 static hipError_t launch_storage(const LaunchArgs &a) {
   if (a.storage == 0) return launch_t<ST, N, double, false>(a);
-  return launch_t<ST, N, float, true>(a);
+  if (a.storage == 1) return launch_t<ST, N, float, true>(a);
+  if constexpr (!ST::ONLAT) return launch_t<ST, N, float, true, double>(a);
+  return hipErrorInvalidValue;
 }
 
 hipError_t launch(const LaunchArgs &a) {

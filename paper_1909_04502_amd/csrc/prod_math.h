@@ -83,10 +83,11 @@ __device__ __forceinline__ constexpr bool group_start_3d(int k) {
 }
 __device__ __forceinline__ constexpr int group_first_3d(int k) { return k < 6 ? 0 : k < 18 ? 6 + 4 * ((k - 6) / 4) : k & ~1; }
 
-template <class ST, typename S, bool TRANSPOSE = false>
+// A is the arithmetic type of the interpolation and of the result (the storage type S, or double
+// for float deviations updated in double).
+template <class ST, typename S, bool TRANSPOSE = false, typename A = S>
 __device__ __forceinline__ void pull_prod(const Tables *__restrict__ tb, const S *__restrict__ fin, int64_t sites,
-                                          const Offs &o, S (&f)[ST::Q]) {
-  typedef S A;
+                                          const Offs &o, A (&f)[ST::Q]) {
   constexpr int D = ST::D, ND = ST::NDIR, KR = ST::NSHELL;
   typedef const __attribute__((address_space(1))) char gchar;   // keeps the loads global after laundering
   gchar *base = (gchar *)fin;
@@ -153,7 +154,7 @@ __device__ __forceinline__ void pull_prod(const Tables *__restrict__ tb, const S
           oz = -oz;
         }
         const uint32_t off = o.x[ox + 1] + o.y[oy + 1] + o.z[oz + 1];
-        acc += pw[z][nfar] * *(const __attribute__((address_space(1))) S *)(plane + off);
+        acc += pw[z][nfar] * (A) * (const __attribute__((address_space(1))) S *)(plane + off);
       }
       f[i] = acc;
       }

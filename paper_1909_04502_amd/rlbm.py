@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(HERE, "librlbm.so")
 
 OK, ERR_INVALID_ARG, ERR_UNSUPPORTED, ERR_QUADRATURE, ERR_DEVICE, ERR_NONPHYSICAL = range(6)
 KIND = {"ur_onlattice": 0, "product": 1, "massive_onlattice": 2}
-STORAGE = {"f64": 0, "f32dev": 1}
+STORAGE = {"f64": 0, "f32dev": 1, "f32dev_f64": 2}
 BC = {"periodic": 0, "open": 1, "wall": 2}
 
 

@@ -49,7 +49,7 @@ def make(specs, storage="f64", order=3):
     return b, ns, Ts, us
 
 
-@pytest.mark.parametrize("storage,order", [("f64", 3), ("f64", 2), ("f32dev", 3)])
+@pytest.mark.parametrize("storage,order", [("f64", 3), ("f64", 2), ("f32dev", 3), ("f32dev_f64", 3)])
 def test_batch_equals_each_lattice_alone(storage, order):
     print(f"[case] batch vs solo {storage} N={order}", flush=True)
     b, ns, Ts, us = make(SPECS, storage, order)

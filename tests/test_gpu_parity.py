@@ -122,38 +122,70 @@ def test_c1_full_length_against_oracle():
     assert max(err.values()) < 1e-11
 
 
-def test_c2_full_length_sampled_against_oracle():
-    """The headline workload over its full 1000 steps: 1024 x 1024, zeta = 1, N = 3 product rule,
-    FP64, tau = 0.8, Taylor-Green u0 = 0.1 with density noise 1e-3 (seed 2), in the default launch
-    configuration; n, eps, T and U at 512 seeded sites against the oracle's own 1000 steps
-    (tests/golden/make_c2_samples.py); the two paths' round-off accumulates over the run."""
+U_F32 = 2.0 ** -24      # unit round-off of float
+
+
+def c2_golden():
+    """The oracle's samples of the headline workload at its checkpoints (tests/golden/
+    make_c2_samples.py): {"L", "ys", "xs", "samples": {step: {n, eps, T, U}}}."""
     import json
     import os
+    path = os.path.join(os.path.dirname(__file__), "golden", "c2_samples.json")
+    if os.path.exists(path):
+        return json.load(open(path))
+    # the 1000-step samples alone (same sites, same script before it kept the earlier checkpoints)
+    g = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "c2_1000_samples.json")))
+    return {"L": g["L"], "ys": g["ys"], "xs": g["xs"],
+            "samples": {str(g["steps"]): {k: g[k] for k in ("n", "eps", "T", "U")}}}
+
+
+# error bounds per checkpoint k (max-normalised, per field).  Double: the two paths' round-off.
+# Float deviations updated in float: the rounding of the interpolated pull and of the moment
+# sums has the same sign pattern from one step to the next (the state changes slowly), so it
+# adds up coherently and the error grows linearly in k; measured on this workload 0.42 u per
+# step on U, 0.02 u on n (u = 2^-24), bounded by u per step plus a constant 16 u.  Float
+# deviations updated in double: only the rounding of the stored values remains, which does
+# not build up coherently (measured at step 1000: 2.7e-8 = 0.45 u on U, 4e-9 on n, against
+# 2.5e-5 and 1.2e-6 when updated in float); bounded by 32 u + sqrt(k) u.
+C2_BOUNDS = {"f64": lambda k: 1e-11,
+             "f32dev": lambda k: (16 + k) * U_F32,
+             "f32dev_f64": lambda k: (32 + math.sqrt(k)) * U_F32}
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32dev_f64", "f32dev"])
+def test_c2_full_length_sampled_against_oracle(storage):
+    """The headline workload over its full 1000 steps: 1024 x 1024, zeta = 1, N = 3 product rule,
+    tau = 0.8, Taylor-Green u0 = 0.1 with density noise 1e-3 (seed 2), in the default launch
+    configuration; n, eps, T and U at 512 seeded sites against the FP64 oracle's own run at each
+    checkpoint, within the error growth stated for the storage mode (C2_BOUNDS)."""
     from paper_1909_04502_amd import rlbm as R
-    print("[case] C2 full length", flush=True)
-    path = os.path.join(os.path.dirname(__file__), "golden", "c2_1000_samples.json")
-    if not os.path.exists(path):
-        pytest.skip("tests/golden/c2_1000_samples.json not generated (tests/golden/make_c2_samples.py)")
-    gold = json.load(open(path))
-    L, steps = gold["L"], gold["steps"]
+    print(f"[case] C2 full length {storage}", flush=True)
+    gold = c2_golden()
+    L = gold["L"]
     n, T, u = (torch.tensor(a) for a in W.taylor_green_2d(L, L, 0.1, density_sigma=1e-3, seed=2))
-    lat = R.Lattice(d=2, zeta=1.0, order=3, extent=(L, L), tau=0.8)
-    res = lat.step(lat.init(n, T, u), lat.new_state(), steps)
-    mom = lat.moments(res)
-    lat.sync()
+    lat = R.Lattice(d=2, zeta=1.0, order=3, extent=(L, L), storage=storage, tau=0.8)
     ys, xs = torch.tensor(gold["ys"]), torch.tensor(gold["xs"])
-    err = {k: rel(mom[k].cpu()[ys, xs], torch.tensor(gold[k], dtype=torch.float64)) for k in ("n", "eps", "T")}
-    err["U"] = rel(mom["U"].cpu()[1:, ys, xs], torch.tensor(gold["U"], dtype=torch.float64)[1:])
-    print("C2 1000-step errors", err, flush=True)
-    # measured: n 1.1e-13, eps 6.0e-14, T 1.4e-13, U 1.4e-12 (the velocity is ~0.1 of U^0)
-    assert max(err.values()) < 1e-11
+    fa, fb = lat.init(n, T, u), lat.new_state()
+    cur, done = fa, 0
+    for k in sorted(int(s) for s in gold["samples"]):
+        cur = lat.step(cur, fb if cur is fa else fa, k - done)
+        done = k
+        mom = lat.moments(cur)
+        lat.sync()
+        ref = gold["samples"][str(k)]
+        err = {f: rel(mom[f].cpu()[ys, xs], torch.tensor(ref[f], dtype=torch.float64)) for f in ("n", "eps", "T")}
+        err["U"] = rel(mom["U"].cpu()[1:, ys, xs], torch.tensor(ref["U"], dtype=torch.float64)[1:])
+        print(f"C2 {storage} step {k} errors", err, flush=True)
+        assert max(err.values()) < C2_BOUNDS[storage](k), (k, err)
 
 
+@pytest.mark.parametrize("storage", ["f32dev", "f32dev_f64"])
 @pytest.mark.parametrize("name", ["c2_ragged", "n2_open"])
-def test_f32_deviation_storage(name):
-    """Float deviations from f^ref with double eigenproblem / EOS: macro fields within 1e-5 after 40 steps."""
-    print(f"[case] f32dev {name}", flush=True)
-    gl, ol, (n, T, u, xi, amp) = setup_case(name, storage="f32dev")
+def test_f32_deviation_storage(name, storage):
+    """Float deviations from f^ref (updated in float, or in double): macro fields within 1e-5 of
+    the oracle after 40 steps (measured: about 1e-6 in float arithmetic, 1e-7 in double)."""
+    print(f"[case] {storage} {name}", flush=True)
+    gl, ol, (n, T, u, xi, amp) = setup_case(name, storage=storage)
     nsteps = 40
     fa = gl.init(n, T, u, xi, amp)
     fb = gl.new_state()
@@ -166,7 +198,7 @@ def test_f32_deviation_storage(name):
     ref = ol.macro(ol.stream(fs))
     errs = {k: rel(mom[k], ref[k]) for k in ("n", "eps", "T")}
     errs.update({f"U{a}": rel(mom["U"][a], ref["U"][a]) for a in range(3)})
-    print("f32dev errors", errs, flush=True)
+    print(f"{storage} errors", errs, flush=True)
     assert max(errs.values()) < F32_TOL
 
 

@@ -219,47 +219,54 @@ def test_full_size_shock_tube_sampled():
     assert err < F32_TOL
 
 
-def test_c3_full_length_float_deviations_against_fp64():
-    """The C3 shock tube over its full 2000 steps (256^3, zeta = 1, N = 3, open x): the FP64 run against
-    the oracle's own 2000 steps on the equivalent 256 x 1 x 1 lattice (tests/golden/make_c3_profile.py),
-    the float-deviation run against the FP64 run, both on the x-profiles of n, eps, T and U^x, and
-    the symmetries of the set-up: the state depends on x only,
+U_F32 = 2.0 ** -24      # unit round-off of float
+
+# error bounds per checkpoint k (max-normalised, per field).  Double: the two paths' round-off.
+# Float deviations updated in float: correlated rounding of the interpolation and moment sums
+# grows linearly in k (measured 2.1 u per step on U^x, 1.2 u on n, u = 2^-24), bounded by
+# 4 u per step plus 16 u.  Updated in double: the rounding of the stored values alone, which
+# does not build up coherently (measured on U^x 2.3e-8 at step 10, 1.4e-7 = 2.4 u at step 2000,
+# against 2.5e-4 when updated in float), bounded by 32 u + sqrt(k) u.
+C3_BOUNDS = {"f64": lambda k: 1e-11,
+             "f32dev": lambda k: (16 + 4 * k) * U_F32,
+             "f32dev_f64": lambda k: (32 + k ** 0.5) * U_F32}
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32dev_f64", "f32dev"])
+def test_c3_full_length_against_oracle(storage):
+    """The C3 shock tube over its full 2000 steps (256^3, zeta = 1, N = 3, open x): the x-profiles of
+    n, eps, T and U^x against the oracle's own run on the equivalent 256 x 1 x 1 lattice after 10,
+    100, 500, 1000 and 2000 steps (tests/golden/make_c3_profile.py), within the error growth stated
+    for the storage mode (C3_BOUNDS); and the symmetries of the set-up: the state depends on x only,
     so every (y, z) column equals the first one (each site's update is the same arithmetic on the
     same inputs) and U^y = U^z = 0 up to round-off.  tau = 0.8: at the configuration's tau = 0.6 the
     scheme itself (the FP64 oracle on the equivalent 256 x 1 x 1 lattice) turns non-physical at
     step 113, populations going negative at the discontinuity from step 2."""
     from paper_1909_04502_amd import rlbm as R
+    print(f"[case] C3 full length {storage}", flush=True)
+    gold = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "c3_tau08_profiles.json")))
     ext = (256, 256, 256)
+    assert gold["nx"] == ext[0] and gold["tau"] == 0.8
     bc = ("open", "periodic", "periodic")
-    steps = 2000
     n, T, u = (torch.tensor(a) for a in riemann(ext))
-    prof = {}
-    for storage, sym_tol in (("f64", 1e-12), ("f32dev", 1e-5)):
-        print(f"[case] C3 full length {storage}", flush=True)
-        gl = R.Lattice(d=3, zeta=1.0, order=3, extent=ext, bc=bc, storage=storage, tau=0.8)
-        fa = gl.init(n, T, u)
-        res = gl.step(fa, gl.new_state(), steps)
-        mac = gl.moments(res)
+    gl = R.Lattice(d=3, zeta=1.0, order=3, extent=ext, bc=bc, storage=storage, tau=0.8)
+    fa, fb = gl.init(n, T, u), gl.new_state()
+    cur, done = fa, 0
+    for k in gold["checkpoints"]:
+        cur = gl.step(cur, fb if cur is fa else fa, k - done)
+        done = k
+        mac = gl.moments(cur)
         gl.sync()
-        for k in ("n", "eps", "T"):
-            assert (mac[k] - mac[k][:1, :1, :]).abs().max().item() == 0.0, (storage, k)
-        assert (mac["U"] - mac["U"][:, :1, :1, :]).abs().max().item() == 0.0, storage
-        assert mac["U"][2:].abs().max().item() < sym_tol, storage
-        prof[storage] = {k: mac[k][0, 0].cpu() for k in ("n", "eps", "T")}
-        prof[storage]["Ux"] = mac["U"][1, 0, 0].cpu()
-        del gl, fa, res, mac
-        torch.cuda.empty_cache()
-    # the FP64 run against the oracle's own 2000 steps (tests/golden/make_c3_profile.py)
-    gold = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "c3_tau08_2000_profile.json")))
-    assert gold["steps"] == steps and gold["nx"] == ext[0]
-    ferr = {k: rel(prof["f64"][k], torch.tensor(gold[k], dtype=torch.float64)) for k in ("n", "eps", "T", "Ux")}
-    print("C3 2000-step FP64 vs oracle", ferr, flush=True)
-    # the two paths' round-off accumulates over 2000 steps: 1.1e-12 measured (n), 2.6e-13 (T)
-    assert max(ferr.values()) < 1e-11
-    errs = {k: rel(prof["f32dev"][k], prof["f64"][k]) for k in ("n", "eps", "T", "Ux")}
-    print("C3 2000-step float deviations vs FP64", errs, flush=True)
-    # measured: n 1.5e-4, eps 1.8e-4, T 3.5e-5, U^x 2.5e-4 (max-normalised)
-    assert max(errs.values()) < 1e-3
+        ref = gold["profiles"][str(k)]
+        prof = {f: mac[f][0, 0] for f in ("n", "eps", "T")}
+        prof["Ux"] = mac["U"][1, 0, 0]
+        err = {f: rel(prof[f], torch.tensor(ref[f], dtype=torch.float64)) for f in ("n", "eps", "T", "Ux")}
+        print(f"C3 {storage} step {k} errors", err, flush=True)
+        assert max(err.values()) < C3_BOUNDS[storage](k), (k, err)
+    for f in ("n", "eps", "T"):
+        assert (mac[f] - mac[f][:1, :1, :]).abs().max().item() == 0.0, f
+    assert (mac["U"] - mac["U"][:, :1, :1, :]).abs().max().item() == 0.0
+    assert mac["U"][2:].abs().max().item() < (1e-12 if storage == "f64" else 1e-5)
 
 
 @pytest.mark.parametrize("zeta,kind", [(0.5, "product"), (1.0, "product"), (5.0, "product"),
@@ -287,13 +294,14 @@ def test_3d_equation_of_state_over_its_range(zeta, kind):
     ol = OL.Lattice(q, 0.9, (nx, ny, nz), bc=bc)
     tn, tT, tu = (torch.tensor(a) for a in (n, T, u))
     f0, fields0 = gl.init(tn, tT, tu, want_fields=True)
+    init_state = f0.clone()         # an even step count leaves its result in f0 itself
     res = gl.step(f0, gl.new_state(), 2)
     mom = gl.moments(res)
     gl.sync()
     fs = ol.collide(ol.init(tn, tT, tu))
     mac0 = ol.macro(ol.init(tn, tT, tu))
     assert rel(fields0["T"], mac0["T"]) < FP64_TOL and rel(fields0["n"], mac0["n"]) < FP64_TOL
-    assert rel(f0, fs) < FP64_TOL
+    assert rel(init_state, fs) < FP64_TOL
     for _ in range(2):
         fs = ol.collide(ol.stream(fs))
     ref = ol.macro(ol.stream(fs))

@@ -216,6 +216,9 @@ def test_create_validates_massive_lattices(rlbm_lib):
     cfg.extent[0], cfg.extent[1], cfg.extent[2] = 8, 8, 8
     cfg.force[0] = 1e-5
     assert rlbm_lib.rlbm_create(ctypes.byref(cfg), ctypes.byref(h)) == R.ERR_UNSUPPORTED
+    cfg.force[0] = 0.0
+    cfg.storage, cfg.n_ref = R.STORAGE["f32dev_f64"], 1.0   # double arithmetic on float storage: product rules
+    assert rlbm_lib.rlbm_create(ctypes.byref(cfg), ctypes.byref(h)) == R.ERR_UNSUPPORTED
     ur = R.Config()
     ur.model = R.Model(d=2, order=2, kind=R.KIND["ur_onlattice"], pad_=0, zeta=0.0)
     ur.extent[0], ur.extent[1], ur.extent[2] = 16, 4, 1     # |n_y| reaches 5
