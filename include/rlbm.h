@@ -244,6 +244,38 @@ rlbm_status rlbm_moments(rlbm_lattice *h, const void *f, const rlbm_fields *out,
 /* Drain the stream and report a deferred device error (clears the flag). */
 rlbm_status rlbm_sync(rlbm_lattice *h, hipStream_t stream);
 
+/* ------------------------------------------------ allocation-free stepping
+ *
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): rlbm_step
+ * without a handle.  The per-lattice tables that rlbm_create allocates (and a
+ * spare error flag) live instead in a static device array of
+ * RLBM_STATIC_SCRATCH_BYTES on each GPU the library runs on, held until the
+ * process ends; every configuration's tables fit it (the size is checked when
+ * the library is built).  No hipMalloc, hipFree or other allocating device
+ * call is made.
+ *
+ * cfg is validated as by rlbm_create (same errors).  The first call on a GPU,
+ * and each call whose configuration differs from the previous call's on that
+ * GPU (tau_field aside), builds the tables on the host, copies them into the
+ * array on `stream` and waits for that copy; later calls with the same
+ * configuration only launch the steps.  The steps are those of rlbm_step
+ * (same kernels, default launch shape and store kind, so the same results),
+ * launched one by one on `stream` (no graph).  f_a, f_b, nsteps and last are
+ * as for rlbm_step; the caller owns every buffer.
+ *
+ * flag (device int32, or NULL): set to 1 by a kernel that meets a
+ * non-physical state; the caller clears and reads it.  NULL: the flag is
+ * written to the array and not reported.
+ *
+ * All calls on one GPU share its array, which keeps the last call's tables:
+ * calls that overlap on one GPU (several host threads, or several streams whose
+ * work overlaps) with different configurations race.  Host threads are
+ * serialised by a lock; the device work of calls on different streams is not. */
+#define RLBM_STATIC_SCRATCH_BYTES (128 * 1024)
+rlbm_status rlbm_step_static(const rlbm_config *cfg, void *f_a, void *f_b, int32_t nsteps,
+                             const rlbm_fields *last, int32_t *flag, hipStream_t stream);
+
 /* ------------------------------------------------------------ reverse mode
  *
  * Hand-written adjoint of the update (not part of the paper; it lets tau or

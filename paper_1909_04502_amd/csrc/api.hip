@@ -3,6 +3,7 @@
 
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -900,6 +901,100 @@ rlbm_status rlbm_autotune(rlbm_lattice *h, int32_t steps, float *ms_out, hipStre
   if (st != RLBM_OK) return st;
   if (he != hipSuccess) return fail(RLBM_ERR_DEVICE, hipGetErrorString(he));
   return rlbm_sync(h, stream);
+}
+
+// ---------------------------------------------------------------------------
+// Allocation-free step: the tables of the last configuration stepped on a GPU, and a spare error
+// flag, live in a file-scope device array (one copy per GPU, kept until the process ends).
+// ---------------------------------------------------------------------------
+}  // extern "C"
+
+namespace {
+
+constexpr size_t kStaticTablesBytes = (sizeof(rlbm::Tables) + 255) & ~size_t(255);
+constexpr size_t kStaticFlagOffset = kStaticTablesBytes;
+static_assert(kStaticTablesBytes + 256 <= RLBM_STATIC_SCRATCH_BYTES,
+              "the tables of one lattice and the error flag must fit the static scratch array");
+
+// Host-side state per device: the device address of its scratch array and the configuration whose
+// tables the array holds.
+constexpr int kStaticMaxDevices = 64;
+struct StaticSlot {
+  void *scratch = nullptr;
+  rlbm_lattice *lat = nullptr;   // description of the resident configuration (host)
+};
+StaticSlot g_static[kStaticMaxDevices];
+std::mutex g_static_mu;
+
+// Two configurations give the same tables and launch shape (the tau field pointer aside).
+bool same_tables(const rlbm_config &a, const rlbm_config &b) {
+  if (a.model.d != b.model.d || a.model.order != b.model.order || a.model.kind != b.model.kind ||
+      a.model.zeta != b.model.zeta || a.model.v0 != b.model.v0 || a.storage != b.storage || a.tau != b.tau ||
+      a.n_ref != b.n_ref || a.tau_T != b.tau_T)
+    return false;
+  for (int k = 0; k < 3; ++k) {
+    if (a.extent[k] != b.extent[k] || a.bc[k] != b.bc[k] || a.force[k] != b.force[k]) return false;
+    if (a.wall_T[k][0] != b.wall_T[k][0] || a.wall_T[k][1] != b.wall_T[k][1]) return false;
+  }
+  return true;
+}
+
+}  // namespace
+
+static __device__ __align__(256) unsigned char scratch[RLBM_STATIC_SCRATCH_BYTES];
+
+extern "C" {
+
+rlbm_status rlbm_step_static(const rlbm_config *cfg, void *f_a, void *f_b, int32_t nsteps, const rlbm_fields *last,
+                             int32_t *flag, hipStream_t stream) {
+  if (!cfg || !f_a || !f_b || nsteps < 0) return fail(RLBM_ERR_INVALID_ARG, "bad argument");
+  int dev = -1;
+  hipError_t he = hipGetDevice(&dev);
+  if (he != hipSuccess) return fail(RLBM_ERR_DEVICE, hipGetErrorString(he));
+  if (dev < 0 || dev >= kStaticMaxDevices) return fail(RLBM_ERR_UNSUPPORTED, "device index beyond the static slots");
+  std::lock_guard<std::mutex> lock(g_static_mu);
+  StaticSlot &slot = g_static[dev];
+  if (!slot.scratch) {
+    // once per device, with the device current: the array's address on this GPU
+    void *ptr = nullptr;
+    he = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (he != hipSuccess || !ptr) return fail(RLBM_ERR_DEVICE, he != hipSuccess ? hipGetErrorString(he) : "no scratch address");
+    slot.scratch = ptr;
+  }
+  if (!slot.lat || !same_tables(slot.lat->cfg, *cfg)) {
+    // a new configuration: build its tables on the host and copy them into the array (the copy is
+    // ordered after earlier work on this stream, and waited for before the host copy is freed)
+    rlbm_lattice *h = new (std::nothrow) rlbm_lattice();
+    rlbm::Tables *t = new (std::nothrow) rlbm::Tables;
+    rlbm_status st = (h && t) ? prepare_lattice(cfg, h, t) : fail(RLBM_ERR_DEVICE, "out of host memory");
+    if (st == RLBM_OK) {
+      he = hipMemcpyAsync(slot.scratch, t, sizeof(rlbm::Tables), hipMemcpyHostToDevice, stream);
+      if (he == hipSuccess) he = hipStreamSynchronize(stream);
+      if (he != hipSuccess) st = fail(RLBM_ERR_DEVICE, hipGetErrorString(he));
+    }
+    delete t;
+    if (st != RLBM_OK) {
+      delete h;
+      if (he != hipSuccess) {
+        // the array's contents are unknown now
+        delete slot.lat;
+        slot.lat = nullptr;
+      }
+      return st;
+    }
+    delete slot.lat;
+    slot.lat = h;
+  }
+  rlbm_lattice *h = slot.lat;
+  h->cfg.tau_field = cfg->tau_field;
+  const int64_t bytes = (int64_t)(h->cfg.storage == RLBM_F64 ? 8 : 4) * h->quad.Q * h->sites;
+  const char *pa = (const char *)f_a, *pb = (const char *)f_b;
+  if (pa < pb + bytes && pb < pa + bytes) return fail(RLBM_ERR_INVALID_ARG, "f_a and f_b overlap");
+  rlbm::LaunchArgs a = base_args(h, stream);
+  a.tb = (const rlbm::Tables *)slot.scratch;
+  a.err = flag ? (int *)flag : (int *)((char *)slot.scratch + kStaticFlagOffset);
+  he = launch_steps(a, f_a, f_b, nsteps, last);
+  return he == hipSuccess ? RLBM_OK : fail(RLBM_ERR_DEVICE, hipGetErrorString(he));
 }
 
 }  // extern "C"

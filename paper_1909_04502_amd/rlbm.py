@@ -93,6 +93,9 @@ def lib():
                             POINTER(Fields), c_void_p]
     L.rlbm_step.restype = st
     L.rlbm_step.argtypes = [c_void_p, c_void_p, c_void_p, c_int32, POINTER(Fields), c_void_p]
+    L.rlbm_step_static.restype = st
+    L.rlbm_step_static.argtypes = [POINTER(Config), c_void_p, c_void_p, c_int32, POINTER(Fields), c_void_p,
+                                   c_void_p]
     L.rlbm_moments.restype = st
     L.rlbm_moments.argtypes = [c_void_p, c_void_p, POINTER(Fields), c_void_p]
     L.rlbm_sync.restype = st
@@ -308,6 +311,15 @@ class Lattice:
                                ctypes.byref(fs) if fs is not None else None, _stream()))
         res = f_b if nsteps % 2 == 1 else f_a
         return (res, fd) if want_last else res
+
+    def step_static(self, f_a, f_b, nsteps, flag=None):
+        """rlbm_step_static on this lattice's configuration (no handle, no device allocation);
+        flag: optional device int32 tensor set to 1 on a non-physical state.  Returns the buffer
+        holding the result."""
+        assert f_a.dtype == self.dtype and f_b.dtype == self.dtype
+        _check(lib().rlbm_step_static(ctypes.byref(self.cfg), _ptr(f_a), _ptr(f_b), int(nsteps), None, _ptr(flag),
+                                      _stream()))
+        return f_b if nsteps % 2 == 1 else f_a
 
     def moments(self, f):
         """Macroscopic fields of the streamed populations of state f."""

@@ -74,6 +74,8 @@ def test_create_validates_before_touching_the_device(rlbm_lib):
     assert rlbm_lib.rlbm_create(ctypes.byref(cfg), ctypes.byref(h)) == R.ERR_INVALID_ARG
     cfg.tau_T = 0.0
     assert rlbm_lib.rlbm_step(None, None, None, 1, None, None) == R.ERR_INVALID_ARG
+    assert rlbm_lib.rlbm_step_static(None, None, None, 1, None, None, None) == R.ERR_INVALID_ARG
+    assert rlbm_lib.rlbm_step_static(ctypes.byref(cfg), None, None, 1, None, None, None) == R.ERR_INVALID_ARG
 
 
 def test_create_rejects_sizes_beyond_the_limits(rlbm_lib):
