@@ -533,9 +533,9 @@ static hipError_t batch_build_tiles(rlbm_batch *b) {
   const int bx = rlbm::kBatchTiles[tv][0], by = rlbm::kBatchTiles[tv][1];
   std::vector<int2> tl;
   for (size_t l = 0; l < b->lats.size(); ++l) {
-    const int nx = (int)b->lats[l]->cfg.extent[0], ny = (int)b->lats[l]->cfg.extent[1];
-    const int n = ((nx + bx - 1) / bx) * ((ny + by - 1) / by);
-    for (int t = 0; t < n; ++t) tl.push_back(make_int2((int)l, t));
+    const int64_t nx = b->lats[l]->cfg.extent[0], ny = b->lats[l]->cfg.extent[1];
+    const int64_t n = tv == rlbm::kBatchLinearTile ? (nx * ny + bx - 1) / bx : ((nx + bx - 1) / bx) * ((ny + by - 1) / by);
+    for (int64_t t = 0; t < n; ++t) tl.push_back(make_int2((int)l, (int)t));
   }
   // the cached graph's kernel arguments name the old tile list: drop it before that list is freed
   if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
@@ -579,6 +579,10 @@ rlbm_status rlbm_batch_create(const rlbm_config *cfgs, int32_t nlat, rlbm_batch 
   b->order = cfgs[0].model.order;
   b->storage = cfgs[0].storage;
   b->elem = b->storage == RLBM_F64 ? 8 : 4;
+  // default launch: runs of 256 consecutive sites (no lane idles past a row's end: 5-6 % faster
+  // than 64 x 4 tiles on 256 lattices of sides 64..512), the 2048-block grid in double and the
+  // 512-block grid in float
+  b->variant = b->storage == RLBM_F64 ? 2 * 4 + rlbm::kBatchLinearTile : rlbm::kBatchLinearTile;
   for (int l = 0; l < nlat; ++l) {
     rlbm_lattice *h = nullptr;
     rlbm_status st = rlbm_create(&cfgs[l], &h);

@@ -2,7 +2,8 @@
 //
 // Every lattice keeps its own constant tables (zeta, tau, quadrature) and its
 // own SoA population block inside one flat state buffer.  The work is a list
-// of tiles (lattice, tile index); a fixed grid of workgroups walks it, each
+// of tiles (lattice, tile index: a 2D tile of sites, or a run of 256 consecutive
+// sites); a fixed grid of workgroups walks it, each
 // XCD taking a contiguous range of tiles so that neighbouring tiles of a
 // lattice share that XCD's L2.  All lattices of a batch use the same stencil,
 // order and storage (one kernel instantiation).
@@ -24,6 +25,8 @@ __global__ void __launch_bounds__(BX * BY) k_step_batch(const Tables *__restrict
                                                         const int64_t *__restrict__ elem_off,
                                                         const int2 *__restrict__ tiles, int ntiles,
                                                         const S *__restrict__ fin, S *__restrict__ fout, int *err) {
+  // a one-row block of 256 takes 256 consecutive sites (tile shape kBatchLinearTile)
+  constexpr bool LINEAR = BX == 256 && BY == 1;
   // XCD k (blocks with blockIdx.x % 8 == k) walks tiles [k*chunk, (k+1)*chunk)
   const int per_xcd = gridDim.x / 8;
   const int k = blockIdx.x % 8, b = blockIdx.x / 8;
@@ -33,12 +36,22 @@ __global__ void __launch_bounds__(BX * BY) k_step_batch(const Tables *__restrict
     const int2 d = tiles[t];
     const Tables *__restrict__ tb = tabs + d.x;
     const int nx = tb->nx, ny = tb->ny;
-    const int gx = (nx + BX - 1) / BX;
-    const int x = (d.y % gx) * BX + threadIdx.x;
-    const int y = (d.y / gx) * BY + threadIdx.y;
-    if (x >= nx || y >= ny) continue;
     const int64_t sites = tb->sites;
-    const int64_t site = (int64_t)y * nx + x;
+    int x, y;
+    int64_t site;
+    if constexpr (LINEAR) {
+      // 256 consecutive sites in row-major order
+      site = (int64_t)d.y * BX + threadIdx.x;
+      if (site >= sites) continue;
+      y = (int)(site / nx);
+      x = (int)(site - (int64_t)y * nx);
+    } else {
+      const int gx = (nx + BX - 1) / BX;
+      x = (d.y % gx) * BX + threadIdx.x;
+      y = (d.y / gx) * BY + threadIdx.y;
+      if (x >= nx || y >= ny) continue;
+      site = (int64_t)y * nx + x;
+    }
     const S *fi = fin + elem_off[d.x];
     S *fo = fout + elem_off[d.x];
     Offs o;

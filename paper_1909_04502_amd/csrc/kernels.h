@@ -70,8 +70,10 @@ struct AdjointArgs {
 // reverse-mode kernels (2D product rules, periodic boundaries)
 hipError_t launch_adjoint(const AdjointArgs &a);
 
-// Batched step: tile shapes (0: 64x4, 1: 64x2, 2: 128x2, 3: 32x8) and grid sizes
+// Batched step: tile shapes (0: 64 x 4, 1: 64 x 2, 2: 128 x 2 sites; 3: 256 consecutive sites of
+// a lattice, its rows joined end to end, so that no lane idles past a row's end) and grid sizes
 constexpr int kBatchTiles[4][2] = {{64, 4}, {64, 2}, {128, 2}, {256, 1}};
+constexpr int kBatchLinearTile = 3;
 struct BatchArgs {
   int stencil = 0, order = 0, storage = 0;
   int tile = 0;                  // index into kBatchTiles

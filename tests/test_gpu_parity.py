@@ -130,13 +130,7 @@ def c2_golden():
     make_c2_samples.py): {"L", "ys", "xs", "samples": {step: {n, eps, T, U}}}."""
     import json
     import os
-    path = os.path.join(os.path.dirname(__file__), "golden", "c2_samples.json")
-    if os.path.exists(path):
-        return json.load(open(path))
-    # the 1000-step samples alone (same sites, same script before it kept the earlier checkpoints)
-    g = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "c2_1000_samples.json")))
-    return {"L": g["L"], "ys": g["ys"], "xs": g["xs"],
-            "samples": {str(g["steps"]): {k: g[k] for k in ("n", "eps", "T", "U")}}}
+    return json.load(open(os.path.join(os.path.dirname(__file__), "golden", "c2_samples.json")))
 
 
 # error bounds per checkpoint k (max-normalised, per field).  Double: the two paths' round-off.
