@@ -218,11 +218,12 @@ static rlbm_status prepare_lattice(const rlbm_config *cfg, rlbm_lattice *h, rlbm
   h->cfg = *cfg;
   h->stencil = stencil_of(m);
   // default launch shapes (from sweeps of every variant on MI355X):
-  //  * 3D product rules: float deviations keep ~100 populations in registers at occupancy 2,
-  //    64 x 4 tiles in (y, z) patches per XCD (as fast as the untiled order, and half the
-  //    re-reads from beyond the L2: 1.19x the algorithmic bytes instead of 2.35x); in double
-  //    (storage or arithmetic) the occupancy-2 build spills to scratch, so the unconstrained
-  //    build (468 registers, one wave per SIMD) in untiled 64 x 4 is 1.6x faster;
+  //  * 3D product rules: 64 x 4 tiles in (y, z) patches per XCD (half the re-reads from beyond
+  //    the L2 of the untiled order: 1.19x the algorithmic bytes instead of 2.35x) with the
+  //    unconstrained build, in float storage (4.39 ms at 256^3 in float arithmetic, 4.56 with
+  //    the occupancy-2 build; 6.67 ms in double arithmetic, whose occupancy-2 build spills); in
+  //    double storage the unconstrained build (468 registers, one wave per SIMD) in untiled
+  //    64 x 4 tiles (10.5 ms, 10.7 in patches);
   //  * the 3D massive rule: 64 x 2 XCD-ordered tiles (double, streaming kernel) or 64 x 1 patches
   //    (float);
   //  * 2D product rules in double: rows of 64 sites; float storage with double arithmetic:
@@ -234,7 +235,7 @@ static rlbm_status prepare_lattice(const rlbm_config *cfg, rlbm_lattice *h, rlbm
   //    so that four times as many blocks spread over the CUs (about 9 % faster at 64 x 64)
   if (m.d == 3 && m.kind == RLBM_QUAD_MASSIVE_ONLATTICE) h->variant = cfg->storage == RLBM_F64 ? 4 : 8;
   else if (m.d == 3 && m.kind == RLBM_QUAD_UR_ONLATTICE) h->variant = 4;   // streaming kernel, as the 3D massive rule
-  else if (m.d == 3) h->variant = cfg->storage == RLBM_F32_DEV ? 3 : 0;
+  else if (m.d == 3) h->variant = cfg->storage == RLBM_F64 ? 0 : 11;
   else if (m.kind == RLBM_QUAD_PRODUCT && cfg->storage == RLBM_F64) h->variant = 5;
   else if (m.kind == RLBM_QUAD_PRODUCT && cfg->storage == RLBM_F32_DEV_F64) h->variant = 9;
   else if (m.kind == RLBM_QUAD_MASSIVE_ONLATTICE && (m.order == 2 || cfg->storage != RLBM_F64)) h->variant = 10;

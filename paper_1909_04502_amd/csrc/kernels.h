@@ -21,11 +21,11 @@ struct FieldPtrs {
 struct Variant {
   int bx, by, bz, occ, xcd;
 };
-constexpr int kNumVariants = 11;
+constexpr int kNumVariants = 12;
 constexpr Variant kVariants[kNumVariants] = {
     {64, 4, 1, 0, 0}, {64, 4, 1, 0, 1}, {64, 4, 1, 2, 0}, {64, 4, 1, 2, 2}, {64, 2, 1, 0, 1},
     {64, 1, 1, 0, 1}, {128, 2, 1, 0, 1}, {256, 1, 1, 0, 1}, {64, 1, 1, 2, 2}, {64, 2, 2, 2, 2},
-    {64, 4, 1, 4, 1}};
+    {64, 4, 1, 4, 1}, {64, 4, 1, 0, 2}};
 
 struct LaunchArgs {
   int op = 0;
