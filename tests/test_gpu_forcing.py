@@ -35,6 +35,8 @@ CASES = {
     "f2_walls": (2, 2.5, 3, (19, 12), ("wall", "periodic"), 1.1, (0.0, 3e-4), "f64"),
     "f2_walls_n2": (2, 0.5, 2, (16, 9), ("periodic", "wall"), 0.9, (1e-4, 0.0), "f64"),
     "f2_f32dev": (2, 1.0, 3, (40, 24), ("wall", "periodic"), 0.8, (0.0, 2e-4), "f32dev"),
+    "f2_f32dev_f64": (2, 1.0, 3, (40, 24), ("wall", "periodic"), 0.8, (0.0, 2e-4), "f32dev_f64"),
+    "f3_f32dev_f64": (3, 1.0, 3, (9, 7, 6), ("wall", "periodic", "periodic"), 0.7, (0.0, 2e-4, 1e-4), "f32dev_f64"),
     "f3_walls": (3, 1.0, 3, (9, 7, 6), ("wall", "periodic", "periodic"), 0.7, (0.0, 2e-4, 1e-4), "f64"),
     # the massive on-lattice rules (Sec. 5.3) with the force: the set-up of the forcing validation
     "m2_walls": (2, 5.0, 3, (19, 8), ("wall", "periodic"), 0.9, (0.0, 3e-4), "f64", "massive_onlattice"),

@@ -108,10 +108,12 @@ def test_step_parity_3d(name):
     assert rel(mom["U"], nxt["U"]) < FP64_TOL
 
 
+@pytest.mark.parametrize("storage", ["f32dev", "f32dev_f64"])
 @pytest.mark.parametrize("name", ["r3_open", "s3_periodic"])
-def test_f32_deviation_storage_3d(name):
-    print(f"[case] f32dev3d {name}", flush=True)
-    gl, ol, (n, T, u, xi, amp) = setup(name, storage="f32dev")
+def test_f32_deviation_storage_3d(name, storage):
+    """Float deviations (updated in float, or in double) against the FP64 oracle after 20 steps."""
+    print(f"[case] {storage} 3d {name}", flush=True)
+    gl, ol, (n, T, u, xi, amp) = setup(name, storage=storage)
     nsteps = 20
     fa = gl.init(n, T, u, xi, amp)
     res = gl.step(fa, gl.new_state(), nsteps)
@@ -123,7 +125,7 @@ def test_f32_deviation_storage_3d(name):
     ref = ol.macro(ol.stream(fs))
     errs = {k: rel(mom[k], ref[k]) for k in ("n", "eps", "T")}
     errs["U"] = rel(mom["U"], ref["U"])
-    print("f32dev 3d errors", errs, flush=True)
+    print(f"{storage} 3d errors", errs, flush=True)
     assert max(errs.values()) < F32_TOL
 
 

@@ -33,6 +33,8 @@ CASES = {
     "prod2d_f32dev": (2, 1.0, 3, "product", (96, 70), ("periodic", "periodic"), "f32dev", None),
     "prod2d_force_walls": (2, 2.5, 3, "product", (19, 12), ("wall", "periodic"), "f64", (0.0, 3e-4)),
     "prod3d_f32dev": (3, 1.0, 3, "product", (13, 9, 7), ("periodic",) * 3, "f32dev", None),
+    "prod2d_f32dev_f64": (2, 1.0, 3, "product", (96, 70), ("wall", "periodic"), "f32dev_f64", (0.0, 3e-4)),
+    "prod3d_f32dev_f64": (3, 1.0, 3, "product", (13, 9, 7), ("periodic",) * 3, "f32dev_f64", None),
     "ur_order3": (2, 0.0, 3, "ur_onlattice", (37, 11), ("periodic", "periodic"), "f64", None),
     "massive2d_n3": (2, 5.0, 3, "massive_onlattice", (41, 12), ("open", "periodic"), "f64", None),
     "massive3d_f64": (3, 5.0, 3, "massive_onlattice", (9, 7, 6), ("periodic",) * 3, "f64", None),
