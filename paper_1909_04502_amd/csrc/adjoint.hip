@@ -81,6 +81,130 @@ __global__ void __launch_bounds__(256) k_adjoint(const Tables *__restrict__ tb, 
   if (dtau != nullptr) dtau[site] += taub;
 }
 
+// The same reverse step for float storage and arithmetic, in three passes over the shells that each
+// pull what they need again (cache hits: the taps were read just before), so that one shell's
+// populations are live at a time instead of all Q twice over: the moments of F_t; the reverse of the
+// relaxation and of the equilibrium (F_t and S^T lam_{t+1}); and lam_t = mu (1 - Omega) + the terms
+// through n, T and U, stored shell by shell.  That fits two waves per SIMD.
+template <class ST, int N, typename S, bool DEV>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8)))
+k_adjoint_streamed(const Tables *__restrict__ tb, const S *__restrict__ Bprev, const S *__restrict__ lam_next,
+                   S *__restrict__ lam, const void *__restrict__ tau_field, double *__restrict__ dtau, int *err) {
+  constexpr int D = ST::D, ND = ST::NDIR, NPD = ND / 2, KR = ST::NSHELL;
+  using B = BasisDef<D, N>;
+  using A = S;
+  int x, y, z;
+  if (!site_xyz(tb, x, y, z)) return;
+  const int64_t sites = tb->sites;
+  const int64_t site = ((int64_t)z * tb->ny + y) * tb->nx + x;
+  const Offs o = offs_periodic<ST, S>(tb, x, y, z);
+  // ---- forward recomputation: moments, Landau frame, n, T, equilibrium coefficients ----
+  MomAcc<D> acc;
+#pragma unroll
+  for (int j = 0; j < KR; ++j) {
+    A fs[ND];
+    pull_shell<ST, S, false, A>(tb, Bprev, sites, o, j, fs);
+    moments_shell<ST, A, ND>(tb, j, fs, 0, acc);
+  }
+  double Nv[D + 1], T[D + 1][D + 1];
+  moments_finish<ST, DEV>(tb, acc, Nv, T);
+  Macro<D> mac;
+  mac.ok = landau_frame<D, 3>(T, mac.eps, mac.U);
+  mac.n = lorentz_dot<D>(mac.U, Nv);
+  const double m = tb->m;
+  mac.ok = temperature_2d(mac.eps / mac.n, m, mac.T) && mac.ok;
+  mac.ok = mac.ok && mac.n > 0.0 && mac.eps > 0.0;
+  if (!mac.ok) set_err(err);
+  const RatiosD rd = ratios_2d_d(m / mac.T);
+  double ap[B::NM];
+  {
+    Ratios rr;
+    rr.r0 = rd.r0;
+    rr.r2 = rd.r2;
+    rr.r3 = rd.r3;
+    double Md[B::NM];
+    basis_moments<D, N>(mac.n, mac.T, mac.U, rr, Md);
+    feq_coefficients<D, N, DEV>(tb, Md, ap);
+  }
+  const double itau = 1.0 / tau_at<S>(tb, tau_field, site);
+  const double a0 = mac.U[0] * itau;
+  double nU[NPD];
+#pragma unroll
+  for (int q = 0; q < NPD; ++q) {
+    double c0 = 0.0;
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+      const double c = nhat<ST>(2 * q, a);
+      if (c != 0.0) c0 += c * mac.U[a + 1];
+    }
+    nU[q] = c0 * itau;
+  }
+  // ---- reverse of the relaxation and of the equilibrium evaluation ----
+  // (the base pointers pass through an empty asm on a forward result: the pulls are issued again
+  // here rather than their values kept live from the pass above)
+  const S *fb = Bprev, *lb = lam_next;
+  asm volatile("" : "+s"(fb), "+s"(lb) : "v"(ap[0]));
+  double a0b = 0.0, nUb[NPD], apb[B::NM];
+#pragma unroll
+  for (int q = 0; q < NPD; ++q) nUb[q] = 0.0;
+#pragma unroll
+  for (int k = 0; k < B::NM; ++k) apb[k] = 0.0;
+#pragma unroll
+  for (int j = 0; j < KR; ++j) {
+    A fs[ND], ms[ND];
+    pull_shell<ST, S, false, A>(tb, fb, sites, o, j, fs);
+    pull_shell<ST, S, true, A>(tb, lb, sites, o, j, ms);
+    relax_vjp_shell<ST, N, A>(tb, j, fs, ms, ap, a0, nU, a0b, nUb, apb);
+  }
+  // Omega depends on tau through a0 = U^0 / tau and nU = (n . U) / tau
+  double Ub[D + 1];
+  Ub[0] = a0b * itau;
+  double taub = -a0b * a0;
+#pragma unroll
+  for (int a = 1; a <= D; ++a) Ub[a] = 0.0;
+#pragma unroll
+  for (int q = 0; q < NPD; ++q) {
+    taub -= nUb[q] * nU[q];
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+      const double c = nhat<ST>(2 * q, a);
+      if (c != 0.0) Ub[a + 1] += c * nUb[q] * itau;
+    }
+  }
+  taub *= itau;
+  // ---- reverse of the equilibrium coefficients, EOS, density and Landau frame ----
+  double Mb[B::NM];
+  coefficients_vjp<D, N>(tb, apb, Mb);
+  double nb = 0.0, Tb = 0.0;
+  basis_moments_vjp<D, N>(mac.n, mac.T, mac.U, m, rd, Mb, nb, Tb, Ub);
+  double Nb[D + 1], Tbar[D + 1][D + 1], Ts[D + 1][D + 1];
+  macro_vjp_moments<D>(tb, Nv, T, mac, nb, 0.0, Tb, Ub, Nb, Tbar);
+#pragma unroll
+  for (int a = 0; a <= D; ++a)
+#pragma unroll
+    for (int b = 0; b <= D; ++b) Ts[a][b] = 0.5 * (Tbar[a][b] + Tbar[b][a]);
+  // ---- lam_t = mu (1 - Omega) + dL/dN^a p^a + dL/dT^ab p^a p^b, shell by shell ----
+  const S *lb2 = lam_next;
+  asm volatile("" : "+s"(lb2) : "v"(Nb[0]));
+  const uint32_t so = (uint32_t)site * (uint32_t)sizeof(S);
+#pragma unroll
+  for (int j = 0; j < KR; ++j) {
+    A ms[ND], out[ND];
+    pull_shell<ST, S, true, A>(tb, lb2, sites, o, j, ms);
+    const double v = tb->sv[j];
+#pragma unroll
+    for (int qp = 0; qp < NPD; ++qp) {
+      const double b = v * nU[qp];
+      out[2 * qp] = (A)((double)ms[2 * qp] * (1.0 - (a0 - b)));
+      out[2 * qp + 1] = (A)((double)ms[2 * qp + 1] * (1.0 - (a0 + b)));
+    }
+    moments_vjp_shell<ST, A, ND>(tb, j, Nb, Ts, out, 0);
+#pragma unroll
+    for (int k = 0; k < ND; ++k) *(S *)((char *)(lam + (int64_t)(j * ND + k) * sites) + so) = (S)out[k];
+  }
+  if (dtau != nullptr) dtau[site] += taub;
+}
+
 // lam_{T+1}(x) = J_macro(F(x))^T g(x), F = S(B); g = (dL/dn, dL/deps, dL/dT, dL/dU)
 template <class ST, int N, typename S, bool DEV, typename A = S>
 __global__ void __launch_bounds__(256) k_moments_vjp(const Tables *__restrict__ tb, const S *__restrict__ B,
@@ -190,8 +314,15 @@ static hipError_t launch_adj_t(const AdjointArgs &a) {
   dim3 grid((unsigned)nb, 1, 1);
   switch (a.op) {
     case ADJ_STEP:
-      hipLaunchKernelGGL((k_adjoint<ST, N, S, DEV, A>), grid, block, 0, a.stream, a.tb, (const S *)a.state,
-                         (const S *)a.lam_in, (S *)a.lam_out, a.tau_field, a.dtau, a.err);
+      // float storage and arithmetic: the streamed kernel (two waves per SIMD); double storage or
+      // arithmetic: the register-resident one (re-pulled doubles miss the L1 and the streamed form
+      // is slower there)
+      if constexpr (sizeof(S) == 4 && sizeof(A) == 4)
+        hipLaunchKernelGGL((k_adjoint_streamed<ST, N, S, DEV>), grid, block, 0, a.stream, a.tb, (const S *)a.state,
+                           (const S *)a.lam_in, (S *)a.lam_out, a.tau_field, a.dtau, a.err);
+      else
+        hipLaunchKernelGGL((k_adjoint<ST, N, S, DEV, A>), grid, block, 0, a.stream, a.tb, (const S *)a.state,
+                           (const S *)a.lam_in, (S *)a.lam_out, a.tau_field, a.dtau, a.err);
       break;
     case ADJ_MOMENTS:
       hipLaunchKernelGGL((k_moments_vjp<ST, N, S, DEV, A>), grid, block, 0, a.stream, a.tb, (const S *)a.state,

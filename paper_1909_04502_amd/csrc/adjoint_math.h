@@ -145,6 +145,38 @@ __device__ __forceinline__ double eos_slope_2d(double T, double m, const RatiosD
   return r.r2 - 1.0 - z * r.d2;
 }
 
+// Reverse of feq_coefficients (the deviation shift by M^ref has no derivative): given
+// apb = dL/da', sets Mb = dL/dM (unshifted basis moments).
+template <int D, int N>
+__device__ __forceinline__ void coefficients_vjp(const Tables *__restrict__ tb, const double (&apb)[BasisDef<D, N>::NM],
+                                                 double (&Mb)[BasisDef<D, N>::NM]) {
+  using B = BasisDef<D, N>;
+  constexpr AngTable<D, N> AT{};
+  // a' = Linv^T a  ->  abar = Linv a'bar ;  a = Linv M'  ->  M'bar = Linv^T abar
+  double ab[B::NM];
+#pragma unroll
+  for (int r = 0; r < B::NM; ++r) {
+    double acc = 0.0;
+#pragma unroll
+    for (int c = 0; c <= r; ++c)
+      if (AT.cls[r] == AT.cls[c]) acc += tb->Linv[r][c] * apb[c];
+    ab[r] = acc;
+  }
+#pragma unroll
+  for (int c = 0; c < B::NM; ++c) {
+    double acc = 0.0;
+#pragma unroll
+    for (int r = c; r < B::NM; ++r)
+      if (AT.cls[r] == AT.cls[c]) acc += tb->Linv[r][c] * ab[r];
+    Mb[c] = acc;
+  }
+  // M'_(1,e) = M_(1,e) - m M_(0,e)
+  const double m = tb->m;
+#pragma unroll
+  for (int q = 0; q < AT.n; ++q)
+    if (AT.m1[q] >= 0) Mb[AT.m0[q]] -= m * Mb[AT.m1[q]];
+}
+
 // Transposed product-rule equilibrium evaluation: given g_i = dL/df^eq_i,
 // accumulate dL/dM (unshifted basis moments).
 template <class ST, int N, typename A>
@@ -181,37 +213,14 @@ __device__ __forceinline__ void feq_vjp(const Tables *__restrict__ tb, const A (
       if (AT.m1[q] >= 0) apb[AT.m1[q]] += ceb[q] * tb->sfeq[j][1][l];
     }
   }
-  // a' = Linv^T a  ->  abar = Linv a'bar ;  a = Linv M'  ->  M'bar = Linv^T abar
-  double ab[B::NM];
-#pragma unroll
-  for (int r = 0; r < B::NM; ++r) {
-    double acc = 0.0;
-#pragma unroll
-    for (int c = 0; c <= r; ++c)
-      if (AT.cls[r] == AT.cls[c]) acc += tb->Linv[r][c] * apb[c];
-    ab[r] = acc;
-  }
-#pragma unroll
-  for (int c = 0; c < B::NM; ++c) {
-    double acc = 0.0;
-#pragma unroll
-    for (int r = c; r < B::NM; ++r)
-      if (AT.cls[r] == AT.cls[c]) acc += tb->Linv[r][c] * ab[r];
-    Mb[c] = acc;
-  }
-  // M'_(1,e) = M_(1,e) - m M_(0,e)
-  const double m = tb->m;
-#pragma unroll
-  for (int q = 0; q < AT.n; ++q)
-    if (AT.m1[q] >= 0) Mb[AT.m0[q]] -= m * Mb[AT.m1[q]];
+  coefficients_vjp<D, N>(tb, apb, Mb);
 }
 
-// Forward equilibrium of the product rule from basis moments (deviation form
-// for DEV): used by the initial condition.
-template <class ST, int N, typename A, bool DEV>
-__device__ __forceinline__ void feq_prod(const Tables *__restrict__ tb, double (&Md)[BasisDef<ST::D, N>::NM],
-                                         A (&feq)[ST::Q]) {
-  constexpr int D = ST::D, ND = ST::NDIR, NPD = ND / 2, KR = ST::NSHELL;
+// Coefficients a' = Linv^T Linv M' of the projected equilibrium over the shifted monomials
+// (Sec. 5.2), from the basis moments Md (deviation form for DEV: Md becomes M - M^ref).
+template <int D, int N, bool DEV>
+__device__ __forceinline__ void feq_coefficients(const Tables *__restrict__ tb, double (&Md)[BasisDef<D, N>::NM],
+                                                 double (&ap)[BasisDef<D, N>::NM]) {
   using B = BasisDef<D, N>;
   constexpr AngTable<D, N> AT{};
   if constexpr (DEV) {
@@ -231,7 +240,6 @@ __device__ __forceinline__ void feq_prod(const Tables *__restrict__ tb, double (
       if (AT.cls[r] == AT.cls[c]) acc += tb->Linv[r][c] * Md[c];
     ak[r] = acc;
   }
-  double ap[B::NM];
 #pragma unroll
   for (int c = 0; c < B::NM; ++c) {
     double acc = 0.0;
@@ -240,17 +248,38 @@ __device__ __forceinline__ void feq_prod(const Tables *__restrict__ tb, double (
       if (AT.cls[r] == AT.cls[c]) acc += tb->Linv[r][c] * ak[r];
     ap[c] = acc;
   }
+}
+
+// Angular coefficients of shell j: ce[q] multiplies the direction monomial n^e(q) in the
+// equilibrium of that shell's populations.
+template <int D, int N>
+__device__ __forceinline__ void shell_coefficients(const Tables *__restrict__ tb, int j,
+                                                   const double (&ap)[BasisDef<D, N>::NM], double (&ce)[20]) {
+  constexpr AngTable<D, N> AT{};
+#pragma unroll
+  for (int q = 0; q < AT.n; ++q) {
+    const int l = AT.e[q][0] + AT.e[q][1] + AT.e[q][2];
+    double acc = 0.0;
+    if (AT.m0[q] >= 0) acc += ap[AT.m0[q]] * tb->sfeq[j][0][l];
+    if (AT.m1[q] >= 0) acc += ap[AT.m1[q]] * tb->sfeq[j][1][l];
+    ce[q] = acc;
+  }
+}
+
+// Forward equilibrium of the product rule from basis moments (deviation form
+// for DEV): used by the initial condition.
+template <class ST, int N, typename A, bool DEV>
+__device__ __forceinline__ void feq_prod(const Tables *__restrict__ tb, double (&Md)[BasisDef<ST::D, N>::NM],
+                                         A (&feq)[ST::Q]) {
+  constexpr int D = ST::D, ND = ST::NDIR, NPD = ND / 2, KR = ST::NSHELL;
+  using B = BasisDef<D, N>;
+  constexpr AngTable<D, N> AT{};
+  double ap[B::NM];
+  feq_coefficients<D, N, DEV>(tb, Md, ap);
 #pragma unroll
   for (int j = 0; j < KR; ++j) {
     double ce[20];
-#pragma unroll
-    for (int q = 0; q < AT.n; ++q) {
-      const int l = AT.e[q][0] + AT.e[q][1] + AT.e[q][2];
-      double acc = 0.0;
-      if (AT.m0[q] >= 0) acc += ap[AT.m0[q]] * tb->sfeq[j][0][l];
-      if (AT.m1[q] >= 0) acc += ap[AT.m1[q]] * tb->sfeq[j][1][l];
-      ce[q] = acc;
-    }
+    shell_coefficients<D, N>(tb, j, ap, ce);
 #pragma unroll
     for (int qp = 0; qp < NPD; ++qp) {
       const int k = 2 * qp;
@@ -269,64 +298,69 @@ __device__ __forceinline__ void feq_prod(const Tables *__restrict__ tb, double (
   }
 }
 
-// Moments of the populations (product structure), double.
-template <class ST, typename S, bool DEV>
-__device__ __forceinline__ void moments_prod(const Tables *__restrict__ tb, const S (&f)[ST::Q],
-                                             double (&Nv)[ST::D + 1], double (&T)[ST::D + 1][ST::D + 1]) {
-  constexpr int D = ST::D, ND = ST::NDIR, NPD = ND / 2, KR = ST::NSHELL;
-  double N0 = 0, T00 = 0, Na[D], T0a[D], Tab[D * (D + 1) / 2];
+// Moment sums of a product rule, accumulated shell by shell.
+template <int D>
+struct MomAcc {
+  double N0 = 0, T00 = 0, Na[D] = {}, T0a[D] = {}, Tab[D * (D + 1) / 2] = {};
+};
+
+// Adds shell j's populations f[base .. base + NDIR) to the moment sums.
+template <class ST, typename S, int M>
+__device__ __forceinline__ void moments_shell(const Tables *__restrict__ tb, int j, const S (&f)[M], int base,
+                                              MomAcc<ST::D> &acc) {
+  constexpr int D = ST::D, ND = ST::NDIR, NPD = ND / 2;
+  double S0 = 0, Sa[D], Sab[D * (D + 1) / 2];
 #pragma unroll
-  for (int a = 0; a < D; ++a) Na[a] = T0a[a] = 0;
+  for (int a = 0; a < D; ++a) Sa[a] = 0;
 #pragma unroll
-  for (int a = 0; a < D * (D + 1) / 2; ++a) Tab[a] = 0;
+  for (int a = 0; a < D * (D + 1) / 2; ++a) Sab[a] = 0;
 #pragma unroll
-  for (int j = 0; j < KR; ++j) {
-    double S0 = 0, Sa[D], Sab[D * (D + 1) / 2];
-#pragma unroll
-    for (int a = 0; a < D; ++a) Sa[a] = 0;
-#pragma unroll
-    for (int a = 0; a < D * (D + 1) / 2; ++a) Sab[a] = 0;
-#pragma unroll
-    for (int q = 0; q < NPD; ++q) {
-      const int k = 2 * q;
-      const double s = (double)f[j * ND + k] + (double)f[j * ND + k + 1];
-      const double d = (double)f[j * ND + k] - (double)f[j * ND + k + 1];
-      S0 += s;
-#pragma unroll
-      for (int a = 0; a < D; ++a) {
-        const double c = nhat<ST>(k, a);
-        if (c != 0.0) Sa[a] += c * d;
-      }
-      int ab = 0;
-#pragma unroll
-      for (int a = 0; a < D; ++a)
-#pragma unroll
-        for (int b = a; b < D; ++b) {
-          const double c = nhat<ST>(k, a) * nhat<ST>(k, b);
-          if (c != 0.0) Sab[ab] += c * s;
-          ++ab;
-        }
-    }
-    N0 += tb->smom[j][0] * S0;
-    T00 += tb->smom[j][2] * S0;
+  for (int q = 0; q < NPD; ++q) {
+    const int k = 2 * q;
+    const double s = (double)f[base + k] + (double)f[base + k + 1];
+    const double d = (double)f[base + k] - (double)f[base + k + 1];
+    S0 += s;
 #pragma unroll
     for (int a = 0; a < D; ++a) {
-      Na[a] += tb->smom[j][1] * Sa[a];
-      T0a[a] += tb->smom[j][3] * Sa[a];
+      const double c = nhat<ST>(k, a);
+      if (c != 0.0) Sa[a] += c * d;
     }
+    int ab = 0;
 #pragma unroll
-    for (int a = 0; a < D * (D + 1) / 2; ++a) Tab[a] += tb->smom[j][4] * Sab[a];
+    for (int a = 0; a < D; ++a)
+#pragma unroll
+      for (int b = a; b < D; ++b) {
+        const double c = nhat<ST>(k, a) * nhat<ST>(k, b);
+        if (c != 0.0) Sab[ab] += c * s;
+        ++ab;
+      }
   }
-  Nv[0] = N0;
-  T[0][0] = T00;
+  acc.N0 += tb->smom[j][0] * S0;
+  acc.T00 += tb->smom[j][2] * S0;
+#pragma unroll
+  for (int a = 0; a < D; ++a) {
+    acc.Na[a] += tb->smom[j][1] * Sa[a];
+    acc.T0a[a] += tb->smom[j][3] * Sa[a];
+  }
+#pragma unroll
+  for (int a = 0; a < D * (D + 1) / 2; ++a) acc.Tab[a] += tb->smom[j][4] * Sab[a];
+}
+
+// N^a and T^ab from the accumulated sums (plus the reference moments for DEV).
+template <class ST, bool DEV>
+__device__ __forceinline__ void moments_finish(const Tables *__restrict__ tb, const MomAcc<ST::D> &acc,
+                                               double (&Nv)[ST::D + 1], double (&T)[ST::D + 1][ST::D + 1]) {
+  constexpr int D = ST::D;
+  Nv[0] = acc.N0;
+  T[0][0] = acc.T00;
   int ab = 0;
 #pragma unroll
   for (int a = 1; a <= D; ++a) {
-    Nv[a] = Na[a - 1];
-    T[0][a] = T[a][0] = T0a[a - 1];
+    Nv[a] = acc.Na[a - 1];
+    T[0][a] = T[a][0] = acc.T0a[a - 1];
 #pragma unroll
     for (int b = a; b <= D; ++b) {
-      T[a][b] = T[b][a] = Tab[ab];
+      T[a][b] = T[b][a] = acc.Tab[ab];
       ++ab;
     }
   }
@@ -345,11 +379,52 @@ __device__ __forceinline__ void moments_prod(const Tables *__restrict__ tb, cons
   }
 }
 
+// Moments of the populations (product structure), double.
+template <class ST, typename S, bool DEV>
+__device__ __forceinline__ void moments_prod(const Tables *__restrict__ tb, const S (&f)[ST::Q],
+                                             double (&Nv)[ST::D + 1], double (&T)[ST::D + 1][ST::D + 1]) {
+  MomAcc<ST::D> acc;
+#pragma unroll
+  for (int j = 0; j < ST::NSHELL; ++j) moments_shell<ST, S, ST::Q>(tb, j, f, j * ST::NDIR, acc);
+  moments_finish<ST, DEV>(tb, acc, Nv, T);
+}
+
+// dL/dF_i of shell j's populations from dL/dN^a and the symmetric part Ts of dL/dT^ab:
+// sum_a Nb_a p^a + sum_ab Ts_ab p^a p^b, added to out[base .. base + NDIR).
+template <class ST, typename A, int M>
+__device__ __forceinline__ void moments_vjp_shell(const Tables *__restrict__ tb, int j, const double (&Nb)[ST::D + 1],
+                                                  const double (&Ts)[ST::D + 1][ST::D + 1], A (&out)[M], int base) {
+  constexpr int D = ST::D, ND = ST::NDIR, NPD = ND / 2;
+  const double p0 = tb->smom[j][0], pm = tb->smom[j][1];
+#pragma unroll
+  for (int qp = 0; qp < NPD; ++qp) {
+    const int k = 2 * qp;
+    double nN = 0.0, nT0 = 0.0, nTn = 0.0;
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+      const double ca = nhat<ST>(k, a);
+      if (ca == 0.0) continue;
+      nN += ca * Nb[a + 1];
+      nT0 += ca * Ts[0][a + 1];
+#pragma unroll
+      for (int b = 0; b < D; ++b) {
+        const double cb = nhat<ST>(k, b);
+        if (cb == 0.0) continue;
+        nTn += ca * cb * Ts[a + 1][b + 1];
+      }
+    }
+    const double even = Nb[0] * p0 + Ts[0][0] * p0 * p0 + pm * pm * nTn;
+    const double odd = pm * nN + 2.0 * p0 * pm * nT0;
+    out[base + k] = (A)((double)out[base + k] + even + odd);
+    out[base + k + 1] = (A)((double)out[base + k + 1] + even - odd);
+  }
+}
+
 // dL/dF_i from dL/dN^a and dL/dT^ab (full matrix): sum_a Nb_a p^a + sum_ab Tb_ab p^a p^b.
 template <class ST, typename A>
 __device__ __forceinline__ void moments_vjp_add(const Tables *__restrict__ tb, const double (&Nb)[ST::D + 1],
                                                 const double (&Tb)[ST::D + 1][ST::D + 1], A (&out)[ST::Q]) {
-  constexpr int D = ST::D, ND = ST::NDIR, NPD = ND / 2, KR = ST::NSHELL;
+  constexpr int D = ST::D;
   // symmetric parts of Tb
   double Ts[D + 1][D + 1];
 #pragma unroll
@@ -357,31 +432,34 @@ __device__ __forceinline__ void moments_vjp_add(const Tables *__restrict__ tb, c
 #pragma unroll
     for (int b = 0; b <= D; ++b) Ts[a][b] = 0.5 * (Tb[a][b] + Tb[b][a]);
 #pragma unroll
-  for (int j = 0; j < KR; ++j) {
-    const double p0 = tb->smom[j][0], pm = tb->smom[j][1];
+  for (int j = 0; j < ST::NSHELL; ++j) moments_vjp_shell<ST, A, ST::Q>(tb, j, Nb, Ts, out, j * ST::NDIR);
+}
+
+// Reverse of the macroscopic map F -> (n, eps, T, U) given the forward values, up to the
+// moments: dL/dN^a (Nb) and dL/dT^ab (Tbar, full matrix) from the incoming adjoints nb, epsb,
+// Tb, Ub (Ub is updated in place).
+template <int D>
+__device__ __forceinline__ void macro_vjp_moments(const Tables *__restrict__ tb, const double (&Nv)[D + 1],
+                                                  const double (&T)[D + 1][D + 1], const Macro<D> &mac, double nb,
+                                                  double epsb, double Tb, double (&Ub)[D + 1], double (&Nb)[D + 1],
+                                                  double (&Tbar)[D + 1][D + 1]) {
+  const double m = tb->m;
+  const RatiosD rd = ratios_2d_d(m / mac.T);
+  // T = EOS^{-1}(e), e = eps / n
+  const double eb = Tb / eos_slope_2d(mac.T, m, rd);
+  epsb += eb / mac.n;
+  nb -= eb * mac.eps / (mac.n * mac.n);
+  // n = U_a N^a
 #pragma unroll
-    for (int qp = 0; qp < NPD; ++qp) {
-      const int k = 2 * qp;
-      double nN = 0.0, nT0 = 0.0, nTn = 0.0;
-#pragma unroll
-      for (int a = 0; a < D; ++a) {
-        const double ca = nhat<ST>(k, a);
-        if (ca == 0.0) continue;
-        nN += ca * Nb[a + 1];
-        nT0 += ca * Ts[0][a + 1];
-#pragma unroll
-        for (int b = 0; b < D; ++b) {
-          const double cb = nhat<ST>(k, b);
-          if (cb == 0.0) continue;
-          nTn += ca * cb * Ts[a + 1][b + 1];
-        }
-      }
-      const double even = Nb[0] * p0 + Ts[0][0] * p0 * p0 + pm * pm * nTn;
-      const double odd = pm * nN + 2.0 * p0 * pm * nT0;
-      out[j * ND + k] = (A)((double)out[j * ND + k] + even + odd);
-      out[j * ND + k + 1] = (A)((double)out[j * ND + k + 1] + even - odd);
-    }
+  for (int a = 0; a <= D; ++a) {
+    Nb[a] = nb * eta_c(a, a) * mac.U[a];
+    Ub[a] += nb * eta_c(a, a) * Nv[a];
   }
+#pragma unroll
+  for (int a = 0; a <= D; ++a)
+#pragma unroll
+    for (int b = 0; b <= D; ++b) Tbar[a][b] = 0.0;
+  landau_vjp<D>(T, mac.eps, mac.U, epsb, Ub, Tbar);
 }
 
 // Reverse of the macroscopic map F -> (n, eps, T, U) given the forward values:
@@ -392,25 +470,8 @@ __device__ __forceinline__ void macro_vjp(const Tables *__restrict__ tb, const d
                                           double nb, double epsb, double Tb, double (&Ub)[ST::D + 1],
                                           A (&out)[ST::Q]) {
   constexpr int D = ST::D;
-  const double m = tb->m;
-  const RatiosD rd = ratios_2d_d(m / mac.T);
-  // T = EOS^{-1}(e), e = eps / n
-  const double eb = Tb / eos_slope_2d(mac.T, m, rd);
-  epsb += eb / mac.n;
-  nb -= eb * mac.eps / (mac.n * mac.n);
-  // n = U_a N^a
-  double Nb[D + 1];
-#pragma unroll
-  for (int a = 0; a <= D; ++a) {
-    Nb[a] = nb * eta_c(a, a) * mac.U[a];
-    Ub[a] += nb * eta_c(a, a) * Nv[a];
-  }
-  double Tbar[D + 1][D + 1];
-#pragma unroll
-  for (int a = 0; a <= D; ++a)
-#pragma unroll
-    for (int b = 0; b <= D; ++b) Tbar[a][b] = 0.0;
-  landau_vjp<D>(T, mac.eps, mac.U, epsb, Ub, Tbar);
+  double Nb[D + 1], Tbar[D + 1][D + 1];
+  macro_vjp_moments<D>(tb, Nv, T, mac, nb, epsb, Tb, Ub, Nb, Tbar);
   moments_vjp_add<ST, A>(tb, Nb, Tbar, out);
 }
 
@@ -500,6 +561,124 @@ __device__ __forceinline__ bool collide_vjp(const Tables *__restrict__ tb, S (&f
   // ---- reverse of EOS, density, Landau frame and moments ----
   macro_vjp<ST, S>(tb, Nv, T, mac, nb, 0.0, Tb, Ub, f);
   return mac.ok;
+}
+
+
+// ---------------------------------------------------------------------------
+// The reverse step streamed shell by shell (2D product rules, float storage).
+// collide_vjp keeps the populations, the adjoint and the equilibrium of all Q
+// directions in registers at once; the streamed kernel pulls what each pass
+// over the shells needs again (from the cache: the same taps were read moments
+// before), so that one shell's populations are live at a time.
+// ---------------------------------------------------------------------------
+
+// Pre-collision values of shell j's populations: the interpolated pull of pull_prod (2D) for the
+// directions of that shell; TRANSPOSE mirrors the taps as there.
+template <class ST, typename S, bool TRANSPOSE, typename A>
+__device__ __forceinline__ void pull_shell(const Tables *__restrict__ tb, const S *fin, int64_t sites, const Offs &o,
+                                           int j, A (&fs)[ST::NDIR]) {
+  static_assert(ST::D == 2, "the streamed reverse step is built for the 2D product rules");
+  constexpr int ND = ST::NDIR;
+  typedef const __attribute__((address_space(1))) char gchar;
+  gchar *base = (gchar *)fin;
+  const A v = tab<A>(tb->sv[j], tb->svf[j]);
+  A pw[3][3];
+#pragma unroll
+  for (int z = 1; z <= 2; ++z) {
+    const A mag = v * (A)kInvNorm[z];
+    const A cm = (A)1 - mag;
+#pragma unroll
+    for (int nf = 0; nf <= z; ++nf) {
+      A r = 1;
+#pragma unroll
+      for (int t = 0; t < nf; ++t) r *= mag;
+#pragma unroll
+      for (int t = nf; t < z; ++t) r *= cm;
+      pw[z][nf] = r;
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < ND; ++k) {
+    gchar *plane = base + (int64_t)(j * ND + k) * sites * (int64_t)sizeof(S);
+    const int dx = ST::dir(k, 0), dy = ST::dir(k, 1);
+    const int z = (dx != 0) + (dy != 0);
+    A acc = 0;
+#pragma unroll
+    for (int tap = 0; tap < (1 << z); ++tap) {
+      int bit = 0, ox = 0, oy = 0, nfar = 0;
+      if (dx != 0) {
+        const int c = (tap >> bit++) & 1;
+        ox = dx > 0 ? (c ? 0 : -1) : (c ? 1 : 0);
+        nfar += ox != 0;
+      }
+      if (dy != 0) {
+        const int c = (tap >> bit++) & 1;
+        oy = dy > 0 ? (c ? 0 : -1) : (c ? 1 : 0);
+        nfar += oy != 0;
+      }
+      if (TRANSPOSE) {
+        ox = -ox;
+        oy = -oy;
+      }
+      const uint32_t off = o.x[ox + 1] + o.y[oy + 1];
+      acc += pw[z][nfar] * (A) * (const __attribute__((address_space(1))) S *)(plane + off);
+    }
+    fs[k] = acc;
+  }
+}
+
+// Shell j's part of the reverse of the relaxation and of the equilibrium evaluation.  With
+// B_i = F_i + Omega_i (f^eq_i - F_i), Omega_i = (U^0 - v_j n_i . U)/tau = a0 -+ v_j nU:
+// dL/dOmega_i = mu_i (f^eq_i - F_i) accumulates into a0b and nUb, and dL/df^eq_i = mu_i Omega_i,
+// pushed through the shell's equilibrium evaluation, into apb = dL/da'.  f and mu are the shell's
+// pre-collision populations and adjoint (deviations for DEV, as is the equilibrium from ap).
+template <class ST, int N, typename A>
+__device__ __forceinline__ void relax_vjp_shell(const Tables *__restrict__ tb, int j, const A (&f)[ST::NDIR],
+                                                const A (&mu)[ST::NDIR],
+                                                const double (&ap)[BasisDef<ST::D, N>::NM], double a0,
+                                                const double (&nU)[ST::NDIR / 2], double &a0b,
+                                                double (&nUb)[ST::NDIR / 2], double (&apb)[BasisDef<ST::D, N>::NM]) {
+  constexpr int D = ST::D, ND = ST::NDIR, NPD = ND / 2;
+  constexpr AngTable<D, N> AT{};
+  const double v = tb->sv[j];
+  double ce[20], ceb[20];
+  shell_coefficients<D, N>(tb, j, ap, ce);
+#pragma unroll
+  for (int q = 0; q < AT.n; ++q) ceb[q] = 0.0;
+#pragma unroll
+  for (int qp = 0; qp < NPD; ++qp) {
+    const int k = 2 * qp;
+    double E = 0.0, O = 0.0;
+#pragma unroll
+    for (int q = 0; q < AT.n; ++q) {
+      const double c = nhat_pow<ST>(k, AT.e[q][0], AT.e[q][1], AT.e[q][2]) * dir_weight<ST>(k);
+      const bool odd = (AT.e[q][0] + AT.e[q][1] + AT.e[q][2]) & 1;
+      if (c == 0.0) continue;
+      if (odd) O += c * ce[q];
+      else E += c * ce[q];
+    }
+    const double b = v * nU[qp];
+    const double m0 = (double)mu[k], m1 = (double)mu[k + 1];
+    const double g0 = m0 * ((E + O) - (double)f[k]);
+    const double g1 = m1 * ((E - O) - (double)f[k + 1]);
+    a0b += g0 + g1;
+    nUb[qp] += v * (g1 - g0);
+    const double e0 = m0 * (a0 - b), e1 = m1 * (a0 + b);
+    const double Eb = e0 + e1, Ob = e0 - e1;
+#pragma unroll
+    for (int q = 0; q < AT.n; ++q) {
+      const double c = nhat_pow<ST>(k, AT.e[q][0], AT.e[q][1], AT.e[q][2]) * dir_weight<ST>(k);
+      const bool odd = (AT.e[q][0] + AT.e[q][1] + AT.e[q][2]) & 1;
+      if (c == 0.0) continue;
+      ceb[q] += c * (odd ? Ob : Eb);
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < AT.n; ++q) {
+    const int l = AT.e[q][0] + AT.e[q][1] + AT.e[q][2];
+    if (AT.m0[q] >= 0) apb[AT.m0[q]] += ceb[q] * tb->sfeq[j][0][l];
+    if (AT.m1[q] >= 0) apb[AT.m1[q]] += ceb[q] * tb->sfeq[j][1][l];
+  }
 }
 
 }  // namespace rlbm
