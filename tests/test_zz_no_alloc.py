@@ -53,3 +53,26 @@ def test_static_step_rejects_bad_arguments():
     b = lat.new_state()
     assert L.rlbm_step_static(ctypes.byref(bad), ctypes.c_void_p(a.data_ptr()), ctypes.c_void_p(b.data_ptr()),
                               1, None, None, R._stream()) == R.ERR_INVALID_ARG
+
+
+def test_static_step_sets_the_callers_flag_on_a_non_physical_state():
+    """A state of all-zero populations has no timelike Landau eigenvector: the kernels set the
+    caller's flag (and leave it clear for a physical state)."""
+    from paper_1909_04502_amd import rlbm as R
+    L = R.lib()
+    lat = R.Lattice(d=2, zeta=1.0, order=3, extent=(16, 8), tau=0.8)
+    flag = torch.zeros(1, dtype=torch.int32, device="cuda")
+    a, b = torch.zeros((lat.Q, 8, 16), dtype=torch.float64, device="cuda"), lat.new_state()
+    st = L.rlbm_step_static(ctypes.byref(lat.cfg), ctypes.c_void_p(a.data_ptr()), ctypes.c_void_p(b.data_ptr()), 1,
+                            None, ctypes.c_void_p(flag.data_ptr()), R._stream())
+    assert st == R.OK
+    torch.cuda.synchronize()
+    assert flag.item() == 1
+    flag.zero_()
+    n, T, u = (torch.tensor(x) for x in W.taylor_green_2d(16, 8, 0.05, seed=1))
+    a = lat.init(n, T, u)
+    st = L.rlbm_step_static(ctypes.byref(lat.cfg), ctypes.c_void_p(a.data_ptr()), ctypes.c_void_p(b.data_ptr()), 2,
+                            None, ctypes.c_void_p(flag.data_ptr()), R._stream())
+    assert st == R.OK
+    lat.sync()
+    assert flag.item() == 0
