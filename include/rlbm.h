@@ -338,8 +338,9 @@ rlbm_status rlbm_batch_autotune(rlbm_batch *b, void *f_a, void *f_b, int32_t ste
 /* ------------------------------------------------------- launch variants */
 
 /* The step kernel has rlbm_variant_count() launch variants (block shape,
- * register / occupancy target, XCD-aware tile order); results do not depend
- * on the variant.  rlbm_autotune times every variant for `steps` steps on
+ * register / occupancy target, XCD-aware tile order, and for the 2D product
+ * rules on a periodic x axis whose extent is a multiple of 4, upstream windows
+ * staged in LDS); results do not depend on the variant.  rlbm_autotune times every variant for `steps` steps on
  * scratch buffers of the lattice's size (allocated and freed inside the
  * call; the caller's buffers are not touched), selects the fastest and
  * returns after synchronising the stream.  ms_out (host, may be NULL)

@@ -17,15 +17,17 @@ struct FieldPtrs {
 // Launch variants of the step kernel: block shape bx x by x bz (2D lattices
 // fold bz into by), occupancy target (minimum waves per SIMD the compiler must
 // allow, 0 = its choice) and tile order (0 = as dealt, 1 = a contiguous band of
-// tiles per XCD, 2 = (y, z) patches per XCD in 3D, a band in 2D).
+// tiles per XCD, 2 = (y, z) patches per XCD in 3D, a band in 2D).  lds: the 2D
+// product rules stage their upstream windows in LDS (64 x 4 band tiles); lattices
+// the staged kernel does not cover take the register kernel of the same shape.
 struct Variant {
-  int bx, by, bz, occ, xcd;
+  int bx, by, bz, occ, xcd, lds;
 };
-constexpr int kNumVariants = 12;
+constexpr int kNumVariants = 13;
 constexpr Variant kVariants[kNumVariants] = {
-    {64, 4, 1, 0, 0}, {64, 4, 1, 0, 1}, {64, 4, 1, 2, 0}, {64, 4, 1, 2, 2}, {64, 2, 1, 0, 1},
-    {64, 1, 1, 0, 1}, {128, 2, 1, 0, 1}, {256, 1, 1, 0, 1}, {64, 1, 1, 2, 2}, {64, 2, 2, 2, 2},
-    {64, 4, 1, 4, 1}, {64, 4, 1, 0, 2}};
+    {64, 4, 1, 0, 0, 0}, {64, 4, 1, 0, 1, 0}, {64, 4, 1, 2, 0, 0}, {64, 4, 1, 2, 2, 0}, {64, 2, 1, 0, 1, 0},
+    {64, 1, 1, 0, 1, 0}, {128, 2, 1, 0, 1, 0}, {256, 1, 1, 0, 1, 0}, {64, 1, 1, 2, 2, 0}, {64, 2, 2, 2, 2, 0},
+    {64, 4, 1, 4, 1, 0}, {64, 4, 1, 0, 2, 0}, {64, 4, 1, 0, 1, 1}};
 
 struct LaunchArgs {
   int op = 0;
@@ -42,6 +44,7 @@ struct LaunchArgs {
   int *err = nullptr;               // device error flag
   int ext = 0;                      // the lattice has an external force or no-slip walls
   int nt = 0;                       // step kernels store the populations non-temporally
+  int lds_ok = 0;                   // the LDS-staged 2D product kernel covers this lattice
   hipStream_t stream = 0;
 };
 

@@ -239,6 +239,249 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(OCC > 
   if (last.any) write_fields<ST::D>(last, site, sites, mac);
 }
 
+// LDS-staged pull of the 2D product rules (periodic x; every row a whole number of 16-byte chunks).
+// A block of 64 x 4 sites stages, one shell at a time, the upstream windows of the shell's 8 planes
+// in LDS: 5 rows (the tile's 4 and the row upstream of it in y) of 64 + 2E columns (E elements to
+// either side), brought in by direct global-to-LDS loads of 16 bytes per lane, which hold no
+// registers while in flight.  Two buffers alternate, so the loads of shell j + 1 are in flight
+// while the taps of shell j are read from LDS and summed; the block's four waves share each window.
+// The taps, weights and summation order are those of pull_prod, so the populations are the same
+// values to the last bit.  Sites past the lattice's edge take part in the loads and barriers and
+// skip the update.
+template <class ST>
+constexpr uint32_t lds_row_back() {
+  uint32_t m = 0;
+  for (int k = 0; k < ST::NDIR; ++k)
+    if (ST::dir(k, 1) > 0) m |= 1u << k;
+  return m;
+}
+
+template <class ST, typename S>
+struct LdsWindow {
+  static constexpr int E = 16 / (int)sizeof(S);   // elements per 16-byte chunk
+  static constexpr int W = 64 + 2 * E;             // window columns, from x0 - E
+  static constexpr int CR = W / E;                 // chunks per window row
+  static constexpr int RW = 5;                     // window rows
+  static constexpr int CP = RW * CR;               // chunks per plane
+  static constexpr int NIP = (CP + 63) / 64;       // load instructions per plane (one plane each)
+  static constexpr int PW = ST::NDIR / 4;          // planes per wave and shell
+  static constexpr int NI = PW * NIP;              // load instructions per wave and shell
+  static_assert(ST::NDIR % 4 == 0, "a shell's planes split evenly over the four waves");
+  // directions whose window starts one row before the tile (upstream in y is y - 1)
+  static constexpr uint32_t kRowBack = lds_row_back<ST>();
+};
+
+// s_waitcnt vmcnt(N) lgkmcnt(0) (gfx9 encoding: vmcnt in bits 3:0 and 15:14, expcnt 6:4 left at its
+// maximum, lgkmcnt 11:8): all but the N most recent vector memory loads of this wave, to registers
+// or to LDS, and every LDS read of this wave are done
+template <int N>
+__device__ __forceinline__ void wait_vm_lgkm() {
+  static_assert(N >= 0 && N < 64, "vmcnt range");
+  __builtin_amdgcn_s_waitcnt((N & 15) | ((N >> 4) << 14) | (0x7 << 4));
+}
+__device__ __forceinline__ void wait_lgkm() { __builtin_amdgcn_s_waitcnt(15 | (3 << 14) | (0x7 << 4)); }
+
+// One direct global-to-LDS load: each active lane l reads the 16 bytes at base + voff and writes
+// them to LDS at byte lds + 16 l (base and lds wave-uniform; m0 holds the LDS address, and one
+// wait state separates its write from the load).  Written as asm so that the compiler does not
+// track these loads: it would make every LDS read of the kernel wait for all of them.  The kernel
+// waits for them itself (wait_vm_lgkm); they have no register results.
+__device__ __forceinline__ void lds_load16(const void *base, uint32_t voff, uint32_t lds) {
+  // both uniform operands pass through readfirstlane: the compiler may otherwise hold a uniform
+  // value it cannot prove uniform in a vector register, which an "s" operand does not accept
+  const uint64_t b = ((uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)((uintptr_t)base >> 32)) << 32) |
+                     (uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)(uintptr_t)base);
+  const uint32_t m = __builtin_amdgcn_readfirstlane(lds);
+  asm volatile("s_mov_b32 m0, %2\n\ts_nop 0\n\tglobal_load_lds_dwordx4 %1, %0" : : "s"(b), "v"(voff), "s"(m)
+               : "memory", "m0");
+}
+
+// Byte offsets within a plane of this lane's chunk in each load instruction of a plane, for windows
+// starting at the tile's first row (back = 0) or one row before it (back = 1).  Wave w loads the
+// planes w, w + 4, ... of every shell; a lane's chunk of instruction n is n * 64 + lane of the plane.
+template <class ST, typename S>
+__device__ __forceinline__ void lds_offsets(const Tables *__restrict__ tb, int x0, int y0,
+                                            uint32_t (&off)[2][LdsWindow<ST, S>::NIP]) {
+  using L = LdsWindow<ST, S>;
+  const int nx = tb->nx, ny = tb->ny, openy = tb->open[1];
+#pragma unroll
+  for (int n = 0; n < L::NIP; ++n) {
+    const int c = n * 64 + (int)threadIdx.x;
+    const int r = c / L::CR, q = c - r * L::CR;
+    // one wrap brings every row and column an update reads into the lattice; on lattices narrower
+    // or shorter than the window the rest may still lie past the edge and are read from row or
+    // column 0 instead (no site uses them); lanes past the window are masked off at the load
+    int xs = x0 - L::E + q * L::E;
+    xs = xs < 0 ? xs + nx : (xs >= nx ? xs - nx : xs);
+    xs = xs < nx ? xs : 0;
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+      int ys = wrap_or_clamp(y0 - b + r, ny, openy);
+      ys = ys < ny ? ys : 0;
+      off[b][n] = ((uint32_t)ys * (uint32_t)nx + (uint32_t)xs) * (uint32_t)sizeof(S);
+    }
+  }
+}
+
+template <class ST, typename S, int NIP>
+__device__ __forceinline__ void lds_load_shell(const S *__restrict__ fin, int64_t sites, int shell, int w,
+                                               const uint32_t (&off)[2][NIP], S *dst_) {
+  using L = LdsWindow<ST, S>;
+  // LDS byte address of the buffer (the low 32 bits of a local-address-space pointer)
+  const uint32_t lds = (uint32_t)(uintptr_t)(__attribute__((address_space(3))) S *)dst_;
+#pragma unroll
+  for (int e = 0; e < L::PW; ++e) {
+    const int p = w + 4 * e;   // wave-uniform
+    const int b = (L::kRowBack >> p) & 1u;
+    const char *plane = (const char *)fin + (int64_t)(shell * ST::NDIR + p) * sites * (int64_t)sizeof(S);
+#pragma unroll
+    for (int n = 0; n < L::NIP; ++n) {
+      if (L::CP % 64 == 0 || n * 64 + (int)threadIdx.x < L::CP)
+        lds_load16(plane, b ? off[1][n] : off[0][n], lds + (uint32_t)((p * L::CP + n * 64) * 16));
+    }
+  }
+}
+
+// Taps of shell j from its staged windows: the values (read) and their weighted sums (interpolate)
+// are separate steps, so that the next shell's loads can be issued between them.
+template <class ST, typename S>
+struct LdsTaps {
+  static constexpr int count() {
+    int c = 0;
+    for (int k = 0; k < ST::NDIR; ++k) c += 1 << ((ST::dir(k, 0) != 0) + (ST::dir(k, 1) != 0));
+    return c;
+  }
+  S v[count()];
+};
+
+// src: the buffer plus this thread's window offset (lds_lane_offset)
+template <class ST, typename S>
+__device__ __forceinline__ void lds_read_taps(const __attribute__((address_space(3))) S *src, LdsTaps<ST, S> &t) {
+  using L = LdsWindow<ST, S>;
+  int m = 0;
+#pragma unroll
+  for (int k = 0; k < ST::NDIR; ++k) {
+    const int dx = ST::dir(k, 0), dy = ST::dir(k, 1);
+    const int z = (dx != 0) + (dy != 0);
+    const __attribute__((address_space(3))) S *pl = src + k * L::RW * L::W + (dy > 0 ? L::W : 0);
+#pragma unroll
+    for (int tap = 0; tap < (1 << z); ++tap) {
+      int bit = 0, ox = 0, oy = 0;
+      if (dx != 0) {
+        const int c = (tap >> bit++) & 1;
+        ox = dx > 0 ? (c ? 0 : -1) : (c ? 1 : 0);
+      }
+      if (dy != 0) {
+        const int c = (tap >> bit++) & 1;
+        oy = dy > 0 ? (c ? 0 : -1) : (c ? 1 : 0);
+      }
+      t.v[m++] = pl[oy * L::W + ox];
+    }
+  }
+}
+
+template <class ST, typename S, typename A>
+__device__ __forceinline__ void lds_interpolate(const Tables *__restrict__ tb, int j, const LdsTaps<ST, S> &t,
+                                                A (&f)[ST::Q]) {
+  const A v = tab<A>(tb->sv[j], tb->svf[j]);
+  A pw[3][3];
+#pragma unroll
+  for (int z = 1; z <= 2; ++z) {
+    const A mag = v * (A)kInvNorm[z];
+    const A cm = (A)1 - mag;
+#pragma unroll
+    for (int nf = 0; nf <= z; ++nf) {
+      A r = 1;
+#pragma unroll
+      for (int q = 0; q < nf; ++q) r *= mag;
+#pragma unroll
+      for (int q = nf; q < z; ++q) r *= cm;
+      pw[z][nf] = r;
+    }
+  }
+  int m = 0;
+#pragma unroll
+  for (int k = 0; k < ST::NDIR; ++k) {
+    const int dx = ST::dir(k, 0), dy = ST::dir(k, 1);
+    const int z = (dx != 0) + (dy != 0);
+    A acc = 0;
+#pragma unroll
+    for (int tap = 0; tap < (1 << z); ++tap) {
+      int bit = 0, nfar = 0;
+      if (dx != 0) nfar += dx > 0 ? !((tap >> bit++) & 1) : ((tap >> bit++) & 1);
+      if (dy != 0) nfar += dy > 0 ? !((tap >> bit++) & 1) : ((tap >> bit++) & 1);
+      acc += pw[z][nfar] * (A)t.v[m++];
+    }
+    f[j * ST::NDIR + k] = acc;
+  }
+}
+
+// One 64 x 4 tile per block; tiles are dealt to the 8 XCDs in contiguous bands of the row-major tile
+// order (block b runs on XCD b mod 8), as the register kernel's band order.
+template <class ST, int N, typename S, bool DEV, bool NT, typename A = S>
+__global__ void __launch_bounds__(256) k_step_lds(const Tables *__restrict__ tb, const S *__restrict__ fin,
+                                                  S *__restrict__ fout, const void *__restrict__ tau_field,
+                                                  FieldPtrs last, int *err, Tiling tl) {
+  static_assert(ST::D == 2 && !ST::ONLAT && ST::NDIR == 8, "2D product rules");
+  using L = LdsWindow<ST, S>;
+  constexpr int KR = ST::NSHELL;
+  static_assert(KR >= 2, "two shells in flight");
+  constexpr int HALF = ST::NDIR * L::RW * L::W;   // elements of one buffer
+  __shared__ __attribute__((aligned(16))) S buf[2 * HALF];
+  typedef __attribute__((address_space(3))) S lds_t;
+  const uint32_t gx = (tb->nx + 63) / 64;
+  uint32_t t = blockIdx.x;
+  {
+    const uint32_t q = tl.nb / 8, r = tl.nb % 8, k = t % 8, l = t / 8;
+    t = k * q + (k < r ? k : r) + l;
+  }
+  const int x0 = (int)(t % gx) * 64, y0 = (int)(t / gx) * 4;
+  const int x = x0 + threadIdx.x, y = y0 + threadIdx.y;
+  const int64_t sites = tb->sites;
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.y);
+  uint32_t off[2][L::NIP];
+  lds_offsets<ST, S>(tb, x0, y0, off);
+  lds_load_shell<ST, S>(fin, sites, 0, w, off, buf);
+  lds_load_shell<ST, S>(fin, sites, 1, w, off, buf + HALF);
+  const uint32_t lane_off = threadIdx.y * L::W + threadIdx.x + L::E;   // this thread's window offset
+  A f[ST::Q];
+#pragma unroll
+  for (int j = 0; j < KR; ++j) {
+    // shell j has landed in this wave's part of its buffer once at most the loads of shell j + 1
+    // are in flight (no other vector memory access is issued before the last shell); the barrier
+    // extends that to the whole block
+    if (j + 1 < KR) wait_vm_lgkm<L::NI>();
+    else wait_vm_lgkm<0>();
+    asm volatile("" ::: "memory");
+    __builtin_amdgcn_s_barrier();
+    asm volatile("" ::: "memory");
+    const lds_t *src = (const lds_t *)buf + (j & 1) * HALF + lane_off;
+    LdsTaps<ST, S> taps;
+    lds_read_taps<ST, S>(src, taps);
+    if (j + 2 < KR) {
+      // every wave has read shell j before its buffer is refilled with shell j + 2, whose loads
+      // then overlap the interpolation and shell j + 1
+      wait_lgkm();
+      asm volatile("" ::: "memory");
+      __builtin_amdgcn_s_barrier();
+      asm volatile("" ::: "memory");
+      lds_load_shell<ST, S>(fin, sites, j + 2, w, off, buf + (j & 1) * HALF);
+    }
+    lds_interpolate<ST, S, A>(tb, j, taps, f);
+    // the shell's sums are formed here, before the next barrier, so that its taps do not stay live
+    // in registers across the later shells (the compiler would otherwise sink every sum to the end)
+#pragma unroll
+    for (int k = 0; k < ST::NDIR; ++k) asm volatile("" : "+v"(f[j * ST::NDIR + k]));
+  }
+  if (x >= tb->nx || y >= tb->ny) return;
+  const int64_t site = (int64_t)y * tb->nx + x;
+  const double tau = site_tau<S>(tb, tau_field, site);
+  const Macro<ST::D> mac = collide_site<ST, N, A, DEV, true, false>(tb, f, tau, -1.0);
+  if (!mac.ok) flag_error(err);
+  store_site<ST, S, NT, A>(fout, sites, (uint32_t)site * (uint32_t)sizeof(S), f);
+  if (last.any) write_fields<ST::D>(last, site, sites, mac);
+}
+
 // Massive rules whose populations do not fit in registers (the 143-vector 3D
 // stencil in double storage): every population is loaded once for the
 // moments; the first kStreamKeep of them stay in registers, the others are
@@ -484,6 +727,20 @@ static hipError_t launch_t(const LaunchArgs &a) {
       using F = std::false_type;
       using T = std::true_type;
       const bool ext = a.ext && !kStream;
+      if constexpr (ST::D == 2 && !ST::ONLAT) {
+        if (vr.lds && a.lds_ok && !ext) {
+          const long ntile = ((a.nx + 63) / 64) * (long)((a.ny + 3) / 4);
+          const Tiling ltl{64, 4, 1, (int)ntile, 1};
+          auto lds = [&](auto nt) {
+            constexpr bool T = decltype(nt)::value;
+            hipLaunchKernelGGL((k_step_lds<ST, N, S, DEV, T, A>), dim3((unsigned)ntile, 1, 1), dim3(64, 4, 1), 0,
+                               a.stream, a.tb, (const S *)a.fin, (S *)a.fout, a.tau_field, a.fields, a.err, ltl);
+          };
+          if (a.nt) lds(T{});
+          else lds(F{});
+          break;
+        }
+      }
       if constexpr (kStreamAll) {
         // one build (no occupancy target) for the 288-vector rule: every other build multiplies its
         // compile time and none is faster for a kernel that streams its populations

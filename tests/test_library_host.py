@@ -128,7 +128,7 @@ def test_launch_and_store_mode_entry_points_reject_bad_arguments(rlbm_lib):
     """Null handles and out-of-range modes are argument errors, answered without a device."""
     from paper_1909_04502_amd import rlbm as R
     m, nt = ctypes.c_int32(-1), ctypes.c_int32(-1)
-    assert rlbm_lib.rlbm_variant_count() == 12
+    assert rlbm_lib.rlbm_variant_count() == 13
     for mode in (0, 1, 2, 3, -1):
         assert rlbm_lib.rlbm_set_store_mode(None, mode) == R.ERR_INVALID_ARG
         assert rlbm_lib.rlbm_batch_set_store_mode(None, mode) == R.ERR_INVALID_ARG
