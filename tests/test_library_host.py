@@ -226,3 +226,32 @@ def test_create_validates_massive_lattices(rlbm_lib):
     ur.extent[0], ur.extent[1], ur.extent[2] = 16, 4, 1     # |n_y| reaches 5
     ur.tau = 0.8
     assert rlbm_lib.rlbm_create(ctypes.byref(ur), ctypes.byref(h)) == R.ERR_INVALID_ARG
+
+
+def test_lds_loads_take_uniform_operands(rlbm_lib, tmp_path):
+    """The LDS-staged step loads its windows with inline-assembly global-to-LDS loads: each sets m0
+    (the LDS address) from a scalar register, waits one state, and loads with a scalar address pair
+    and a vector offset.  A vector register in either scalar slot would be a build the hardware does
+    not execute as written, so the built library's gfx950 code object (this build's own code) is
+    disassembled and every such load is checked."""
+    import shutil
+    import subprocess
+    from paper_1909_04502_amd import build as b
+    tools = {t: os.path.join("/opt/rocm/llvm/bin", t) for t in ("llvm-objcopy", "clang-offload-bundler", "llvm-objdump")}
+    if not all(os.path.exists(p) for p in tools.values()):
+        pytest.skip("LLVM binary tools not installed")
+    fat, co = str(tmp_path / "fatbin"), str(tmp_path / "gfx950.o")
+    subprocess.run([tools["llvm-objcopy"], f"--dump-section=.hip_fatbin={fat}", b.LIB, str(tmp_path / "lib.so")],
+                   check=True, capture_output=True)
+    subprocess.run([tools["clang-offload-bundler"], "--type=o", "--targets=hipv4-amdgcn-amd-amdhsa--gfx950",
+                    f"--input={fat}", f"--output={co}", "--unbundle"], check=True, capture_output=True)
+    dis = subprocess.run([tools["llvm-objdump"], "-d", co], check=True, capture_output=True, text=True).stdout
+    lines = [l.split("//")[0].strip() for l in dis.splitlines()]
+    lines = [l for l in lines if l and not l.endswith(">:")]
+    loads = [i for i, l in enumerate(lines) if l.startswith("global_load_lds_dwordx4")]
+    assert loads, "no global-to-LDS loads in the library"
+    for i in loads:
+        assert re.fullmatch(r"global_load_lds_dwordx4 v\d+, s\[\d+:\d+\]", lines[i]), lines[i]
+        assert lines[i - 1] == "s_nop 0", lines[i - 2:i + 1]
+        assert re.fullmatch(r"s_mov_b32 m0, s\d+", lines[i - 2]), lines[i - 2:i + 1]
+    shutil.rmtree(tmp_path, ignore_errors=True)
