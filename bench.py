@@ -331,6 +331,26 @@ def adjoint_leg(L, warmup, steps):
         loss.backward()
         torch.cuda.synchronize()
         t2 = time.perf_counter()
+    gt45, gu45 = taug.grad.clone(), u0g.grad.clone()
+    # the same run with every state kept (2001 states of 33.5 MB, 67 GB of HBM): no segment recompute
+    taug = tau.clone().cuda().requires_grad_(True)
+    u0g = torch.tensor(u).cuda().requires_grad_(True)
+    torch.cuda.synchronize()
+    s0 = time.perf_counter()
+    U = A.run(lat, taug, u0g, n_t, T_t, nrun, every=1)
+    loss = A.velocity_loss(U, ut)
+    torch.cuda.synchronize()
+    s1 = time.perf_counter()
+    loss.backward()
+    torch.cuda.synchronize()
+    s2 = time.perf_counter()
+    store_all = {"forward_ms_per_step": round((s1 - s0) / nrun * 1e3, 5),
+                 "backward_ms_per_step": round((s2 - s1) / nrun * 1e3, 5),
+                 "backward_over_forward_step": round((s2 - s1) / nrun / t_fwd, 3),
+                 "state_GB": round((nrun + 1) * lat.Q * 4 * L * L / 1e9, 1),
+                 "gradient_equals_checkpointed": bool(torch.equal(taug.grad, gt45) and torch.equal(u0g.grad, gu45))}
+    del U, loss, taug, u0g, gt45, gu45
+    torch.cuda.empty_cache()
     out = {"workload": f"{L}x{L} zeta=1 N=3 f32dev with tau field", "forward_ms": round(t_fwd * 1e3, 5),
            "run_steps": nrun, "run_checkpoint_every": 45,
            "run_forward_ms_per_step": round((t1 - t0) / nrun * 1e3, 5),
@@ -339,7 +359,8 @@ def adjoint_leg(L, warmup, steps):
            "run_forward_over_step_kernel": round((t1 - t0) / nrun / t_fwd, 3),
            "adjoint_ms": round(t_adj * 1e3, 5), "adjoint_over_forward": round(t_adj / t_fwd, 3),
            "adjoint_MLUPS": round(sites / t_adj / 1e6, 2), "adjoint_achieved_GBs": round(ab / t_adj / 1e9, 1),
-           "adjoint_frac": round(ab / t_adj / 1e9 / HBM_PEAK_GBS, 4)}
+           "adjoint_frac": round(ab / t_adj / 1e9 / HBM_PEAK_GBS, 4),
+           "run_store_all_states": store_all}
     del lat, fa, fb, lam_a, lam_b
     torch.cuda.empty_cache()
     return out

@@ -7,7 +7,10 @@ then segment by segment (last first) the states of the segment are
 recomputed from its checkpoint and lam_t = rlbm_adjoint_step(B_{t-1},
 lam_{t+1}) runs down to the segment start; finally rlbm_init_vjp gives
 dL/du0.  dL/dtau(x) is accumulated by every reverse kernel.  Memory: the
-checkpoints plus one segment of states.  The tau field of the forward run is
+checkpoints plus one segment of states.  every = 1 keeps every state (T + 1
+state buffers: 67 GB for 2000 steps of a 512 x 512 float-deviation lattice, a
+quarter of one GPU's HBM): each forward step writes a fresh buffer and the
+backward recomputes nothing.  The tau field of the forward run is
 kept and restored into the lattice before the backward recomputes, so other
 runs on the same lattice between a forward and its backward do not change
 the gradient.
@@ -31,16 +34,25 @@ class _Run(torch.autograd.Function):
         cur, nxt = _work_pair(lat)
         lat.init(n0, T0, u0d, noise, amp, out=cur)
         ckpt = {0: cur.clone()}
-        t = 0
-        while t < nsteps:                                  # one library call per checkpoint segment
-            k = min(every, nsteps - t)
-            res = lat.step(cur, nxt, k)
-            if res is nxt:
-                cur, nxt = nxt, cur
-            t += k
-            if t < nsteps:
-                ckpt[t] = cur.clone()
-        final = cur.clone()
+        if every == 1:
+            # every state kept, in one allocation: B_t stepped from B_{t-1} straight into its slot
+            store = torch.empty((nsteps + 1,) + tuple(cur.shape), dtype=cur.dtype, device=cur.device)
+            store[0].copy_(cur)
+            for t in range(1, nsteps + 1):
+                lat.step(store[t - 1], store[t], 1)
+            ckpt = {t: store[t] for t in range(nsteps)}
+            final = store[nsteps]
+        else:
+            t = 0
+            while t < nsteps:                              # one library call per checkpoint segment
+                k = min(every, nsteps - t)
+                res = lat.step(cur, nxt, k)
+                if res is nxt:
+                    cur, nxt = nxt, cur
+                t += k
+                if t < nsteps:
+                    ckpt[t] = cur.clone()
+            final = cur.clone()
         fields = lat.moments(final)
         ctx.lat, ctx.ckpt, ctx.final = lat, ckpt, final
         # the kernels read tau through the lattice's own buffer, which another run on the same

@@ -236,6 +236,18 @@ def test_c5_segmentation_against_oracle(storage):
         assert el < 1e-6 and et < 5e-6 and eu < 5e-6
 
 
+@pytest.mark.parametrize("storage", ["f64", "f32dev"])
+def test_store_all_states_gives_the_checkpointed_gradient(storage):
+    """every = 1 keeps every state instead of recomputing segments: the same kernels on the same
+    states, so the loss and both gradients equal those of the run checkpointed every 45 steps bit for
+    bit (24 x 20, 100 steps)."""
+    print(f"[case] store-all gradient {storage}", flush=True)
+    L45, gt45, gu45 = gpu_gradient(24, 20, 100, 45, storage=storage)
+    L1, gt1, gu1 = gpu_gradient(24, 20, 100, 1, storage=storage)
+    assert L1 == L45
+    assert torch.equal(gt1, gt45) and torch.equal(gu1, gu45)
+
+
 def test_c5_full_size_directional_differences_fp64():
     """C5's full size and length in double storage: 512 x 512, 2000 steps checkpointed every 45; the
     adjoint gradient along two seeded directions (tau field and initial velocity together) against
