@@ -76,8 +76,10 @@
  * Errors
  *   Functions return rlbm_status.  Invalid arguments are reported
  *   synchronously.  A non-physical state met by a kernel (n <= 0, eps <= 0,
- *   T <= 0, NaN, a space-like Landau eigenvector) sets a device flag that
- *   rlbm_sync reports as RLBM_ERR_NONPHYSICAL.
+ *   T <= 0, NaN, a space-like Landau eigenvector; in 3D with m > 0 also a
+ *   temperature outside [1/128, 128], the range of the equation of state's
+ *   fitted series) sets a device flag that rlbm_sync reports as
+ *   RLBM_ERR_NONPHYSICAL.
  */
 #ifndef RLBM_H
 #define RLBM_H

@@ -215,17 +215,39 @@ __device__ __forceinline__ double cheb_eval(const double *__restrict__ c, double
   return s * b1 - b2 + c[0];
 }
 
+// A piecewise series at u in [-1, 1] (the whole fitted range; clamped): the piece of u and the
+// local variable s in [-1, 1] of that piece (the host's fit uses the same map).  When the wave's
+// sites share a piece (the usual case: temperature varies smoothly) the series is read through
+// uniform (scalar) loads of that piece; a wave that straddles a piece boundary evaluates every
+// piece, each with uniform loads, and keeps its own.
+__device__ __forceinline__ double cheb_eval_pieces(const double (*__restrict__ c)[48], double u) {
+  u = fmin(1.0, fmax(-1.0, u));
+  const double t = (u + 1.0) * (0.5 * kEosPieces);
+  int p = (int)t;
+  p = p < 0 ? 0 : (p >= kEosPieces ? kEosPieces - 1 : p);
+  const double s = 2.0 * (t - p) - 1.0;
+  const int q = __builtin_amdgcn_readfirstlane(p);
+  if (__all(p == q)) return cheb_eval(c[q], s);
+  double r = 0.0;
+#pragma unroll 1
+  for (int k = 0; k < kEosPieces; ++k) {
+    const double v = cheb_eval(c[k], s);
+    r = p == k ? v : r;
+  }
+  return r;
+}
+
 __device__ __forceinline__ double cheb_r(const Tables *__restrict__ tb, double z, bool &inrange) {
-  // Clenshaw on s in [-1, 1], s affine in log z; the series fits h = r (z + 2) / z, which stays
-  // O(1) from z -> 0 (r ~ z/2) to z -> inf (r -> 1)
-  double s = (2.0 * log(z) - (tb->cheb_lo + tb->cheb_hi)) / (tb->cheb_hi - tb->cheb_lo);
-  inrange = s >= -1.0 && s <= 1.0;
-  s = fmin(1.0, fmax(-1.0, s));
-  return cheb_eval(tb->cheb, s) * (z / (z + 2.0));
+  // Clenshaw on the piece's s in [-1, 1], affine in log z; the series fits h = r (z + 2) / z, which
+  // stays O(1) from z -> 0 (r ~ z/2) to z -> inf (r -> 1)
+  const double u = (2.0 * log(z) - (tb->cheb_lo + tb->cheb_hi)) / (tb->cheb_hi - tb->cheb_lo);
+  inrange = u >= -1.0 && u <= 1.0;
+  return cheb_eval_pieces(tb->cheb, u) * (z / (z + 2.0));
 }
 
 // d = 3: T from e = eps/n through the fitted inverse T = (e - m) u(log(e - m)), then r = K1/K2 at
-// z = m/T.  Both fits hold to ~1e-15 on T in [1/4, 4]; outside that range the site is flagged.
+// z = m/T.  Both fits hold to ~1e-15 on T in [kEosTmin, kEosTmax] = [1/128, 128]; outside that range
+// the site is flagged.
 __device__ __forceinline__ bool temperature_3d(const Tables *__restrict__ tb, double e, double m, double &T,
                                                double &r_out) {
   if (m == 0.0) {
@@ -235,10 +257,9 @@ __device__ __forceinline__ bool temperature_3d(const Tables *__restrict__ tb, do
   }
   const double d = e - m;
   bool ok = d > 0.0;
-  double s = (2.0 * log(d) - (tb->chebT_lo + tb->chebT_hi)) / (tb->chebT_hi - tb->chebT_lo);
-  ok = ok && s >= -1.0 && s <= 1.0;
-  s = fmin(1.0, fmax(-1.0, s));
-  T = d * cheb_eval(tb->chebT, s);
+  const double u = (2.0 * log(d) - (tb->chebT_lo + tb->chebT_hi)) / (tb->chebT_hi - tb->chebT_lo);
+  ok = ok && u >= -1.0 && u <= 1.0;
+  T = d * cheb_eval_pieces(tb->chebT, u);
   bool inr;
   r_out = cheb_r(tb, m / T, inr);
   return ok && inr && T > 0.0;

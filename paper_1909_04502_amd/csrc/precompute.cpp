@@ -280,8 +280,11 @@ int build_quadrature(int d, double m, int order, int kind, double v0, QuadHost &
 // K_nu(z) = int_0^inf exp(-z cosh t) cosh(nu t) dt (trapezoidal rule).
 // ---------------------------------------------------------------------------
 static ld bessel_k(ld nu, ld z) {
+  // trapezoid rule on K_nu(z) = int_0^inf exp(-z cosh t) cosh(nu t) dt, the integrand being
+  // analytic in a strip about the real axis: steps of 0.05 (errors far below long double rounding),
+  // and no more than a quarter of the width 1/sqrt(z) of the integrand's peak at large z
   ld tmax = acoshl(fmaxl(2.0L, 11000.0L / z + 1.0L));
-  const ld h = 0.01L;
+  const ld h = fminl(0.05L, 0.25L / sqrtl(z));
   ld s = 0.5L * expl(-z);
   for (int k = 1; k * h <= tmax; ++k) {
     ld t = k * h;
@@ -414,24 +417,66 @@ static ld cheb_eval(const double *coef, int n, ld s) {
   return s * b1 - b2 + (ld)coef[0];
 }
 
-// r(z) = K1/K2 from the fitted series (what the kernels evaluate)
-static ld r_fitted(const Tables &t, ld z) {
-  const ld s = (2.0L * logl(z) - ((ld)t.cheb_lo + (ld)t.cheb_hi)) / ((ld)t.cheb_hi - (ld)t.cheb_lo);
-  return cheb_eval(t.cheb, t.cheb_n, s) * z / (z + 2.0L);
+// The pieces split the variable u in [-1, 1] of the whole range into kEosPieces equal parts: the
+// piece of u (u clamped to the range) and u as the local variable s in [-1, 1] of that piece, and
+// back.  The kernels evaluate the same map.
+static int cheb_piece(ld u, ld &s) {
+  u = u < -1.0L ? -1.0L : (u > 1.0L ? 1.0L : u);
+  const ld t = (u + 1.0L) * (0.5L * kEosPieces);
+  int p = (int)t;
+  p = p < 0 ? 0 : (p >= kEosPieces ? kEosPieces - 1 : p);
+  s = 2.0L * (t - p) - 1.0L;
+  return p;
+}
+static ld cheb_global(int p, ld s) { return ((s + 1.0L) * 0.5L + p) * (2.0L / kEosPieces) - 1.0L; }
+
+static ld cheb_eval_pieces(const double (*coef)[48], int n, ld u) {
+  ld s;
+  const int p = cheb_piece(u, s);
+  return cheb_eval(coef[p], n, s);
 }
 
-// e - m = m (r(m/T) - 1) + 3 T for d = 3 (e = eps/n = T (G_3 - 1), G_3 = z r + 4)
-static ld kinetic_fitted(const Tables &t, ld m, ld T) { return m * (r_fitted(t, m / T) - 1.0L) + 3.0L * T; }
+// e - m = m (r(m/T) - 1) + 3 T for d = 3 (e = eps/n = T (G_3 - 1), G_3 = z r + 4), with r from
+// the long double Bessel functions; its derivative in T is 3 - z^2 r'(z), r' = r^2 + 3 r/z - 1
+static ld kinetic_exact(ld m, ld T, ld &dk) {
+  const ld z = m / T, r = bessel_k(1.0L, z) / bessel_k(2.0L, z);
+  dk = 3.0L - z * z * (r * r + 3.0L * r / z - 1.0L);
+  return m * (r - 1.0L) + 3.0L * T;
+}
 
-static ld temperature_fitted(const Tables &t, ld m, ld d) {
-  // Newton on kinetic(T) = d, kinetic' = 3 - z^2 r'(z), r' = r^2 + 3 r/z - 1
-  ld T = d / 2.2L;
-  for (int it = 0; it < 60; ++it) {
-    const ld z = m / T, r = r_fitted(t, z);
-    const ld rp = r * r + 3.0L * r / z - 1.0L;
-    const ld dT = (kinetic_fitted(t, m, T) - d) / (3.0L - z * z * rp);
-    T -= dT;
-    if (fabsl(dT) <= 1e-19L * T) break;
+// r(z) = K1/K2 from the fitted series (what the kernels evaluate), and the kinetic energy from it
+static ld r_fitted(const Tables &t, ld z) {
+  const ld u = (2.0L * logl(z) - ((ld)t.cheb_lo + (ld)t.cheb_hi)) / ((ld)t.cheb_hi - (ld)t.cheb_lo);
+  return cheb_eval_pieces(t.cheb, t.cheb_n, u) * z / (z + 2.0L);
+}
+
+// the temperature of kinetic energy d per particle.  kinetic(T) increases in T from 1.5 T (cold)
+// to 3 T (hot), so the root lies in [d/3, d/1.5]: bisection on the kinetic energy of the fitted r
+// (cheap, and good to about 1e-12 where the cold cancellation magnifies the fit's rounding), then
+// safeguarded Newton steps on the exact kinetic energy
+static ld temperature_exact(const Tables &t, ld m, ld d) {
+  ld lo = d / 3.05L, hi = d / 1.45L;
+  {
+    ld a = fmaxl(lo, (ld)kEosTmin), b = fminl(hi, (ld)kEosTmax);
+    for (int it = 0; it < 200 && b - a > 1e-18L * b; ++it) {
+      const ld mid = 0.5L * (a + b);
+      if (m * (r_fitted(t, m / mid) - 1.0L) + 3.0L * mid < d) a = mid;
+      else b = mid;
+    }
+    lo = fmaxl(lo, 0.5L * (a + b) * (1.0L - 1e-6L));
+    hi = fminl(hi, 0.5L * (a + b) * (1.0L + 1e-6L));
+  }
+  ld T = 0.5L * (lo + hi);
+  for (int it = 0; it < 100; ++it) {
+    ld dk;
+    const ld f = kinetic_exact(m, T, dk) - d;
+    if (f < 0.0L) lo = T;
+    else hi = T;
+    ld Tn = T - f / dk;
+    if (!(Tn > lo && Tn < hi)) Tn = 0.5L * (lo + hi);
+    const bool done = fabsl(Tn - T) <= 1e-20L * T;
+    T = Tn;
+    if (done) break;
   }
   return T;
 }
@@ -441,36 +486,40 @@ int build_eos_fit(double m, Tables &t, std::string &err) {
   t.chebT_n = 0;
   if (m == 0.0) return 0;
   const int n = kEosTerms;
-  // r(z) = K1(z)/K2(z) through h = r (z + 2)/z on log z in [log(m/4), log(4m)] (T in [1/4, 4])
-  const ld lo = logl((ld)m / 4.0L), hi = logl((ld)m * 4.0L);
-  auto hfun = [&](ld s) {
-    const ld z = expl(0.5L * (hi + lo) + 0.5L * (hi - lo) * s);
+  const ld tmin = kEosTmin, tmax = kEosTmax;
+  // r(z) = K1(z)/K2(z) through h = r (z + 2)/z on log z in [log(m/tmax), log(m/tmin)], by pieces
+  const ld lo = logl((ld)m / tmax), hi = logl((ld)m / tmin);
+  auto hfun = [&](ld u) {
+    const ld z = expl(0.5L * (hi + lo) + 0.5L * (hi - lo) * u);
     return bessel_k(1.0L, z) / bessel_k(2.0L, z) * (z + 2.0L) / z;
   };
-  cheb_fit(n, hfun, t.cheb);
+  for (int p = 0; p < kEosPieces; ++p) cheb_fit(n, [&](ld s) { return hfun(cheb_global(p, s)); }, t.cheb[p]);
   t.cheb_n = n;
   t.cheb_lo = (double)lo;
   t.cheb_hi = (double)hi;
-  for (int k = 0; k <= 64; ++k) {
-    const ld s = -1.0L + 2.0L * k / 64.0L, ref = hfun(s);
-    if (fabsl(cheb_eval(t.cheb, n, s) - ref) > 5e-16L * fabsl(ref)) {
+  for (int k = 0; k <= 64 * kEosPieces; ++k) {
+    const ld u = -1.0L + 2.0L * k / (64.0L * kEosPieces), ref = hfun(u);
+    if (fabsl(cheb_eval_pieces(t.cheb, n, u) - ref) > 5e-16L * fabsl(ref)) {
       err = "equation-of-state fit failed";
       return RLBM_ERR_QUADRATURE;
     }
   }
-  // inverse: T = (e - m) u(x), x = log(e - m), over the same temperature range
-  const ld xlo = logl(kinetic_fitted(t, m, 0.25L)), xhi = logl(kinetic_fitted(t, m, 4.0L));
-  auto ufun = [&](ld s) {
-    const ld d = expl(0.5L * (xhi + xlo) + 0.5L * (xhi - xlo) * s);
-    return temperature_fitted(t, m, d) / d;
+  // inverse: T = (e - m) u(x), x = log(e - m), over the same temperature range, fitted to the
+  // exact equation of state (the kinetic energy m (r - 1) + 3 T cancels to 1.5 T from terms of
+  // size m when cold, so it is taken from the long double Bessel functions, not the fitted r)
+  ld dk;
+  const ld xlo = logl(kinetic_exact(m, tmin, dk)), xhi = logl(kinetic_exact(m, tmax, dk));
+  auto ufun = [&](ld u) {
+    const ld d = expl(0.5L * (xhi + xlo) + 0.5L * (xhi - xlo) * u);
+    return temperature_exact(t, m, d) / d;
   };
-  cheb_fit(n, ufun, t.chebT);
+  for (int p = 0; p < kEosPieces; ++p) cheb_fit(n, [&](ld s) { return ufun(cheb_global(p, s)); }, t.chebT[p]);
   t.chebT_n = n;
   t.chebT_lo = (double)xlo;
   t.chebT_hi = (double)xhi;
-  for (int k = 0; k <= 64; ++k) {
-    const ld s = -1.0L + 2.0L * k / 64.0L, ref = ufun(s);
-    if (fabsl(cheb_eval(t.chebT, n, s) - ref) > 1e-15L * fabsl(ref)) {
+  for (int k = 0; k <= 64 * kEosPieces; ++k) {
+    const ld u = -1.0L + 2.0L * k / (64.0L * kEosPieces), ref = ufun(u);
+    if (fabsl(cheb_eval_pieces(t.chebT, n, u) - ref) > 1e-15L * fabsl(ref)) {
       err = "inverse equation-of-state fit failed";
       return RLBM_ERR_QUADRATURE;
     }

@@ -32,8 +32,9 @@ int build_massive(int d, double m, int order, double v0, QuadHost &q, std::strin
 int build_tables(const QuadHost &q, double tau, double n_ref, int storage, const int64_t extent[3],
                  const int bc[3], Tables &t, std::string &err);
 
-// d = 3: Chebyshev fit of r(z) = K1(z)/K2(z) in log z for temperatures
-// T in [1/4, 4] (z = m/T), used by the kernels' equation of state.
+// d = 3: piecewise Chebyshev fits of r(z) = K1(z)/K2(z) in log z and of the
+// inverse equation of state, for temperatures T in [kEosTmin, kEosTmax]
+// (z = m/T), used by the kernels' equation of state.
 int build_eos_fit(double m, Tables &t, std::string &err);
 
 // Rest-frame Maxwell-Juettner moments of the basis monomials (T = 1, U = 0,

@@ -345,6 +345,11 @@ constexpr int kMaxShell = 4;
 constexpr int kNMom3 = 14;   // 4 (N^a) + 10 (T^ab) in 3D; 2D uses 3 + 6
 
 constexpr int kEosTerms = 44;
+// the 3D equation-of-state fits cover T in [1/128, 128] in kEosPieces pieces of equal width in
+// log T (an odd count: T = 1 lies mid-piece, so lattices near the reference temperature evaluate
+// one piece per wave)
+constexpr int kEosPieces = 5;
+constexpr double kEosTmin = 1.0 / 128.0, kEosTmax = 128.0;
 constexpr int kMaxPacked = 96;   // packed class blocks of Linv (91 entries for d = 3, N = 3)
 
 struct Tables {
@@ -360,14 +365,14 @@ struct Tables {
   double inv_tau;
   double n_ref;
   // EOS helper for d = 3: Chebyshev series in log z of h(z) = r(z) (z + 2) / z, r = K1(z)/K2(z),
-  // on [log z_lo, log z_hi]
+  // on [cheb_lo, cheb_hi] = [log z_lo, log z_hi], one series per piece of equal width
   double cheb_lo, cheb_hi;
-  double cheb[48];
+  double cheb[kEosPieces][48];
   int32_t cheb_n, chebT_n;
   // and the inverse of the equation of state: T = (e - m) u(x), x = log(e - m), u a Chebyshev
-  // series in x on [chebT_lo, chebT_hi] (e = eps/n; the same temperature range)
+  // series in x on [chebT_lo, chebT_hi] (e = eps/n; the same temperature range), also by pieces
   double chebT_lo, chebT_hi;
-  double chebT[48];
+  double chebT[kEosPieces][48];
   // per pair of antipodal populations (even member 2pr):
   double c[kMaxPairs][3];       // velocity p^a / p^0
   double mom_e[kMaxPairs][8];   // even moment weights: p0, p0^2, p^a p^b (upper triangle)

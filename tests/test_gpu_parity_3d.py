@@ -274,10 +274,10 @@ def test_c3_full_length_against_oracle(storage):
 @pytest.mark.parametrize("zeta,kind", [(0.5, "product"), (1.0, "product"), (5.0, "product"),
                                        (5.0, "massive_onlattice")])
 def test_3d_equation_of_state_over_its_range(zeta, kind):
-    """The 3D equation of state runs through two Chebyshev series built per lattice on T in [1/4, 4]
-    (K1/K2 in log z, and the inverse T(eps/n)).  Temperatures swept across that whole range (with
-    density and flow varying too): the initial state, its fields and two steps against the oracle,
-    whose temperature is the bisection root of the exact equation of state."""
+    """Two steps of lattices whose temperature spans 0.27 .. 3.7 (with density and flow varying too),
+    against the oracle, whose temperature is the bisection root of the exact equation of state: the
+    initial state, its fields and the two steps.  (Wider spans break the scheme itself in the oracle,
+    not the equation of state: see the next test for its whole fitted range.)"""
     from paper_1909_04502_amd import rlbm as R
     print(f"[case] 3D EOS range zeta={zeta} {kind}", flush=True)
     nx, ny, nz = 24, 6, 5
@@ -310,3 +310,62 @@ def test_3d_equation_of_state_over_its_range(zeta, kind):
     assert rel(res, fs) < FP64_TOL
     for k in ("n", "eps", "T"):
         assert rel(mom[k], ref[k]) < FP64_TOL, k
+
+
+@pytest.mark.parametrize("zeta,kind", [(0.01, "product"), (1.0, "product"), (10.0, "product"),
+                                       (5.0, "massive_onlattice")])
+def test_3d_equation_of_state_over_its_fitted_range(zeta, kind):
+    """The 3D equation of state runs through two piecewise Chebyshev series built per lattice on T in
+    [1/128, 128] (K1/K2 in log z, and the inverse T(eps/n); five pieces each, with boundaries at T =
+    0.054, 0.38, 2.6 and 18).  Temperatures swept over 0.03 .. 30 (every piece of both series): the
+    initial state (its equilibrium built with the fitted K1/K2) against the oracle's (scipy's Bessel
+    functions), and its fields (the temperature recovered from eps/n by the fitted inverse) against
+    the oracle's bisection root of the exact equation of state and against the temperatures put in.
+    Bar 1e-11: far from the quadrature's reference temperature the projection itself loses digits
+    in both paths (measured at zeta = 10 over this span: n 2.9e-12, T 3.5e-12, f 5.0e-12; the
+    oracle's own temperatures 7.6e-13 from the input; at zeta = 1: 2.3e-13 and below)."""
+    from paper_1909_04502_amd import rlbm as R
+    print(f"[case] 3D EOS fitted range zeta={zeta} {kind}", flush=True)
+    nx, ny, nz = 64, 6, 5
+    x = np.arange(nx)[None, None, :]
+    T = np.broadcast_to(0.03 * (30.0 / 0.03) ** (x / (nx - 1)), (nz, ny, nx)).copy()   # 0.03 .. 30
+    n = np.broadcast_to(1.0 + 0.3 * np.sin(2 * np.pi * x / nx), (nz, ny, nx)).copy()
+    u = np.zeros((3, nz, ny, nx))
+    u[1] = 0.05
+    bc = ("open", "periodic", "periodic")
+    if kind == "product":
+        q = qd.product_3d(zeta, 3)
+        gl = R.Lattice(d=3, zeta=zeta, order=3, extent=(nx, ny, nz), bc=bc, tau=0.9)
+    else:
+        q = qd.massive_onlattice(3, zeta, 3)
+        gl = R.Lattice(d=3, zeta=zeta, order=3, kind=kind, extent=(nx, ny, nz), bc=bc, tau=0.9, v0=q.v0)
+    ol = OL.Lattice(q, 0.9, (nx, ny, nz), bc=bc)
+    tn, tT, tu = (torch.tensor(a) for a in (n, T, u))
+    f0, fields0 = gl.init(tn, tT, tu, want_fields=True)
+    gl.sync()
+    mac0 = ol.macro(ol.init(tn, tT, tu))
+    fs = ol.collide(ol.init(tn, tT, tu))
+    eT = ((fields0["T"].cpu() - mac0["T"]).abs() / mac0["T"]).max().item()
+    eT_in = ((fields0["T"].cpu() - tT).abs() / tT).max().item()
+    ef, en = rel(f0, fs), rel(fields0["n"], mac0["n"])
+    print(f"EOS fitted range zeta={zeta}: T vs oracle {eT:.2e}, vs input {eT_in:.2e}, n {en:.2e}, f {ef:.2e}",
+          flush=True)
+    assert eT < 1e-11 and eT_in < 1e-11 and en < 1e-11 and ef < 1e-11
+
+
+@pytest.mark.parametrize("T0", [0.005, 200.0])
+def test_3d_equation_of_state_flags_beyond_its_range(T0):
+    """A 3D massive state whose temperature lies outside the fitted range [1/128, 128] is reported as
+    non-physical (the kernels' flag, raised at the next synchronisation), not evaluated off the fit."""
+    from paper_1909_04502_amd import rlbm as R
+    print(f"[case] 3D EOS beyond range T={T0}", flush=True)
+    nx, ny, nz = 16, 4, 4
+    gl = R.Lattice(d=3, zeta=1.0, order=3, extent=(nx, ny, nz), tau=0.9)
+    n = torch.ones((nz, ny, nx), dtype=torch.float64)
+    T = torch.full((nz, ny, nx), T0, dtype=torch.float64)
+    u = torch.zeros((3, nz, ny, nx), dtype=torch.float64)
+    with pytest.raises(R.RLBMError) as exc:
+        f0 = gl.init(n, T, u)
+        gl.step(f0, gl.new_state(), 1)
+        gl.sync()
+    assert exc.value.status == 5
