@@ -119,7 +119,11 @@ def test_c1_full_length_against_oracle():
     err.update({k: rel(mom[k], ref[k]) for k in ("n", "eps", "T")})
     err["U"] = rel(mom["U"][1:], ref["U"][1:])
     print("C1 100-step errors", err, flush=True)
-    assert max(err.values()) < 1e-11
+    # measured: f 8.1e-15, n 4.2e-15, eps 5.1e-15, T 2.4e-15, U 3.0e-12.  U^x and U^y are normalised
+    # by their own maximum, the flow amplitude 0.01: double round-off on quantities of order one
+    # shows a hundred times larger there
+    assert max(err[k] for k in ("f", "n", "eps", "T")) < 1e-12 + 2.5e-15 * nsteps
+    assert err["U"] < 100 * (1e-12 + 2.5e-15 * nsteps)
 
 
 U_F32 = 2.0 ** -24      # unit round-off of float
@@ -133,7 +137,10 @@ def c2_golden():
     return json.load(open(os.path.join(os.path.dirname(__file__), "golden", "c2_samples.json")))
 
 
-# error bounds per checkpoint k (max-normalised, per field).  Double: the two paths' round-off.
+# error bounds per checkpoint k (max-normalised, per field).  Double: the two paths' round-off,
+# which accumulates step by step: measured on U (the largest) 2.3e-14 at step 10, 2.4e-13 at 100,
+# 9.0e-13 at 500 and 1.42e-12 at 1000, about 2.4e-15 per step; bounded by the one-step bar 1e-12
+# plus 2.5e-15 per step.
 # Float deviations updated in float: the rounding of the interpolated pull and of the moment
 # sums has the same sign pattern from one step to the next (the state changes slowly), so it
 # adds up coherently and the error grows linearly in k; measured on this workload 0.42 u per
@@ -141,7 +148,7 @@ def c2_golden():
 # deviations updated in double: only the rounding of the stored values remains, which does
 # not build up coherently (measured at step 1000: 2.7e-8 = 0.45 u on U, 4e-9 on n, against
 # 2.5e-5 and 1.2e-6 when updated in float); bounded by 32 u + sqrt(k) u.
-C2_BOUNDS = {"f64": lambda k: 1e-11,
+C2_BOUNDS = {"f64": lambda k: 1e-12 + 2.5e-15 * k,
              "f32dev": lambda k: (16 + k) * U_F32,
              "f32dev_f64": lambda k: (32 + math.sqrt(k)) * U_F32}
 

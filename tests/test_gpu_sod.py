@@ -135,7 +135,9 @@ def test_sod_inviscid_against_app_d():
     got = {"n": nn[sites], "eps": EE[sites], "T": TT[sites], "beta": beta[sites]}
     perr = {k: float(np.max(np.abs(got[k] - np.array(gold[k]))) / np.max(np.abs(gold[k]))) for k in got}
     print("against the oracle's 300 steps", perr, flush=True)
-    assert max(perr.values()) < 1e-11
+    # the two paths' double round-off over 300 steps (measured 2.3e-13): the one-step bar 1e-12 plus
+    # 2.5e-15 per step, as for the other full-length runs
+    assert max(perr.values()) < 1e-12 + 2.5e-15 * steps
 
 
 # ---------------------------------------------------------------------------
@@ -241,4 +243,4 @@ def test_sod3d_inviscid_against_app_d():
     got = {"n": nn[sites], "eps": EE[sites], "T": TT[sites], "beta": beta[sites]}
     perr = {k: float(np.max(np.abs(got[k] - np.array(gold[k]))) / np.max(np.abs(gold[k]))) for k in got}
     print("3d against the oracle's 234 steps", perr, flush=True)
-    assert max(perr.values()) < 1e-11
+    assert max(perr.values()) < 1e-12 + 2.5e-15 * STEPS3
