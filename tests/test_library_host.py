@@ -232,8 +232,8 @@ def test_lds_loads_take_uniform_operands(rlbm_lib, tmp_path):
     """The LDS-staged step loads its windows with inline-assembly global-to-LDS loads: each sets m0
     (the LDS address) from a scalar register, waits one state, and loads with a scalar address pair
     and a vector offset.  A vector register in either scalar slot would be a build the hardware does
-    not execute as written, so the built library's gfx950 code object (this build's own code) is
-    disassembled and every such load is checked."""
+    not execute as written, so the built library's gfx950 code object (compiled from this repository's
+    sources) is disassembled and every such load is checked."""
     import shutil
     import subprocess
     from paper_1909_04502_amd import build as b
