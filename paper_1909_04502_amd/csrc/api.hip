@@ -229,10 +229,11 @@ static rlbm_status prepare_lattice(const rlbm_config *cfg, rlbm_lattice *h, rlbm
   //    64 x 4 tiles (10.5 ms, 10.7 in patches);
   //  * the 3D massive rule: 64 x 2 XCD-ordered tiles (double, streaming kernel) or 64 x 1 patches
   //    (float);
-  //  * 2D product rules in double: rows of 64 sites, or the LDS-staged kernel on lattices larger
-  //    than the caches (below); float storage with double arithmetic: 64 x 4 band tiles of the
-  //    occupancy-2 build (4 % faster than rows of 64); float storage and arithmetic: 64 x 4 band
-  //    tiles of the occupancy-4 build (0.057 against 0.060 ms at 1024^2 for the unconstrained one);
+  //  * 2D product rules in double: rows of 64 sites; float storage with double arithmetic: 64 x 4
+  //    band tiles of the occupancy-2 build (4 % faster than rows of 64); float storage and
+  //    arithmetic: 64 x 4 band tiles of the occupancy-4 build (0.057 against 0.060 ms at 1024^2 for
+  //    the unconstrained one); in every storage the LDS-staged kernel on lattices larger than the
+  //    caches (below);
   //  * 2D on-lattice rules: 64 x 4 tiles of the occupancy-2 build, except the massive rules whose
   //    update fits in 128 registers (order 2, and order 3 in float deviations), which take the
   //    occupancy-4 build: four waves per SIMD instead of three, 7-27 % faster; and small lattices
@@ -257,11 +258,14 @@ static rlbm_status prepare_lattice(const rlbm_config *cfg, rlbm_lattice *h, rlbm
     for (int a = 0; a < m.d; ++a)
       if (cfg->bc[a] == RLBM_PERIODIC && std::fabs(h->quad.disp[i * m.d + a]) > (double)cfg->extent[a])
         return fail(RLBM_ERR_INVALID_ARG, "a periodic extent is shorter than the stencil's longest displacement");
-  // 2D product rules in double whose state outgrows the caches (the non-temporal store threshold)
-  // take the LDS-staged kernel where it applies (1024^2: 0.106 against 0.121 ms per step for rows
-  // of 64 sites); below that, where the halo re-reads hit the Infinity Cache, rows of 64 stay ahead
-  if (m.d == 2 && m.kind == RLBM_QUAD_PRODUCT && cfg->storage == RLBM_F64 && cfg->bc[0] == RLBM_PERIODIC &&
-      cfg->extent[0] % 4 == 0 && 2 * 8 * (int64_t)h->quad.Q * sites > kNontemporalFootprint)
+  // 2D product rules whose state outgrows the caches (the non-temporal store threshold) take the
+  // LDS-staged kernel where it applies, in every storage (double at 1024^2: 0.106 against 0.122 ms
+  // per step for rows of 64 sites; at 2048^2 float storage 0.221 against 0.256 ms, float storage
+  // with double arithmetic 0.255 against 0.266 ms); below that, where the halo re-reads hit the
+  // Infinity Cache, the register kernels stay ahead (float storage at 1024^2: 0.057 against 0.059)
+  const int64_t elem = cfg->storage == RLBM_F64 ? 8 : 4;
+  if (m.d == 2 && m.kind == RLBM_QUAD_PRODUCT && cfg->bc[0] == RLBM_PERIODIC && cfg->extent[0] % 4 == 0 &&
+      2 * elem * (int64_t)h->quad.Q * sites > kNontemporalFootprint)
     h->variant = 12;
   int bc[3] = {cfg->bc[0], cfg->bc[1], cfg->bc[2]};
   rc = rlbm::build_tables(h->quad, cfg->tau, cfg->storage != RLBM_F64 ? cfg->n_ref : 1.0, cfg->storage,

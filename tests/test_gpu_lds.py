@@ -7,7 +7,8 @@ than one window, ragged tiles in x and y, an open y axis, a per-site tau field, 
 last step, and lattices of more tiles than fit on the chip at once.  One case is also checked
 against the FP64 oracle.  Lattices the staged windows do not cover (x extent not a multiple of 4,
 an open x axis, walls or a force) take the register kernel under that variant, with the same
-results.
+results.  The staged kernel is the default above 384 MiB of state in every storage: the default
+selection is checked, and a 2048 x 2048 float lattice's default run against the register kernel.
 """
 import numpy as np
 import pytest
@@ -97,3 +98,33 @@ def test_staged_step_against_oracle():
     err = ((res.cpu() - fs).abs().max() / fs.abs().max()).item()
     print("staged vs oracle", err, flush=True)
     assert err < 1e-12
+
+
+@pytest.mark.parametrize("storage,side,want", [("f64", 512, 5), ("f64", 1024, LDS), ("f32dev", 1024, 10),
+                                               ("f32dev", 2048, LDS), ("f32dev_f64", 1024, 9),
+                                               ("f32dev_f64", 2048, LDS), ("f64", 1026, 5)])
+def test_default_variant_follows_the_state_size(storage, side, want):
+    """The staged kernel is the default where the two state buffers exceed 384 MiB (and the x extent
+    is a multiple of 4), in every storage; smaller lattices keep their register kernels."""
+    from paper_1909_04502_amd import rlbm as R
+    print(f"[case] default variant {storage} {side}", flush=True)
+    gl = R.Lattice(d=2, zeta=1.0, order=3, kind="product", extent=(side, side), storage=storage, tau=0.8)
+    assert gl.variant == want
+
+
+def test_staged_default_at_2048_float_equals_register_kernel():
+    """Float storage at 2048 x 2048 (two 512 MiB state buffers): two steps of the default launch (the
+    staged kernel) against the register kernel, bit for bit."""
+    from paper_1909_04502_amd import rlbm as R
+    print("[case] lds default f32dev 2048", flush=True)
+    L = 2048
+    gl = R.Lattice(d=2, zeta=1.0, order=3, kind="product", extent=(L, L), storage="f32dev", tau=0.8)
+    assert gl.variant == LDS
+    n, T, u = (torch.tensor(a) for a in W.taylor_green_2d(L, L, 0.1, density_sigma=1e-3, seed=3))
+    f0 = gl.init(n, T, u)
+    got = gl.step(f0.clone(), gl.new_state(), 2)
+    gl.sync()
+    gl.variant = REG
+    ref = gl.step(f0, gl.new_state(), 2)
+    gl.sync()
+    assert torch.equal(got, ref)
