@@ -344,7 +344,9 @@ rlbm_status rlbm_batch_autotune(rlbm_batch *b, void *f_a, void *f_b, int32_t ste
  * rules on a periodic x axis whose extent is a multiple of 4, upstream windows
  * staged in LDS); results do not depend on the variant.  rlbm_autotune times every variant for `steps` steps on
  * scratch buffers of the lattice's size (allocated and freed inside the
- * call; the caller's buffers are not touched), selects the fastest and
+ * call and holding a shear wave of amplitude 0.05 at T = 1 and a density
+ * of 1 with site-to-site noise of 1e-3; the
+ * caller's buffers are not touched), selects the fastest and
  * returns after synchronising the stream.  ms_out (host, may be NULL)
  * receives rlbm_variant_count() milliseconds per step. */
 int32_t rlbm_variant_count(void);
