@@ -44,10 +44,11 @@ def parse():
     ap.add_argument("--no-3d", action="store_true")
     ap.add_argument("--no-onlattice", action="store_true")
     ap.add_argument("--no-forcing", action="store_true")
+    ap.add_argument("--no-staged-large", action="store_true")
     ap.add_argument("--size-3d", type=int, default=256)
     ap.add_argument("--only", default=None,
                     help="run the headline and this one optional leg (onlattice_ur, massive_onlattice, sod_ur, "
-                         "calibrations, forcing_walls, shock_tube_3d, adjoint, batched, variants)")
+                         "calibrations, forcing_walls, shock_tube_3d, adjoint, batched, variants, staged_large)")
     a = ap.parse_args()
     if a.only is not None:
         a.no_variants = a.only != "variants"
@@ -55,6 +56,7 @@ def parse():
         a.no_3d = a.only != "shock_tube_3d"
         a.no_batch = a.only != "batched"
         a.no_forcing = a.only != "forcing_walls"
+        a.no_staged_large = a.only != "staged_large"
         a.no_onlattice = a.only not in ("onlattice_ur", "massive_onlattice", "sod_ur", "calibrations")
     return a
 
@@ -589,6 +591,33 @@ def calibration_leg():
     return out
 
 
+def staged_large_leg(warmup, steps, L=2048):
+    """The 2D product rule (zeta = 1, N = 3) at L x L in each storage, where the two state buffers
+    exceed 384 MiB: the default launch (the LDS-staged step) against the register kernel that is the
+    default below that size.  Algorithmic bytes per site: 2 Q x element size."""
+    import torch
+    import workloads as W
+    from paper_1909_04502_amd import rlbm as R
+    n, T, u = (torch.tensor(a) for a in W.taylor_green_2d(L, L, 0.1, density_sigma=1e-3, seed=2))
+    out = {"workload": f"2D zeta=1 N=3 Q=32 {L}x{L} periodic, Taylor-Green u0=0.1, tau=0.8"}
+    for storage, reg in (("f64", 5), ("f32dev", 10), ("f32dev_f64", 9)):
+        lat = R.Lattice(d=2, zeta=1.0, order=3, kind="product", extent=(L, L), storage=storage, tau=0.8)
+        b = 2 * lat.Q * (8 if storage == "f64" else 4) * L * L
+        row = {}
+        for name, v in (("default", lat.variant), ("register", reg)):
+            lat.variant = v
+            fa = lat.init(n, T, u)
+            fb = lat.new_state()
+            t = time_steps(lat, fa, fb, warmup, steps)
+            row[name] = {"variant": v, "ms_per_step": round(t * 1e3, 5), "MLUPS": round(L * L / t / 1e6, 2),
+                         "frac": round(b / t / 1e9 / HBM_PEAK_GBS, 4)}
+            del fa, fb
+        out[storage] = row
+        del lat
+        torch.cuda.empty_cache()
+    return out
+
+
 def forcing_leg(L, warmup, steps):
     """The headline workload with the external force of Sec. 5.4 (scheme B, g = 1e-6 along y) and no-slip
     equilibrium walls on the x faces: the force/wall build of the step kernel."""
@@ -758,6 +787,8 @@ def main():
             out["calibrations"] = calibration_leg()
     if not args.no_forcing:
         out["forcing_walls"] = forcing_leg(L, args.warmup, args.steps)
+    if not args.no_staged_large:
+        out["staged_large"] = staged_large_leg(args.warmup, args.steps)
     if not args.no_copy:
         cb = copy_bandwidth(Q * 8 * sites, planes=Q)
         best = max(cb.values())

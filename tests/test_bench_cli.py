@@ -25,3 +25,10 @@ def test_only_selects_known_legs():
     finally:
         sys.argv = argv
     assert not a.no_onlattice and a.no_variants and a.no_adjoint and a.no_batch and a.no_forcing and a.no_3d
+    assert a.no_staged_large
+    try:
+        sys.argv = ["bench.py", "--only", "staged_large"]
+        a = bench.parse()
+    finally:
+        sys.argv = argv
+    assert not a.no_staged_large and a.no_onlattice and a.no_variants and a.no_adjoint and a.no_3d
